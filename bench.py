@@ -1,0 +1,270 @@
+#!/usr/bin/env python3
+"""Benchmark of the staggered CG hot path on one MI355X.
+
+A step is one complete solve of A x = b (A = m^2 - D_eo D_oe) on the
+16^3 x 32 lattice with exp(i 0.3 H) links, m = 0.01, one complex Gaussian
+right-hand side, to true relative residual 1e-8, with fp32 inner CG and fp64
+reliable updates, timed from b resident in HBM to x resident in HBM with the
+fp64 true residual verified. Prints one JSON line on stdout (progress goes
+to stderr).
+
+Beside the headline it reports: the dominant kernel's achieved bandwidth
+against the 8 TB/s HBM peak (HIP events on the launch stream, inside the
+timed solves), plain fp64 CG and fp16-storage mixed CG on the same system
+(time-to-1e-8), the A-apply bandwidth per precision on the 32^3 x 64
+lattice, and the fp64 CPU oracle timed on this host as a baseline.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-8 solve & solves/s, mixed vs FP64 CG; A-apply HBM GB/s; p99 lat"
+WORKLOAD = "c2_16x16x16x32"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(kind, inner, vh, costs, stag):
+    """Algorithmic bytes of one launch of a kernel kind."""
+    if kind == stag.K_HOP1:
+        return vh * costs.hop_bytes_per_site(inner, 1)
+    if kind == stag.K_HOP2:
+        return vh * costs.hop_bytes_per_site(inner, 2)
+    if kind == stag.K_HOP1_64:
+        return vh * costs.hop_bytes_per_site("f64", 1)
+    if kind == stag.K_HOP2_64:  # reads t, x, b; writes r
+        return vh * (costs.hop_bytes_per_site("f64", 2) + costs.SPINOR_BYTES["f64"])
+    if kind == stag.K_UPDATE:
+        return vh * costs.update_bytes_per_site(inner, inner != "f64")
+    if kind == stag.K_XPAY:
+        return vh * costs.xpay_bytes_per_site(inner)
+    return 0
+
+
+KIND_NAMES = ["hop1", "hop2", "hop1_f64", "hop2_f64", "update", "xpay", "other"]
+
+
+def timed_solves(stag, torch, ctx, g, mass, fb, fx, params, k):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(k):
+        rc, st = stag.stag_cg_solve(ctx, g, [mass], fb, fx, params)
+        if rc != 0:
+            raise RuntimeError(f"solve failed: rc={rc} {st}")
+        last = st[0]
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / k, last
+
+
+def a_apply_bandwidth(stag, torch, costs, synth, reps=50):
+    """GB/s of A = both hop stages on the 32^3 x 64 lattice, per precision,
+    timed with torch events on the stream the library launches on."""
+    name = "c3_32x32x32x64"
+    cfg = synth.CONFIGS[name]
+    L = cfg["L"]
+    log("generating", name, "links ...")
+    U = synth.config_links(name)
+    v = synth.gaussian_rhs(L, 1, cfg["rhs_seed"])
+    out = {}
+    with stag.Context(0) as ctx:
+        g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"))
+        del U
+        vh = g.vh
+        stream = torch.cuda.current_stream()
+        for prec in ("f64", "f32", "f16s"):
+            cfgt, _ = stag.stag_tune(ctx, g, prec, 1)
+            fi = ctx.field(g, 0, prec, 1).load(v)
+            fo = ctx.field(g, 0, prec, 1)
+            for _ in range(5):
+                stag.stag_apply_A(ctx, g, [cfg["mass"]], fi, fo, stream=stream)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                stag.stag_apply_A(ctx, g, [cfg["mass"]], fi, fo, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            byts = vh * (costs.hop_bytes_per_site(prec, 1) + costs.hop_bytes_per_site(prec, 2) -
+                         costs.SPINOR_BYTES[prec] * 0)
+            # stag_apply_A's second stage writes without the dot: same bytes
+            gbs = byts / (ms * 1e-3) / 1e9
+            out[prec] = {"us_per_A": round(ms * 1e3, 2), "GB/s": round(gbs, 1),
+                         "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
+                         "GFLOP/s": round(vh * costs.a_flops_per_site() / (ms * 1e-3) / 1e9, 1),
+                         "bytes_per_A": byts, "tune": cfgt}
+            log("A-apply 32^3x64", prec, out[prec])
+            fi.destroy()
+            fo.destroy()
+    return out
+
+
+def cpu_baseline(synth, L, U, b, mass, gpu_fp64_iters, target_s):
+    """The fp64 C oracle's Fig.1 CG on the same system, timed on this host
+    for a bounded number of iterations and scaled to a full solve."""
+    from oracle import c as oc
+    oc.lib()
+    t0 = time.perf_counter()
+    oc.cg_fixed(U, b, L, mass, 5)
+    per_iter = (time.perf_counter() - t0) / 5
+    n = max(10, min(int(target_s / per_iter), gpu_fp64_iters))
+    log(f"cpu baseline: {n} oracle iterations (~{n * per_iter:.1f} s) ...")
+    t0 = time.perf_counter()
+    oc.cg_fixed(U, b, L, mass, n)
+    per_iter = (time.perf_counter() - t0) / n
+    solve_s = per_iter * gpu_fp64_iters
+    return {
+        "value": 1.0 / solve_s, "unit": "solves/s", "cores": oc.threads(), "kind": "oracle",
+        "sample": (f"{n} Fig.1 fp64 CG iterations of the C+OpenMP oracle on the same 16^3x32 "
+                   f"system, scaled to the {gpu_fp64_iters} iterations a full 1e-8 fp64 solve "
+                   f"takes ({per_iter * 1e3:.2f} ms/iteration)"),
+        "ms_per_iteration": per_iter * 1e3,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--inner", default="f32", choices=["f32", "f16s"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the fp64 / f16s comparison solves and the 32^3x64 A-apply")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus}: this build runs one lattice per GPU on a single "
+              "GPU; multi-GPU runs are not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np  # noqa: F401
+    import torch
+
+    import paper_1111_0125_amd as stag
+    import synth
+    from paper_1111_0125_amd import costs
+
+    cfg = synth.CONFIGS[WORKLOAD]
+    L, mass, tol = cfg["L"], cfg["mass"], cfg["tol"]
+    log("inputs", WORKLOAD)
+    U = synth.config_links(WORKLOAD)
+    b = synth.config_rhs(WORKLOAD)
+    torch.cuda.init()
+    ctx = stag.Context(0)
+    g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"))
+    vh = g.vh
+    tunes = {p: stag.stag_tune(ctx, g, p, 1)[0] for p in ("f64", "f32", "f16s")}
+    log("tuned", tunes)
+    fb = ctx.field(g, 0, "f64", 1).load(b)
+    fx = ctx.field(g, 0, "f64", 1)
+    inner = args.inner
+    params = stag.cg_params(tol=tol, inner=inner)
+
+    for _ in range(args.warmup):
+        rc, st = stag.stag_cg_solve(ctx, g, [mass], fb, fx, params)
+        log("warmup", rc, st[0])
+
+    # ---- timed region: K whole solves, kernels timed by in-graph HIP events
+    stag.stag_timing_enable(ctx, True)
+    sec, last = timed_solves(stag, torch, ctx, g, mass, fb, fx, params, args.steps)
+    kinds = {}
+    for k in range(7):
+        n, ms = stag.stag_timing_read(ctx, k)
+        if n:
+            byts = kernel_bytes(k, inner, vh, costs, stag)
+            kinds[KIND_NAMES[k]] = {"launches": n, "avg_us": round(ms / n * 1e3, 3),
+                                    "total_ms": round(ms, 3), "bytes_per_launch": byts,
+                                    "GB/s": round(byts / (ms / n * 1e-3) / 1e9, 1)}
+    stag.stag_timing_enable(ctx, False)
+    dom = max(kinds, key=lambda k: kinds[k]["total_ms"])
+    d = kinds[dom]
+    roofline = {"bound": "hbm", "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(d["GB/s"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"{dom} ({inner})", "avg_us": d["avg_us"],
+                "bytes_per_launch": d["bytes_per_launch"]}
+    log("timed", args.steps, "solves:", sec * 1e3, "ms each;", last)
+    log("kernels", kinds)
+
+    # the same solves without the timing events (graph replays only)
+    sec_plain, _ = timed_solves(stag, torch, ctx, g, mass, fb, fx, params, args.steps)
+
+    result = {
+        "metric": METRIC,
+        "value": round(1.0 / sec, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"{inner}+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"16^3x32 lattice, exp(i*0.3*H) links (seed {cfg['gauge_seed']}), "
+                         f"m={mass}, 1 complex Gaussian RHS (seed {cfg['rhs_seed']}), "
+                         f"true residual {tol:g}, {inner}-inner CG + fp64 reliable updates"),
+            "lattice": list(L), "mass": mass, "tol": tol, "inner": inner, "nrhs": 1,
+        },
+        "roofline": roofline,
+        "solve": {"iters": last["iters"], "reliable_updates": last["reliable_updates"],
+                  "true_rel_res": last["true_rel_res"], "time_to_1e-8_ms": round(sec * 1e3, 3),
+                  "time_to_1e-8_ms_no_events": round(sec_plain * 1e3, 3)},
+        "kernels": kinds,
+        "tune": tunes,
+    }
+
+    fp64_iters = None
+    if not args.no_extras:
+        p64 = stag.cg_params(tol=tol, inner="f64")
+        stag.stag_cg_solve(ctx, g, [mass], fb, fx, p64)
+        s64, st64 = timed_solves(stag, torch, ctx, g, mass, fb, fx, p64, 2)
+        fp64_iters = st64["iters"]
+        result["fp64_cg"] = {"time_to_1e-8_ms": round(s64 * 1e3, 3), "iters": st64["iters"],
+                             "true_rel_res": st64["true_rel_res"],
+                             "solves_per_s": round(1 / s64, 3)}
+        result["speedup_mixed_vs_fp64"] = round(s64 / sec_plain, 3)
+        p16 = stag.cg_params(tol=tol, inner="f16s")
+        stag.stag_cg_solve(ctx, g, [mass], fb, fx, p16)
+        s16, st16 = timed_solves(stag, torch, ctx, g, mass, fb, fx, p16, 2)
+        result["f16s_mixed"] = {"time_to_1e-8_ms": round(s16 * 1e3, 3), "iters": st16["iters"],
+                                "reliable_updates": st16["reliable_updates"],
+                                "true_rel_res": st16["true_rel_res"],
+                                "solves_per_s": round(1 / s16, 3)}
+        log("fp64", result["fp64_cg"], "f16s", result["f16s_mixed"])
+    ctx.close()
+
+    if not args.no_extras:
+        result["a_apply_32x32x32x64"] = a_apply_bandwidth(stag, torch, costs, synth)
+
+    if not args.no_cpu:
+        if fp64_iters is None:
+            with stag.Context(0) as c2:
+                g2 = c2.gauge(L, U, precisions=("f64",))
+                fb2 = c2.field(g2, 0, "f64", 1).load(b)
+                fx2 = c2.field(g2, 0, "f64", 1)
+                _, st = stag.stag_cg_solve(c2, g2, [mass], fb2, fx2, stag.cg_params(tol=tol))
+                fp64_iters = st[0]["iters"]
+        result["cpu_baseline"] = cpu_baseline(synth, L, U, b[0], mass, fp64_iters, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

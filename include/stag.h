@@ -1,0 +1,245 @@
+/*
+ * stag.h -- C ABI of libstag: conjugate-gradient solves of b = A x with the
+ * even-odd staggered normal operator on one AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (Jang, Kim and Lee, "Multi GPU Performance of Conjugate
+ * Gradient Solver with Staggered Fermions in Mixed Precision", Lattice 2011):
+ *
+ *   Sec.2, Eq.1      b = A x with A Hermitian positive definite.
+ *   Sec.2, Eq.4-5    (D chi)(x) = sum_mu U_mu(x) chi(x+mu) - U_mu(x-mu)^+ chi(x-mu),
+ *                    the staggered phase eta_mu(x) = (-1)^(x_0+...+x_{mu-1})
+ *                    multiplied into U_mu (text after Eq.5). No factor 1/2.
+ *   Sec.2, Eq.2-3    A = -D^2 + m^2, applied on the even sites:
+ *                    A chi = m^2 chi - D_eo D_oe chi.
+ *   Sec.2, Fig.1     conjugate gradient.
+ *   Sec.3.2, Eq.6    corrected mixed-precision CG: low-precision inner
+ *                    iterations, fp64 reliable and group-wise updates, the
+ *                    search direction carried over across updates, all inner
+ *                    products in fp64.
+ *
+ * Conventions (fixed by this library; the paper does not state them):
+ *   - Lattice extents L = {Lx, Ly, Lz, Lt}, each even and >= 2, periodic.
+ *   - Site lex = x + Lx*(y + Ly*(z + Lz*t)); parity (x+y+z+t) mod 2; "even" = 0.
+ *   - A parity-p vector is indexed by s = lex / 2 over the sites of parity p.
+ *   - Canonical host layouts are interleaved complex128 (re, im doubles):
+ *       gauge links  U[t][z][y][x][mu][a][b], mu = 0..3 for x, y, z, t,
+ *                    WITHOUT the staggered phases;
+ *       vectors      v[rhs][s][c], c = 0..2.
+ *   - Solver tolerance is relative to |b|: success means the fp64 true
+ *     residual satisfies |b - A x| <= tol |b| for every right-hand side.
+ *
+ * General rules:
+ *   - Every function returns an int status (STAG_OK = 0, negative = error);
+ *     no C++ exception crosses this interface. The text of the last error on
+ *     a context is available from stag_last_error().
+ *   - Objects are opaque and owned by the library; caller buffers passed in
+ *     are only read/written during the call (or, for the asynchronous
+ *     calls, until the given stream reaches the enqueued work).
+ *   - `stream` arguments are hipStream_t values passed as void*; NULL means
+ *     the context's own stream. Work is enqueued without a host sync unless
+ *     stated otherwise.
+ *   - All functions are thread-safe with respect to different contexts.
+ *     Calls on one context may come from several threads; the serving calls
+ *     (submit/poll) are designed for that.
+ */
+#ifndef STAG_H
+#define STAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define STAG_OK 0
+#define STAG_PENDING 1        /* serving: the ticket is not finished yet */
+#define STAG_EINVAL (-1)      /* invalid argument (bad pointer, size, parity, precision, mass) */
+#define STAG_ENOMEM (-2)      /* device memory or the context's HBM budget is exhausted */
+#define STAG_EDEVICE (-3)     /* a HIP runtime error; see stag_last_error */
+#define STAG_ENOCONV (-4)     /* iteration cap reached before the tolerance */
+#define STAG_EBREAKDOWN (-5)  /* <d, A d> <= 0 or a non-finite scalar in the recurrence */
+#define STAG_ESTALL (-6)      /* low-precision iteration stopped making progress */
+#define STAG_EBUSY (-7)       /* serving queue full */
+#define STAG_ENOTFOUND (-8)   /* unknown or already collected ticket */
+
+/* ------------------------------------------------------------- precisions */
+#define STAG_F64 0   /* fp64 storage and arithmetic */
+#define STAG_F32 1   /* fp32 storage and arithmetic */
+#define STAG_F16S 2  /* fp16 storage with one fp32 scale per site; fp32 arithmetic */
+
+/* bit masks of precisions for stag_gauge_create */
+#define STAG_MASK_F64 (1 << STAG_F64)
+#define STAG_MASK_F32 (1 << STAG_F32)
+#define STAG_MASK_F16S (1 << STAG_F16S)
+
+#define STAG_MAX_RHS 16 /* right-hand sides per field / per solve call */
+
+typedef struct stag_ctx stag_ctx;
+typedef struct stag_gauge stag_gauge;
+typedef struct stag_field stag_field;
+typedef int64_t stag_ticket;
+
+/* Library version, encoded as major * 10000 + minor * 100 + patch. */
+int stag_version(void);
+
+/* ---------------------------------------------------------------- context
+ * stag_create: bind a context to HIP device `device` (0-based) and create
+ * its stream. `hbm_budget_bytes` caps the device memory the context may
+ * hold (gauges, fields, solver workspaces); 0 means all currently free
+ * memory. Errors: EINVAL (null out, bad device), EDEVICE.
+ * stag_destroy: waits for the context's work, cancels pending serving
+ * tickets, frees every object created from the context. NULL is a no-op.
+ * stag_last_error: text of the last error on the context (or of the last
+ * failed stag_create on this thread when ctx is NULL); never NULL.
+ */
+int stag_create(int device, size_t hbm_budget_bytes, stag_ctx** out);
+int stag_destroy(stag_ctx* ctx);
+const char* stag_last_error(const stag_ctx* ctx);
+/* Bytes of device memory currently held by the context. */
+int stag_memory_used(const stag_ctx* ctx, size_t* bytes);
+
+/* ---------------------------------------------------------------- gauge
+ * stag_gauge_create: make a gauge field resident on the device (Sec.2:
+ * A is given by the links U and the mass m).
+ *   L           lattice extents {Lx, Ly, Lz, Lt}, each even and >= 2, with
+ *               L[0]*L[1]*L[2]*L[3]/2 < 2^31.
+ *   U           canonical links, complex128 [t][z][y][x][mu][3][3] without
+ *               phases; host memory if U_on_device == 0, device memory of the
+ *               context's device otherwise. Copied; the caller keeps ownership.
+ *   prec_mask   which stored copies to build (STAG_MASK_*); solves need
+ *               STAG_MASK_F64 plus the mask of their inner precision.
+ * The library folds the phases eta_mu into the links, splits them by parity
+ * and stores, per output site, its eight hop links in a site-coalesced
+ * layout. Synchronous. Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+int stag_gauge_create(stag_ctx* ctx, const int L[4], const double* U, int U_on_device,
+                      int prec_mask, stag_gauge** out);
+int stag_gauge_destroy(stag_gauge* gauge);
+/* Number of sites per parity (Vh = Lx*Ly*Lz*Lt/2) of a gauge's lattice. */
+int stag_gauge_sites(const stag_gauge* gauge, int64_t* vh);
+
+/* ---------------------------------------------------------------- fields
+ * A field holds nrhs (1..STAG_MAX_RHS) vectors of one parity in one storage
+ * precision, in a private site-coalesced layout.
+ * stag_field_import / stag_field_export convert from / to the canonical
+ * complex128 layout [nrhs][Vh][3]; `src`/`dst` are host memory when the
+ * *_on_device flag is 0 (then the call synchronises the stream before it
+ * returns) or device memory otherwise (asynchronous on `stream`). Importing
+ * into F32 / F16S rounds to nearest even (F16S: the site scale is the
+ * largest |Re| or |Im| of the site's six reals after rounding to fp32; the
+ * payload is fp16(value / scale); a zero site stores scale 0).
+ * Errors: EINVAL (null, nrhs out of range, parity not 0/1, bad precision),
+ * ENOMEM, EDEVICE.
+ */
+int stag_field_create(stag_ctx* ctx, const stag_gauge* gauge, int parity, int prec, int nrhs,
+                      stag_field** out);
+int stag_field_import(stag_field* f, const double* src, int src_on_device, void* stream);
+int stag_field_export(const stag_field* f, double* dst, int dst_on_device, void* stream);
+int stag_field_destroy(stag_field* f);
+
+/* ---------------------------------------------------------------- operators
+ * stag_dslash (Sec.2, Eq.5): out = D in, from parity p of `in` to parity
+ * 1 - p of `out`, for every right-hand side. `in` and `out` must be distinct
+ * fields of the same gauge, precision and nrhs; the gauge must hold that
+ * precision. F32 / F16S compute in fp32. Asynchronous on `stream`.
+ * Errors: EINVAL, EDEVICE.
+ */
+int stag_dslash(stag_ctx* ctx, const stag_gauge* gauge, const stag_field* in, stag_field* out,
+                void* stream);
+
+/* stag_apply_A (Sec.2, Eq.2-3): out_j = m_j^2 in_j - D_eo D_oe in_j on even
+ * fields, right-hand side j using mass[j] (host array of in->nrhs finite
+ * masses > 0). Asynchronous on `stream`; uses a temporary odd-parity vector
+ * allocated stream-ordered. Errors: EINVAL (parity 1, mismatch, mass <= 0 or
+ * not finite), ENOMEM, EDEVICE.
+ */
+int stag_apply_A(stag_ctx* ctx, const stag_gauge* gauge, const double* mass, const stag_field* in,
+                 stag_field* out, void* stream);
+
+/* ---------------------------------------------------------------- solver */
+typedef struct stag_cg_params {
+    double tol;        /* relative true-residual target, > 0 and < 1 */
+    int max_iter;      /* <= 0: min(10 * 3 * Vh, 10^6) */
+    int inner_prec;    /* STAG_F64: plain CG (Fig.1); STAG_F32 / STAG_F16S: mixed (Sec.3.2) */
+    double delta;      /* mixed: update when |r| < delta * max|r| since the last update; <= 0: 0.1 */
+    int stall_iters;   /* mixed: forced update + direction restart after this many
+                          iterations without a new residual minimum; <= 0: 100 */
+    int max_stall;     /* mixed: ESTALL after this many consecutive stall updates
+                          without halving the true residual; <= 0: 20 */
+    int graph_k;       /* iterations per host poll (replayed as one HIP graph when
+                          use_graph); <= 0: automatic */
+    int use_graph;     /* 1: capture the K-iteration block as a hipGraph */
+} stag_cg_params;
+
+typedef struct stag_cg_stats {
+    int iters;             /* CG iterations (inner iterations for mixed) */
+    int reliable_updates;  /* fp64 updates (mixed) / true-residual checks (plain) */
+    int restarts;          /* direction restarts */
+    int status;            /* STAG_OK, STAG_ENOCONV, STAG_EBREAKDOWN, STAG_ESTALL, STAG_EINVAL */
+    double true_rel_res;   /* |b - A x| / |b| in fp64 at the end */
+    double iter_rel_res;   /* iterated residual norm / |b| at the end */
+    double seconds;        /* wall time of the whole call */
+} stag_cg_stats;
+
+/* Fill *p with the defaults (tol 1e-8, plain fp64 CG). */
+void stag_cg_params_default(stag_cg_params* p);
+
+/* stag_cg_solve: solve A_j x_j = b_j (Sec.2 Eq.1, Fig.1; mixed: Sec.3.2)
+ * for every right-hand side j of the even F64 field `b`, writing the even F64
+ * field `x` (same nrhs; x starts from 0). mass: host array [b->nrhs]. All
+ * right-hand sides of one call are iterated together, each with its own
+ * scalars, sharing every link load. Success requires the fp64 true
+ * residual |b - A x| <= tol |b| for each; b_j = 0 gives x_j = 0. Returns
+ * after all solves ended (the host waits on `stream`); per-RHS outcomes are
+ * in stats[j] (array of b->nrhs, may be NULL). The return value is STAG_OK
+ * when every right-hand side converged, else the first failing status.
+ * Errors: EINVAL (arguments, non-finite b), ENOMEM, EDEVICE; ENOCONV,
+ * EBREAKDOWN, ESTALL as solve outcomes (x holds the last iterate).
+ */
+int stag_cg_solve(stag_ctx* ctx, const stag_gauge* gauge, const double* mass,
+                  const stag_field* b, stag_field* x, const stag_cg_params* params,
+                  stag_cg_stats* stats, void* stream);
+
+
+/* ---------------------------------------------------------------- tuning
+ * Launch shape of the two hop stages of A: S1 / S2 = lanes per output site
+ * (1, 2 or 4) for stage 1 (D_oe) and stage 2 (D_eo with the m^2 update),
+ * nt = non-temporal link loads, swizzle = XCD-aware block order. Every
+ * shape computes bit-identical results; only speed differs.
+ * stag_tune_get / stag_tune_set: the shape used for (prec, nrhs, vh).
+ * stag_tune: time every shape on the gauge's actual links and keep the
+ * fastest (synchronous; allocates temporary vectors). best / best_ms may be
+ * NULL. Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+typedef struct stag_tune_cfg {
+    int S1, S2, nt, swizzle;
+} stag_tune_cfg;
+
+int stag_tune_get(stag_ctx* ctx, int prec, int nrhs, int64_t vh, stag_tune_cfg* out);
+int stag_tune_set(stag_ctx* ctx, int prec, int nrhs, int64_t vh, const stag_tune_cfg* cfg);
+int stag_tune(stag_ctx* ctx, const stag_gauge* gauge, int prec, int nrhs, stag_tune_cfg* best,
+              double* best_ms);
+
+/* ---------------------------------------------------------------- timing
+ * While enabled, stag_cg_solve launches its kernels eagerly (no graph) and
+ * brackets each with HIP events on the launch stream; stag_timing_read
+ * returns the number of launches and their summed duration per kind.
+ * stag_timing_enable waits for the device and resets the counters.
+ */
+#define STAG_K_HOP1 0     /* inner-precision D_oe */
+#define STAG_K_HOP2 1     /* inner-precision D_eo + m^2 update + <d, A d> */
+#define STAG_K_HOP1_64 2  /* fp64 D_oe of a true-residual recompute */
+#define STAG_K_HOP2_64 3  /* fp64 D_eo + residual + norm of a recompute */
+#define STAG_K_UPDATE 4   /* fused x/y and r update with |r|^2 */
+#define STAG_K_XPAY 5     /* direction update d = r + beta d */
+#define STAG_K_OTHER 6
+int stag_timing_enable(stag_ctx* ctx, int on);
+int stag_timing_read(stag_ctx* ctx, int kind, int64_t* count, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STAG_H */

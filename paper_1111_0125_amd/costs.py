@@ -1,0 +1,66 @@
+"""Algorithmic (compulsory) byte and flop counts of the hop path.
+
+Every array a kernel must touch is counted once per launch: each output
+site reads its eight hop links (stored per output site, so there is no
+reuse to be had), reads every input colour vector once (the eight-fold
+neighbour reuse is the caches' job), reads the same-parity vectors its
+epilogue needs and writes its output once. The paper counts one D per site
+as 1584 bytes (8 links, 8 neighbour vectors and one output, fp64, no reuse)
+and 576 flops (8 hops x 9 complex multiply-adds x 8 flops) (Sec.2, after
+Eq.5); the flop convention is the paper's, the byte convention is the
+compulsory one.
+
+Bytes per stored link matrix / colour vector:
+  f64  144 / 48
+  f32   72 / 24
+  f16s  36 (+ one 4-byte scale per site shared by its 8 links) / 16
+"""
+
+LINK_BYTES = {"f64": 144, "f32": 72, "f16s": 36}
+SPINOR_BYTES = {"f64": 48, "f32": 24, "f16s": 16}
+SITE_SCALE_BYTES = {"f64": 0, "f32": 0, "f16s": 4}
+
+FLOPS_PER_SITE_D = 576          # paper's count for one D at one site
+FLOPS_PER_SITE_XPAY = 12        # m^2 x - t over 3 complex numbers
+FLOPS_PER_SITE_DOT = 12         # Re<x, h> over 3 complex numbers
+
+
+def hop_bytes_per_site(prec: str, stage: int, nrhs: int = 1) -> int:
+    """Compulsory bytes per output site of one hop launch.
+
+    stage 1 (D_oe, plain output): 8 links + nrhs x (read input + write output)
+    stage 2 (D_eo, m^2 update + dot): 8 links + nrhs x (read t, read x, write)
+    """
+    links = 8 * LINK_BYTES[prec] + SITE_SCALE_BYTES[prec]
+    vec = SPINOR_BYTES[prec] * (2 if stage == 1 else 3)
+    return links + nrhs * vec
+
+
+def a_bytes_per_site(prec: str, nrhs: int = 1) -> int:
+    """One application of A = both stages, per even site."""
+    return hop_bytes_per_site(prec, 1, nrhs) + hop_bytes_per_site(prec, 2, nrhs)
+
+
+def a_flops_per_site(nrhs: int = 1) -> int:
+    return nrhs * (2 * FLOPS_PER_SITE_D + FLOPS_PER_SITE_XPAY)
+
+
+def update_bytes_per_site(prec: str, mixed: bool) -> int:
+    """Fused update: fp64 CG reads x, r, d, Ad and writes x, r; mixed reads
+    y (fp32), rs, d, Ad and writes y, rs."""
+    if not mixed:
+        return 6 * SPINOR_BYTES["f64"]
+    return 2 * SPINOR_BYTES["f32"] + 4 * SPINOR_BYTES[prec]
+
+
+def xpay_bytes_per_site(prec: str) -> int:
+    return 3 * SPINOR_BYTES[prec]
+
+
+def cg_iteration_bytes_per_site(prec: str, mixed: bool) -> int:
+    return a_bytes_per_site(prec) + update_bytes_per_site(prec, mixed) + xpay_bytes_per_site(prec)
+
+
+def cg_iteration_flops_per_site() -> int:
+    # A + <d,Ad> + 2 axpy + |r|^2 + xpay  (paper-style count, 12 flops per complex-vector op)
+    return 2 * FLOPS_PER_SITE_D + FLOPS_PER_SITE_XPAY + 5 * 12

@@ -1,0 +1,249 @@
+// Vector kernels of the CG iteration (Fig.1 and Sec.3.2): fused axpy + norm
+// updates with fp64 reductions, the direction update, and the pieces of the
+// reliable / group-wise update. One thread per site handles every active
+// right-hand side of the block; the CG scalars are read from, and written
+// to, the device-resident per-RHS state.
+#include "kern.h"
+#include "launch.h"
+
+namespace stag {
+
+template <int N>
+__device__ __forceinline__ unsigned active_mask(const VecArgs& a) {
+    unsigned act = 0;
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+        if (!a.st || (a.st[r].flags & a.run_mask)) act |= 1u << r;
+    return act;
+}
+
+__device__ __forceinline__ char* slot(const VecArgs& a, int k, int r) {
+    return (char*)a.f[k] + (size_t)r * a.rs[k];
+}
+
+template <int P, int N, int OP>
+__global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
+    using T = typename Real<P>::T;
+    const uint32_t blk = logical_block(a.swizzle);
+    const uint32_t s = blk * kBlock + threadIdx.x;
+    const uint32_t Vh = a.Vh;
+    const bool valid = s < Vh;
+    const unsigned act = active_mask<N>(a);
+    double dv[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) dv[r] = 0.0;
+
+    if (valid) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            if (!((act >> r) & 1u)) continue;
+            if constexpr (OP == OP_INIT_B) {
+                // r64 = b, x64 = 0, |b|^2
+                double br[3], bi[3], z[3] = {0.0, 0.0, 0.0}, zi[3] = {0.0, 0.0, 0.0};
+                load_site<P64>(slot(a, 0, r), Vh, s, br, bi);
+                store_site<P64>(slot(a, 1, r), Vh, s, br, bi);
+                store_site<P64>(slot(a, 2, r), Vh, s, z, zi);
+                double acc = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc += br[c] * br[c] + bi[c] * bi[c];
+                dv[r] = acc;
+            } else if constexpr (OP == OP_START) {
+                // d = q(r64); rs = q(r64); y = 0
+                double vr[3], vi[3];
+                load_site<P64>(slot(a, 0, r), Vh, s, vr, vi);
+                T qr[3], qi[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    qr[c] = (T)vr[c];
+                    qi[c] = (T)vi[c];
+                }
+                store_site<P>(slot(a, 1, r), Vh, s, qr, qi);
+                if (a.f[2]) store_site<P>(slot(a, 2, r), Vh, s, qr, qi);
+                if (a.f[3]) {
+                    float z[3] = {0.f, 0.f, 0.f}, zi[3] = {0.f, 0.f, 0.f};
+                    store_site<P32>(slot(a, 3, r), Vh, s, z, zi);
+                }
+            } else if constexpr (OP == OP_UPD_CG) {
+                // x += alpha d; r -= alpha Ad; |r|^2   (all fp64)
+                const double al = a.st[r].alpha;
+                double xr[3], xi[3], rr[3], ri[3], dr[3], di[3], qr[3], qi[3];
+                load_site<P64>(slot(a, 0, r), Vh, s, xr, xi);
+                load_site<P64>(slot(a, 1, r), Vh, s, rr, ri);
+                load_site<P64>(slot(a, 2, r), Vh, s, dr, di);
+                load_site<P64>(slot(a, 3, r), Vh, s, qr, qi);
+                double acc = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xr[c] = fma(al, dr[c], xr[c]);
+                    xi[c] = fma(al, di[c], xi[c]);
+                    rr[c] = fma(-al, qr[c], rr[c]);
+                    ri[c] = fma(-al, qi[c], ri[c]);
+                    acc += rr[c] * rr[c] + ri[c] * ri[c];
+                }
+                store_site<P64>(slot(a, 0, r), Vh, s, xr, xi);
+                store_site<P64>(slot(a, 1, r), Vh, s, rr, ri);
+                dv[r] = acc;
+            } else if constexpr (OP == OP_UPD_MIXED) {
+                // y += alpha d (fp32); rs = q(rs - alpha Ad); |rs|^2 of the stored rs
+                const float al = (float)a.st[r].alpha;
+                float yr[3], yi[3];
+                T sr[3], si[3], dr[3], di[3], qr[3], qi[3];
+                load_site<P32>(slot(a, 0, r), Vh, s, yr, yi);
+                load_site<P>(slot(a, 1, r), Vh, s, sr, si);
+                load_site<P>(slot(a, 2, r), Vh, s, dr, di);
+                load_site<P>(slot(a, 3, r), Vh, s, qr, qi);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    yr[c] = fmaf(al, dr[c], yr[c]);
+                    yi[c] = fmaf(al, di[c], yi[c]);
+                    sr[c] = fmaf(-al, qr[c], sr[c]);
+                    si[c] = fmaf(-al, qi[c], si[c]);
+                }
+                store_site<P32>(slot(a, 0, r), Vh, s, yr, yi);
+                store_site<P>(slot(a, 1, r), Vh, s, sr, si);
+                double acc = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    acc += (double)sr[c] * (double)sr[c] + (double)si[c] * (double)si[c];
+                dv[r] = acc;
+            } else if constexpr (OP == OP_XPAY) {
+                // d = q(r + beta d)
+                const T be = (T)a.st[r].beta;
+                T rr[3], ri[3], dr[3], di[3];
+                load_site<P>(slot(a, 0, r), Vh, s, rr, ri);
+                load_site<P>(slot(a, 1, r), Vh, s, dr, di);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    dr[c] = fma(be, dr[c], rr[c]);
+                    di[c] = fma(be, di[c], ri[c]);
+                }
+                store_site<P>(slot(a, 1, r), Vh, s, dr, di);
+            } else if constexpr (OP == OP_RU_BEGIN) {
+                // x64 += y; y = 0
+                double xr[3], xi[3];
+                float yr[3], yi[3], z[3] = {0.f, 0.f, 0.f}, zi[3] = {0.f, 0.f, 0.f};
+                load_site<P64>(slot(a, 0, r), Vh, s, xr, xi);
+                load_site<P32>(slot(a, 1, r), Vh, s, yr, yi);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xr[c] += (double)yr[c];
+                    xi[c] += (double)yi[c];
+                }
+                store_site<P64>(slot(a, 0, r), Vh, s, xr, xi);
+                store_site<P32>(slot(a, 1, r), Vh, s, z, zi);
+            } else if constexpr (OP == OP_RU_END) {
+                // rs = q(r64); d = restart ? rs : q(rs + beta' d), beta' = |r64|^2 / |rs_prev|^2
+                const bool restart = (a.st[r].flags & F_STALL) != 0;
+                double vr[3], vi[3];
+                load_site<P64>(slot(a, 0, r), Vh, s, vr, vi);
+                T sr[3], si[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    sr[c] = (T)vr[c];
+                    si[c] = (T)vi[c];
+                }
+                store_site<P>(slot(a, 1, r), Vh, s, sr, si);
+                if (restart) {
+                    store_site<P>(slot(a, 2, r), Vh, s, sr, si);
+                } else {
+                    const T be = (T)(a.st[r].rr_true / a.st[r].rr_old);
+                    T dr[3], di[3];
+                    load_site<P>(slot(a, 2, r), Vh, s, dr, di);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        dr[c] = fma(be, dr[c], sr[c]);
+                        di[c] = fma(be, di[c], si[c]);
+                    }
+                    store_site<P>(slot(a, 2, r), Vh, s, dr, di);
+                }
+            } else if constexpr (OP == OP_CG_CHECK) {
+                // restart direction d = r (the true residual)
+                double vr[3], vi[3];
+                load_site<P64>(slot(a, 0, r), Vh, s, vr, vi);
+                store_site<P64>(slot(a, 1, r), Vh, s, vr, vi);
+            } else if constexpr (OP == OP_ZERO) {
+                T z[3] = {T(0), T(0), T(0)}, zi[3] = {T(0), T(0), T(0)};
+                store_site<P>(slot(a, 0, r), Vh, s, z, zi);
+            }
+        }
+    }
+    if constexpr (OP == OP_INIT_B || OP == OP_UPD_CG || OP == OP_UPD_MIXED || OP == OP_RU_END ||
+                  OP == OP_CG_CHECK) {
+        block_reduce_finalize<N, 1>(dv, act, a.red, blk);
+    }
+}
+
+template <int P, int N>
+static hipError_t run_vec_n(int op, const VecArgs& a, hipStream_t st) {
+    const dim3 grid(vec_blocks(a.Vh)), block(kBlock);
+#define STAG_VEC_CASE(OPV)                                                   \
+    case OPV:                                                                \
+        hipLaunchKernelGGL((k_vec<P, N, OPV>), grid, block, 0, st, a);       \
+        return hipGetLastError();
+    switch (op) {
+        STAG_VEC_CASE(OP_START)
+        STAG_VEC_CASE(OP_XPAY)
+        STAG_VEC_CASE(OP_ZERO)
+        default:
+            break;
+    }
+    if constexpr (P == P64) {
+        switch (op) {
+            STAG_VEC_CASE(OP_INIT_B)
+            STAG_VEC_CASE(OP_UPD_CG)
+            STAG_VEC_CASE(OP_CG_CHECK)
+            default:
+                break;
+        }
+    } else {
+        switch (op) {
+            STAG_VEC_CASE(OP_UPD_MIXED)
+            STAG_VEC_CASE(OP_RU_BEGIN)
+            STAG_VEC_CASE(OP_RU_END)
+            default:
+                break;
+        }
+    }
+#undef STAG_VEC_CASE
+    return hipErrorInvalidValue;
+}
+
+template <int P>
+static hipError_t run_vec(int N, int op, const VecArgs& a, hipStream_t st) {
+    switch (N) {
+        case 1: return run_vec_n<P, 1>(op, a, st);
+        case 2: return run_vec_n<P, 2>(op, a, st);
+        case 4: return run_vec_n<P, 4>(op, a, st);
+        case 8: return run_vec_n<P, 8>(op, a, st);
+        case 12: return run_vec_n<P, 12>(op, a, st);
+        case 16: return run_vec_n<P, 16>(op, a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_vec(int prec, int N, int op, const VecArgs& a, hipStream_t st) {
+    switch (prec) {
+        case P64: return run_vec<P64>(N, op, a, st);
+        case P32: return run_vec<P32>(N, op, a, st);
+        case P16S: return run_vec<P16S>(N, op, a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------ hop dispatch
+
+hipError_t launch_hop_p0(int S, int N, int epi, bool nt, const HopArgs& a, hipStream_t st);
+hipError_t launch_hop_p1(int S, int N, int epi, bool nt, const HopArgs& a, hipStream_t st);
+hipError_t launch_hop_p2(int S, int N, int epi, bool nt, const HopArgs& a, hipStream_t st);
+
+hipError_t launch_hop(int prec, int S, int N, int epi, bool nt, const HopArgs& a,
+                      hipStream_t st) {
+    switch (prec) {
+        case P64: return launch_hop_p0(S, N, epi, nt, a, st);
+        case P32: return launch_hop_p1(S, N, epi, nt, a, st);
+        case P16S: return launch_hop_p2(S, N, epi, nt, a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace stag

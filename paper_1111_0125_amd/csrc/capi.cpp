@@ -1,0 +1,601 @@
+// C ABI entry points of libstag: contexts, gauges, fields, the Dirac
+// operator, A, and the CG solve. Argument validation happens here, before
+// any device work; the solver engine is in solver.cpp.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+
+using namespace stag;
+
+namespace stag {
+
+static thread_local std::string g_create_err;
+
+int set_error(stag_ctx* ctx, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) {
+        std::lock_guard<std::mutex> lk(ctx->err_mu);
+        ctx->err = buf;
+    } else {
+        g_create_err = buf;
+    }
+    return code;
+}
+
+int dev_alloc(stag_ctx* ctx, size_t bytes, void** p) {
+    *p = nullptr;
+    if (bytes == 0) return STAG_OK;
+    size_t prev = ctx->used.fetch_add(bytes);
+    if (ctx->budget && prev + bytes > ctx->budget) {
+        ctx->used.fetch_sub(bytes);
+        return set_error(ctx, STAG_ENOMEM, "HBM budget exceeded: %zu + %zu > %zu bytes", prev,
+                         bytes, ctx->budget);
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        ctx->used.fetch_sub(bytes);
+        *p = nullptr;
+        (void)hipGetLastError();
+        return set_error(ctx, STAG_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    return STAG_OK;
+}
+
+void dev_free(stag_ctx* ctx, void* p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    ctx->used.fetch_sub(bytes);
+}
+
+Geom make_geom(const int L[4]) {
+    Geom g{};
+    for (int i = 0; i < 4; ++i) g.L[i] = L[i];
+    const uint64_t V = (uint64_t)L[0] * L[1] * L[2] * L[3];
+    g.Vh = (uint32_t)(V / 2);
+    g.hx = (uint32_t)(L[0] / 2);
+    g.sy = g.hx;
+    g.sz = g.hx * (uint32_t)L[1];
+    g.st = g.sz * (uint32_t)L[2];
+    g.div_hx = make_fastdiv(g.hx);
+    g.div_Ly = make_fastdiv((uint32_t)L[1]);
+    g.div_Lz = make_fastdiv((uint32_t)L[2]);
+    return g;
+}
+
+static long long tune_key(int prec, int N, uint32_t Vh) {
+    int bucket = 0;
+    while ((1u << bucket) < Vh && bucket < 31) ++bucket;
+    return ((long long)prec << 40) | ((long long)N << 32) | bucket;
+}
+
+HopTune get_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh) {
+    {
+        std::lock_guard<std::mutex> lk(ctx->tune_mu);
+        auto it = ctx->tune.find(tune_key(prec, N, Vh));
+        if (it != ctx->tune.end()) return it->second;
+    }
+    // Heuristic default: enough lanes in flight to cover the 256 CUs with a
+    // few waves each; split sites across lanes on small lattices.
+    HopTune t;
+    if (N == 1) {
+        const uint64_t target = 1u << 20;  // threads
+        int S = 1;
+        while (S < 4 && (uint64_t)Vh * S < target) S *= 2;
+        t.S1 = t.S2 = S;
+    }
+    t.nt = 1;
+    t.swizzle = 1;
+    return t;
+}
+
+void set_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh, const HopTune& t) {
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    ctx->tune[tune_key(prec, N, Vh)] = t;
+}
+
+hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, const HopTune& t,
+                       const void* in, size_t in_rs, void* out, size_t out_rs, int p_out,
+                       const void* x, size_t x_rs, const void* b, size_t b_rs, const double* m2,
+                       RhsState* st, unsigned run_mask, const Reduce* red, hipStream_t stream) {
+    HopArgs a{};
+    a.gauge = g->G[prec][p_out];
+    a.gscale = prec == P16S ? g->gscale[p_out] : nullptr;
+    a.in = in;
+    a.in_rs = in_rs;
+    a.out = out;
+    a.out_rs = out_rs;
+    a.x = x;
+    a.x_rs = x_rs;
+    a.b = b;
+    a.b_rs = b_rs;
+    for (int r = 0; r < kMaxN; ++r) a.m2[r] = m2 ? m2[r] : 0.0;
+    a.st = st;
+    a.run_mask = run_mask;
+    a.p_out = p_out;
+    a.swizzle = t.swizzle;
+    a.g = g->g;
+    if (red) a.red = *red;
+    if (N > 1) S = 1;
+    return launch_hop(prec, S, N, epi, t.nt != 0, a, stream);
+}
+
+}  // namespace stag
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+#define STAG_VERSION 10000
+
+#define HIPCK(ctx, call)                                                              \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            (void)hipGetLastError();                                                  \
+            return set_error((ctx), STAG_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+        }                                                                             \
+    } while (0)
+
+extern "C" {
+
+int stag_version(void) { return STAG_VERSION; }
+
+const char* stag_last_error(const stag_ctx* ctx) {
+    if (!ctx) return g_create_err.c_str();
+    return ctx->err.c_str();
+}
+
+int stag_create(int device, size_t hbm_budget_bytes, stag_ctx** out) {
+    if (!out) return set_error(nullptr, STAG_EINVAL, "stag_create: out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return set_error(nullptr, STAG_EDEVICE, "stag_create: no HIP device (%s)",
+                         hipGetErrorString(e));
+    }
+    if (device < 0 || device >= n)
+        return set_error(nullptr, STAG_EINVAL, "stag_create: device %d out of range [0, %d)",
+                         device, n);
+    DeviceGuard dg(device);
+    hipStream_t s = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(nullptr, STAG_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    stag_ctx* c = new stag_ctx();
+    c->device = device;
+    c->stream = s;
+    if (hbm_budget_bytes == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) c->budget = fr;
+        (void)hipGetLastError();
+    } else {
+        c->budget = hbm_budget_bytes;
+    }
+    *out = c;
+    return STAG_OK;
+}
+
+int stag_serve_shutdown_internal(stag_ctx* ctx);  // serve.cpp
+
+int stag_destroy(stag_ctx* ctx) {
+    if (!ctx) return STAG_OK;
+    DeviceGuard dg(ctx->device);
+    stag_serve_shutdown_internal(ctx);
+    (void)hipStreamSynchronize(ctx->stream);
+    std::vector<stag_engine*> engines;
+    std::vector<stag_field*> fields;
+    std::vector<stag_gauge*> gauges;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        engines.swap(ctx->engines);
+        fields.swap(ctx->fields);
+        gauges.swap(ctx->gauges);
+    }
+    for (auto* e : engines) engine_destroy(e);
+    for (auto* f : fields) {
+        dev_free(ctx, f->data, f->rs * f->nrhs);
+        delete f;
+    }
+    for (auto* g : gauges) {
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 2; ++q) (void)hipFree(g->G[p][q]);
+        for (int q = 0; q < 2; ++q) (void)hipFree(g->gscale[q]);
+        delete g;
+    }
+    (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return STAG_OK;
+}
+
+int stag_memory_used(const stag_ctx* ctx, size_t* bytes) {
+    if (!ctx || !bytes) return STAG_EINVAL;
+    *bytes = ctx->used.load();
+    return STAG_OK;
+}
+
+static hipStream_t pick_stream(stag_ctx* ctx, void* s) {
+    return s ? (hipStream_t)s : ctx->stream;
+}
+
+int stag_gauge_create(stag_ctx* ctx, const int L[4], const double* U, int U_on_device,
+                      int prec_mask, stag_gauge** out) {
+    if (!ctx) return STAG_EINVAL;
+    if (!out || !L || !U)
+        return set_error(ctx, STAG_EINVAL, "stag_gauge_create: NULL argument");
+    *out = nullptr;
+    uint64_t V = 1;
+    for (int i = 0; i < 4; ++i) {
+        if (L[i] < 2 || (L[i] & 1))
+            return set_error(ctx, STAG_EINVAL,
+                             "stag_gauge_create: extent L[%d] = %d must be even and >= 2", i, L[i]);
+        V *= (uint64_t)L[i];
+    }
+    if (V / 2 >= (1ull << 31))
+        return set_error(ctx, STAG_EINVAL, "stag_gauge_create: lattice too large");
+    if (prec_mask <= 0 || prec_mask > 7)
+        return set_error(ctx, STAG_EINVAL, "stag_gauge_create: bad precision mask %d", prec_mask);
+    DeviceGuard dg(ctx->device);
+    stag_gauge* g = new stag_gauge();
+    g->ctx = ctx;
+    for (int i = 0; i < 4; ++i) g->L[i] = L[i];
+    g->g = make_geom(L);
+    g->mask = prec_mask;
+    const size_t Vh = g->g.Vh;
+    const size_t ubytes = (size_t)V * 4 * 9 * 16;
+    void* Ud = nullptr;
+    int rc = STAG_OK;
+    auto cleanup = [&]() {
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 2; ++q)
+                if (g->G[p][q]) dev_free(ctx, g->G[p][q], gauge_parity_bytes(p, Vh) - (p == P16S ? Vh * 4 : 0));
+        for (int q = 0; q < 2; ++q)
+            if (g->gscale[q]) dev_free(ctx, g->gscale[q], Vh * 4);
+        delete g;
+    };
+    if (!U_on_device) {
+        hipError_t e = hipMalloc(&Ud, ubytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            cleanup();
+            return set_error(ctx, STAG_ENOMEM, "stag_gauge_create: staging hipMalloc(%zu): %s",
+                             ubytes, hipGetErrorString(e));
+        }
+        e = hipMemcpy(Ud, U, ubytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(Ud);
+            cleanup();
+            return set_error(ctx, STAG_EDEVICE, "stag_gauge_create: copy: %s", hipGetErrorString(e));
+        }
+    }
+    const void* Usrc = U_on_device ? (const void*)U : Ud;
+    for (int p = 0; p < 3 && rc == STAG_OK; ++p) {
+        if (!(prec_mask & (1 << p))) continue;
+        const size_t gb = gauge_parity_bytes(p, Vh) - (p == P16S ? Vh * 4 : 0);
+        for (int q = 0; q < 2 && rc == STAG_OK; ++q) {
+            rc = dev_alloc(ctx, gb, &g->G[p][q]);
+            if (rc == STAG_OK && p == P16S) rc = dev_alloc(ctx, Vh * 4, (void**)&g->gscale[q]);
+            if (rc == STAG_OK) {
+                hipError_t e = launch_gauge_pack(p, Usrc, g->G[p][q], g->gscale[q], g->g, q, ctx->stream);
+                if (e != hipSuccess) {
+                    (void)hipGetLastError();
+                    rc = set_error(ctx, STAG_EDEVICE, "gauge pack: %s", hipGetErrorString(e));
+                }
+            }
+            g->bytes += gb + (p == P16S ? Vh * 4 : 0);
+        }
+    }
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (Ud) (void)hipFree(Ud);
+    if (rc == STAG_OK && e != hipSuccess) {
+        (void)hipGetLastError();
+        rc = set_error(ctx, STAG_EDEVICE, "gauge pack sync: %s", hipGetErrorString(e));
+    }
+    if (rc != STAG_OK) {
+        cleanup();
+        return rc;
+    }
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->gauges.push_back(g);
+    }
+    *out = g;
+    return STAG_OK;
+}
+
+int stag_gauge_destroy(stag_gauge* g) {
+    if (!g) return STAG_OK;
+    stag_ctx* ctx = g->ctx;
+    DeviceGuard dg(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    std::vector<stag_engine*> drop;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto& v = ctx->gauges;
+        for (size_t i = 0; i < v.size(); ++i)
+            if (v[i] == g) {
+                v.erase(v.begin() + i);
+                break;
+            }
+        auto& es = ctx->engines;
+        for (size_t i = 0; i < es.size();) {
+            if (es[i]->gauge == g && !es[i]->in_use) {
+                drop.push_back(es[i]);
+                es.erase(es.begin() + i);
+            } else {
+                ++i;
+            }
+        }
+    }
+    for (auto* e : drop) engine_destroy(e);
+    const size_t Vh = g->g.Vh;
+    for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 2; ++q)
+            if (g->G[p][q]) dev_free(ctx, g->G[p][q], gauge_parity_bytes(p, Vh) - (p == P16S ? Vh * 4 : 0));
+    for (int q = 0; q < 2; ++q)
+        if (g->gscale[q]) dev_free(ctx, g->gscale[q], Vh * 4);
+    delete g;
+    return STAG_OK;
+}
+
+int stag_gauge_sites(const stag_gauge* g, int64_t* vh) {
+    if (!g || !vh) return STAG_EINVAL;
+    *vh = g->g.Vh;
+    return STAG_OK;
+}
+
+int stag_field_create(stag_ctx* ctx, const stag_gauge* g, int parity, int prec, int nrhs,
+                      stag_field** out) {
+    if (!ctx) return STAG_EINVAL;
+    if (!g || !out) return set_error(ctx, STAG_EINVAL, "stag_field_create: NULL argument");
+    *out = nullptr;
+    if (g->ctx != ctx) return set_error(ctx, STAG_EINVAL, "stag_field_create: gauge of another context");
+    if (parity != 0 && parity != 1)
+        return set_error(ctx, STAG_EINVAL, "stag_field_create: parity %d not 0 or 1", parity);
+    if (prec < 0 || prec > 2) return set_error(ctx, STAG_EINVAL, "stag_field_create: precision %d", prec);
+    if (nrhs < 1 || nrhs > STAG_MAX_RHS)
+        return set_error(ctx, STAG_EINVAL, "stag_field_create: nrhs %d out of [1, %d]", nrhs, STAG_MAX_RHS);
+    DeviceGuard dg(ctx->device);
+    stag_field* f = new stag_field();
+    f->ctx = ctx;
+    f->gauge = g;
+    f->parity = parity;
+    f->prec = prec;
+    f->nrhs = nrhs;
+    f->rs = spinor_rhs_bytes(prec, g->g.Vh);
+    int rc = dev_alloc(ctx, f->rs * nrhs, &f->data);
+    if (rc != STAG_OK) {
+        delete f;
+        return rc;
+    }
+    // zero-initialise so an export before any import is well defined
+    hipError_t e = hipMemsetAsync(f->data, 0, f->rs * nrhs, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        dev_free(ctx, f->data, f->rs * nrhs);
+        delete f;
+        return set_error(ctx, STAG_EDEVICE, "field init: %s", hipGetErrorString(e));
+    }
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->fields.push_back(f);
+    }
+    *out = f;
+    return STAG_OK;
+}
+
+int stag_field_destroy(stag_field* f) {
+    if (!f) return STAG_OK;
+    stag_ctx* ctx = f->ctx;
+    DeviceGuard dg(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto& v = ctx->fields;
+        for (size_t i = 0; i < v.size(); ++i)
+            if (v[i] == f) {
+                v.erase(v.begin() + i);
+                break;
+            }
+    }
+    dev_free(ctx, f->data, f->rs * f->nrhs);
+    delete f;
+    return STAG_OK;
+}
+
+int stag_field_import(stag_field* f, const double* src, int src_on_device, void* stream) {
+    if (!f) return STAG_EINVAL;
+    stag_ctx* ctx = f->ctx;
+    if (!src) return set_error(ctx, STAG_EINVAL, "stag_field_import: src is NULL");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = pick_stream(ctx, stream);
+    const size_t Vh = f->gauge->g.Vh;
+    const size_t bytes = (size_t)f->nrhs * Vh * 48;
+    const void* dsrc = src;
+    void* tmp = nullptr;
+    if (!src_on_device) {
+        HIPCK(ctx, hipMallocAsync(&tmp, bytes, s));
+        HIPCK(ctx, hipMemcpyAsync(tmp, src, bytes, hipMemcpyHostToDevice, s));
+        dsrc = tmp;
+    }
+    HIPCK(ctx, launch_import(f->prec, dsrc, f->data, f->rs, (uint32_t)Vh, f->nrhs, s));
+    if (tmp) {
+        HIPCK(ctx, hipFreeAsync(tmp, s));
+        HIPCK(ctx, hipStreamSynchronize(s));
+    }
+    return STAG_OK;
+}
+
+int stag_field_export(const stag_field* f, double* dst, int dst_on_device, void* stream) {
+    if (!f) return STAG_EINVAL;
+    stag_ctx* ctx = f->ctx;
+    if (!dst) return set_error(ctx, STAG_EINVAL, "stag_field_export: dst is NULL");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = pick_stream(ctx, stream);
+    const size_t Vh = f->gauge->g.Vh;
+    const size_t bytes = (size_t)f->nrhs * Vh * 48;
+    void* ddst = dst;
+    void* tmp = nullptr;
+    if (!dst_on_device) {
+        HIPCK(ctx, hipMallocAsync(&tmp, bytes, s));
+        ddst = tmp;
+    }
+    HIPCK(ctx, launch_export(f->prec, f->data, f->rs, ddst, (uint32_t)Vh, f->nrhs, s));
+    if (tmp) {
+        HIPCK(ctx, hipMemcpyAsync(dst, tmp, bytes, hipMemcpyDeviceToHost, s));
+        HIPCK(ctx, hipFreeAsync(tmp, s));
+        HIPCK(ctx, hipStreamSynchronize(s));
+    }
+    return STAG_OK;
+}
+
+static int check_pair(stag_ctx* ctx, const stag_gauge* g, const stag_field* in,
+                      const stag_field* out, const char* fn) {
+    if (!g || !in || !out) return set_error(ctx, STAG_EINVAL, "%s: NULL argument", fn);
+    if (g->ctx != ctx || in->ctx != ctx || out->ctx != ctx)
+        return set_error(ctx, STAG_EINVAL, "%s: objects from another context", fn);
+    if (in->gauge != g || out->gauge != g)
+        return set_error(ctx, STAG_EINVAL, "%s: field of another gauge", fn);
+    if (in == out) return set_error(ctx, STAG_EINVAL, "%s: in and out must differ", fn);
+    if (in->prec != out->prec || in->nrhs != out->nrhs)
+        return set_error(ctx, STAG_EINVAL, "%s: precision / nrhs mismatch", fn);
+    if (!(g->mask & (1 << in->prec)))
+        return set_error(ctx, STAG_EINVAL, "%s: gauge has no copy in precision %d", fn, in->prec);
+    return STAG_OK;
+}
+
+int stag_dslash(stag_ctx* ctx, const stag_gauge* g, const stag_field* in, stag_field* out,
+                void* stream) {
+    if (!ctx) return STAG_EINVAL;
+    int rc = check_pair(ctx, g, in, out, "stag_dslash");
+    if (rc) return rc;
+    if (out->parity != 1 - in->parity)
+        return set_error(ctx, STAG_EINVAL, "stag_dslash: out parity must be 1 - in parity");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = pick_stream(ctx, stream);
+    const int N = pick_n(in->nrhs);
+    // process exactly nrhs blocks: spare slots of the N-kernel get no state
+    // and would be processed, so run in chunks of instantiated sizes
+    int done = 0;
+    while (done < in->nrhs) {
+        int n = in->nrhs - done;
+        int Nk = pick_n(n);
+        if (Nk > n) {
+            // largest instantiated size <= n
+            static const int ns[] = {16, 12, 8, 4, 2, 1};
+            for (int v : ns)
+                if (v <= n) {
+                    Nk = v;
+                    break;
+                }
+        }
+        HopTune t = get_tune(ctx, in->prec, Nk, g->g.Vh);
+        const char* ip = (const char*)in->data + (size_t)done * in->rs;
+        char* op = (char*)out->data + (size_t)done * out->rs;
+        HIPCK(ctx, enqueue_hop(g, in->prec, t.S1, Nk, EPI_PLAIN, t, ip, in->rs, op, out->rs,
+                               out->parity, nullptr, 0, nullptr, 0, nullptr, nullptr, 0, nullptr, s));
+        done += Nk;
+    }
+    (void)N;
+    return STAG_OK;
+}
+
+int stag_apply_A(stag_ctx* ctx, const stag_gauge* g, const double* mass, const stag_field* in,
+                 stag_field* out, void* stream) {
+    if (!ctx) return STAG_EINVAL;
+    int rc = check_pair(ctx, g, in, out, "stag_apply_A");
+    if (rc) return rc;
+    if (!mass) return set_error(ctx, STAG_EINVAL, "stag_apply_A: mass is NULL");
+    if (in->parity != 0 || out->parity != 0)
+        return set_error(ctx, STAG_EINVAL, "stag_apply_A: fields must be even (parity 0)");
+    for (int r = 0; r < in->nrhs; ++r)
+        if (!(mass[r] > 0.0) || !std::isfinite(mass[r]))
+            return set_error(ctx, STAG_EINVAL, "stag_apply_A: mass[%d] must be finite and > 0", r);
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = pick_stream(ctx, stream);
+    void* t = nullptr;
+    HIPCK(ctx, hipMallocAsync(&t, in->rs * in->nrhs, s));
+    int done = 0;
+    while (done < in->nrhs) {
+        int n = in->nrhs - done;
+        int Nk = 1;
+        static const int ns[] = {16, 12, 8, 4, 2, 1};
+        for (int v : ns)
+            if (v <= n) {
+                Nk = v;
+                break;
+            }
+        double m2[kMaxN] = {0};
+        for (int r = 0; r < Nk; ++r) m2[r] = mass[done + r] * mass[done + r];
+        HopTune tu = get_tune(ctx, in->prec, Nk, g->g.Vh);
+        const char* ip = (const char*)in->data + (size_t)done * in->rs;
+        char* tp = (char*)t + (size_t)done * in->rs;
+        char* op = (char*)out->data + (size_t)done * out->rs;
+        HIPCK(ctx, enqueue_hop(g, in->prec, tu.S1, Nk, EPI_PLAIN, tu, ip, in->rs, tp, in->rs, 1,
+                               nullptr, 0, nullptr, 0, nullptr, nullptr, 0, nullptr, s));
+        HIPCK(ctx, enqueue_hop(g, in->prec, tu.S2, Nk, EPI_XPAY, tu, tp, in->rs, op, out->rs, 0, ip,
+                               in->rs, nullptr, 0, m2, nullptr, 0, nullptr, s));
+        done += Nk;
+    }
+    HIPCK(ctx, hipFreeAsync(t, s));
+    return STAG_OK;
+}
+
+void stag_cg_params_default(stag_cg_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->tol = 1e-8;
+    p->max_iter = 0;
+    p->inner_prec = STAG_F64;
+    p->delta = 0.1;
+    p->stall_iters = 100;
+    p->max_stall = 20;
+    p->graph_k = 0;
+    p->use_graph = 1;
+}
+
+int stag_cg_solve(stag_ctx* ctx, const stag_gauge* g, const double* mass, const stag_field* b,
+                  stag_field* x, const stag_cg_params* params, stag_cg_stats* stats,
+                  void* stream) {
+    if (!ctx) return STAG_EINVAL;
+    if (!g || !mass || !b || !x || !params)
+        return set_error(ctx, STAG_EINVAL, "stag_cg_solve: NULL argument");
+    if (g->ctx != ctx || b->ctx != ctx || x->ctx != ctx || b->gauge != g || x->gauge != g)
+        return set_error(ctx, STAG_EINVAL, "stag_cg_solve: objects of another context / gauge");
+    if (b == x) return set_error(ctx, STAG_EINVAL, "stag_cg_solve: b and x must differ");
+    if (b->prec != STAG_F64 || x->prec != STAG_F64 || b->parity != 0 || x->parity != 0)
+        return set_error(ctx, STAG_EINVAL, "stag_cg_solve: b and x must be even F64 fields");
+    if (b->nrhs != x->nrhs) return set_error(ctx, STAG_EINVAL, "stag_cg_solve: nrhs mismatch");
+    const stag_cg_params& p = *params;
+    if (!(p.tol > 0.0 && p.tol < 1.0))
+        return set_error(ctx, STAG_EINVAL, "stag_cg_solve: tol must be in (0, 1)");
+    if (p.inner_prec < 0 || p.inner_prec > 2)
+        return set_error(ctx, STAG_EINVAL, "stag_cg_solve: inner precision %d", p.inner_prec);
+    if (!(g->mask & STAG_MASK_F64) || !(g->mask & (1 << p.inner_prec)))
+        return set_error(ctx, STAG_EINVAL,
+                         "stag_cg_solve: gauge needs the F64 copy and the inner-precision copy");
+    for (int r = 0; r < b->nrhs; ++r)
+        if (!(mass[r] > 0.0) || !std::isfinite(mass[r]))
+            return set_error(ctx, STAG_EINVAL, "stag_cg_solve: mass[%d] must be finite and > 0", r);
+    DeviceGuard dg(ctx->device);
+    stag_engine* e = nullptr;
+    int rc = engine_acquire(ctx, g, p.inner_prec, pick_n(b->nrhs), &e);
+    if (rc) return rc;
+    rc = engine_solve(e, b->nrhs, mass, b->data, b->rs, x->data, x->rs, p, stats,
+                      pick_stream(ctx, stream));
+    engine_release(e);
+    return rc;
+}
+
+}  // extern "C"

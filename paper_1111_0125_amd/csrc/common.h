@@ -1,0 +1,190 @@
+// Internal declarations shared by the HIP kernels and the host engine of
+// libstag. Not part of the public C ABI (that is include/stag.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace stag {
+
+// Storage precisions of a field or of a copy of the gauge field.
+enum Prec : int { P64 = 0, P32 = 1, P16S = 2 };
+
+// ---------------------------------------------------------------------------
+// Lattice geometry.
+//
+// Sites are numbered lex = x + Lx*(y + Ly*(z + Lz*t)); parity (x+y+z+t) & 1.
+// A parity-p field is indexed by the checkerboard index s = lex >> 1, which is
+// a bijection onto [0, Vh) because Lx is even. Periodic in all directions.
+// ---------------------------------------------------------------------------
+
+// Division by a constant through a multiply and a shift (Granlund and
+// Montgomery, "Division by invariant integers using multiplication", 1994):
+// for n < 2^31 and 1 <= d < 2^31, n / d == (n * M) >> (32 + k) with
+// k = ceil(log2 d) and M = ceil(2^(32+k) / d), which fits in 33 bits.
+struct FastDiv {
+    uint64_t mul;
+    uint32_t shift;
+    uint32_t d;
+    __host__ __device__ __forceinline__ uint32_t div(uint32_t n) const {
+        return (uint32_t)(((uint64_t)n * mul) >> shift);
+    }
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f;
+    f.d = d;
+    uint32_t k = 0;
+    while ((1ull << k) < d) ++k;
+    unsigned __int128 num = ((unsigned __int128)1) << (32 + k);
+    f.mul = (uint64_t)((num + d - 1) / d);
+    f.shift = 32 + k;
+    return f;
+}
+
+struct Geom {
+    int L[4];          // Lx, Ly, Lz, Lt
+    uint32_t Vh;       // sites per parity
+    uint32_t hx;       // Lx / 2
+    uint32_t sy, sz, st;  // checkerboard strides of y, z, t: hx, hx*Ly, hx*Ly*Lz
+    FastDiv div_hx, div_Ly, div_Lz;
+};
+
+// Coordinates of the site with checkerboard index s on parity p.
+__device__ __forceinline__ void site_coords(const Geom& g, uint32_t s, int p, int& x, int& y,
+                                            int& z, int& t) {
+    uint32_t row = g.div_hx.div(s);
+    uint32_t xh = s - row * g.hx;
+    uint32_t r2 = g.div_Ly.div(row);
+    y = (int)(row - r2 * (uint32_t)g.L[1]);
+    uint32_t r3 = g.div_Lz.div(r2);
+    z = (int)(r2 - r3 * (uint32_t)g.L[2]);
+    t = (int)r3;
+    x = 2 * (int)xh + ((y + z + t + p) & 1);
+}
+
+// Checkerboard indices of the forward and backward neighbours of site
+// (x, y, z, t) in direction mu (both lie on the opposite parity).
+__device__ __forceinline__ void neighbours(const Geom& g, uint32_t s, int x, int y, int z, int t,
+                                           int mu, uint32_t& nf, uint32_t& nb) {
+    if (mu == 0) {
+        uint32_t base = s - (uint32_t)(x >> 1);
+        int xf = (x + 1 == g.L[0]) ? 0 : x + 1;
+        int xb = (x == 0) ? g.L[0] - 1 : x - 1;
+        nf = base + (uint32_t)(xf >> 1);
+        nb = base + (uint32_t)(xb >> 1);
+    } else if (mu == 1) {
+        nf = (y + 1 == g.L[1]) ? s - (uint32_t)(g.L[1] - 1) * g.sy : s + g.sy;
+        nb = (y == 0) ? s + (uint32_t)(g.L[1] - 1) * g.sy : s - g.sy;
+    } else if (mu == 2) {
+        nf = (z + 1 == g.L[2]) ? s - (uint32_t)(g.L[2] - 1) * g.sz : s + g.sz;
+        nb = (z == 0) ? s + (uint32_t)(g.L[2] - 1) * g.sz : s - g.sz;
+    } else {
+        nf = (t + 1 == g.L[3]) ? s - (uint32_t)(g.L[3] - 1) * g.st : s + g.st;
+        nb = (t == 0) ? s + (uint32_t)(g.L[3] - 1) * g.st : s - g.st;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Field storage (per right-hand side; a field with nrhs > 1 holds nrhs such
+// blocks back to back, each `rhs_bytes` long):
+//   P64   double2 [3][Vh]   (colour-major planes of complex numbers)
+//   P32   float2  [3][Vh]
+//   P16S  Rec16   [Vh]      (three half2 colours and one fp32 site scale)
+// ---------------------------------------------------------------------------
+struct __align__(16) Rec16 {
+    __half2 c[3];
+    float s;
+};
+
+inline size_t spinor_rhs_bytes(int prec, size_t Vh) {
+    return prec == P64 ? Vh * 48 : prec == P32 ? Vh * 24 : Vh * 16;
+}
+
+// ---------------------------------------------------------------------------
+// Gauge storage, one array per output parity p (the parity of the sites the
+// hop kernel writes). For output site s the kernel reads eight "hop links":
+// hop 2*mu   : L = eta_mu(x) U_mu(x)                     applied to chi(x + mu)
+// hop 2*mu+1 : L = -(eta_mu(x - mu) U_mu(x - mu))^dagger applied to chi(x - mu)
+// so the Dirac operator is a plain sum of eight matrix-vector products.
+// The 72 complex entries (hop-major, then row-major 3x3) are stored word-major
+// over the sites so that a wavefront reading word w of 64 consecutive sites
+// touches one contiguous span:
+//   P64   72 words of double2 (one complex)      at [w][Vh]
+//   P32   36 words of float4  (two complex)      at [w][Vh]
+//   P16S  36 words of uint2   (two half2 complex)at [w][Vh], plus one fp32
+//         scale per site at [Vh] (largest |Re|,|Im| over the 144 reals).
+// Hop pair mu (hops 2mu, 2mu+1) is 18 complex = words 18mu.. (P64) or 9mu..
+// (P32, P16S).
+// ---------------------------------------------------------------------------
+inline size_t gauge_parity_bytes(int prec, size_t Vh) {
+    return prec == P64 ? Vh * 72 * 16 : prec == P32 ? Vh * 36 * 16 : Vh * (36 * 8 + 4);
+}
+
+// ---------------------------------------------------------------------------
+// Per right-hand-side solver state, resident in device memory. Scalars of
+// the CG recurrence are computed on the device by the last block of each
+// reduction; the host only reads the flags at poll points.
+// ---------------------------------------------------------------------------
+enum StateFlag : unsigned {
+    F_ACTIVE = 1u,       // iterating
+    F_CONV = 2u,         // iterated residual met the tolerance (plain CG)
+    F_RU = 4u,           // reliable / group-wise update due (mixed CG)
+    F_STALL = 8u,        // no new residual minimum for stall_iters iterations
+    F_DONE = 16u,        // true residual met the tolerance
+    F_BREAKDOWN = 32u,   // <d, A d> <= 0 or not finite
+    F_MAXIT = 64u,       // iteration cap reached
+    F_ESTALL = 128u,     // repeated stall restarts without progress
+    F_BADINPUT = 256u,   // |b|^2 not finite
+};
+
+struct RhsState {
+    double rr;        // |r|^2 of the current (iterated) residual
+    double rr_old;    // previous |r|^2
+    double pAp;       // <d, A d>
+    double alpha, beta;
+    double bb;        // |b|^2
+    double rr_stop;   // tol^2 |b|^2
+    double rr_true;   // last recomputed |b - A x|^2
+    double rmax, rmin;
+    double best_true; // smallest true |r|^2 seen at a stall update
+    double delta;     // update threshold (fraction of the running maximum)
+    double tol2;      // tol^2
+    double m2;        // mass^2
+    int since;        // iterations since the last new residual minimum
+    int stall_iters;
+    int stall_count;
+    int max_stall;
+    int iters;
+    int max_iter;
+    int updates;
+    int restarts;
+    unsigned flags;
+    int pad;
+};
+
+// Finalisation performed by the last block of a reduction kernel.
+enum FinKind : int {
+    FIN_STORE = 0,     // out[r] = sum
+    FIN_ALPHA = 1,     // pAp -> alpha (or breakdown)
+    FIN_CG = 2,        // |r|^2 -> beta, convergence / cap (plain CG)
+    FIN_MIXED = 3,     // |r|^2 -> beta, update / stall triggers (mixed CG)
+    FIN_TRUE = 4,      // rr_true = sum
+    FIN_INIT = 5,      // bb = sum; start state of a solve from x = 0
+    FIN_RU_END = 6,    // state after a reliable / group-wise update (mixed CG)
+    FIN_CG_CHECK = 7,  // accept or restart after a true-residual check (plain CG)
+};
+
+struct Reduce {
+    double* partials;   // [nrhs][nparts]
+    unsigned* counter;  // zero between launches (the last block resets it)
+    RhsState* st;       // [nrhs]
+    double* out;        // FIN_STORE destination [nrhs]
+    int kind;
+    int nparts;
+};
+
+}  // namespace stag

@@ -1,0 +1,231 @@
+// Hop kernel: the staggered Dirac operator of Eq.5 (with the phases of Sec.2
+// folded into the links) applied from one parity to the other, with optional
+// second-stage epilogues that complete A = m^2 - D_eo D_oe (Eq.3).
+//
+// One output site is handled by S lanes of a wavefront (S = 1, 2 or 4); lane
+// j of a site takes the hop pairs mu in [j*4/S, (j+1)*4/S), each pair being a
+// forward and a backward hop whose two 3x3 links are stored contiguously per
+// site. The S partial colour vectors are summed with cross-lane adds. With
+// N > 1 right-hand sides every link is loaded once and applied to all of
+// them (the block operator sharing gauge loads).
+//
+// This file is compiled once per storage precision (HOP_PREC).
+#include "kern.h"
+#include "launch.h"
+
+#ifndef HOP_PREC
+#error "HOP_PREC must be defined"
+#endif
+
+namespace stag {
+
+template <int P, int S, int N, int EPI, bool NT>
+__global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
+    using T = typename Real<P>::T;
+    const uint32_t blk = logical_block(a.swizzle);
+    const uint32_t gt = blk * kBlock + threadIdx.x;
+    const uint32_t s = gt / S;
+    const int j = (int)(gt % S);
+    const uint32_t Vh = a.g.Vh;
+
+    unsigned act = 0;
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+        if (!a.st || (a.st[r].flags & a.run_mask)) act |= 1u << r;
+
+    T ar[N][3], ai[N][3];
+    [[maybe_unused]] T hr2[N][3], hi2[N][3];  // S = 1: sum of pairs 2 and 3 in progress
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ar[r][c] = ai[r][c] = hr2[r][c] = hi2[r][c] = T(0);
+
+    const bool valid = s < Vh;
+    if (valid && act) {
+        int x, y, z, t;
+        site_coords(a.g, s, a.p_out, x, y, z, t);
+        // Each hop pair mu contributes p_mu = F_mu chi(x+mu) + B_mu chi(x-mu),
+        // accumulated from zero; the pairs are combined as
+        // (p0 + p1) + (p2 + p3), lane-locally for the pairs this lane owns
+        // and across the S lanes of the site below. This fixes the rounding
+        // independently of S and of the number of right-hand sides.
+#pragma unroll
+        for (int k = 0; k < 4 / S; ++k) {
+            const int mu = j * (4 / S) + k;
+            uint32_t nf, nb;
+            neighbours(a.g, s, x, y, z, t, mu, nf, nb);
+            T lr[18], li[18];
+            load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, lr, li);
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                if (!((act >> r) & 1u)) continue;
+                const char* in_r = (const char*)a.in + (size_t)r * a.in_rs;
+                T vr[3], vi[3], pr[3] = {T(0), T(0), T(0)}, pi[3] = {T(0), T(0), T(0)};
+                load_site<P>(in_r, Vh, nf, vr, vi);
+                matvec_acc(lr, li, 0, vr, vi, pr, pi);
+                load_site<P>(in_r, Vh, nb, vr, vi);
+                matvec_acc(lr, li, 9, vr, vi, pr, pi);
+                if constexpr (S == 1) {
+                    // k = 0, 2 start a pair sum; k = 1, 3 complete it;
+                    // k = 3 also adds the two pair sums
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        if (k == 0) {
+                            ar[r][c] = pr[c];
+                            ai[r][c] = pi[c];
+                        } else if (k == 1) {
+                            ar[r][c] = ar[r][c] + pr[c];
+                            ai[r][c] = ai[r][c] + pi[c];
+                        } else if (k == 2) {
+                            hr2[r][c] = pr[c];
+                            hi2[r][c] = pi[c];
+                        } else {
+                            ar[r][c] = ar[r][c] + (hr2[r][c] + pr[c]);
+                            ai[r][c] = ai[r][c] + (hi2[r][c] + pi[c]);
+                        }
+                    }
+                } else if constexpr (S == 2) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        if (k == 0) {
+                            ar[r][c] = pr[c];
+                            ai[r][c] = pi[c];
+                        } else {
+                            ar[r][c] = ar[r][c] + pr[c];
+                            ai[r][c] = ai[r][c] + pi[c];
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        ar[r][c] = pr[c];
+                        ai[r][c] = pi[c];
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (S > 1) {
+        // lanes 2i and 2i + 1 hold consecutive pair sums; xor 1 forms
+        // (p0 + p1) and (p2 + p3), xor 2 adds them. IEEE addition is
+        // commutative, so both lanes of each exchange hold the same value.
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int off = 1; off < S; off <<= 1) {
+                    ar[r][c] = ar[r][c] + __shfl_xor(ar[r][c], off, 64);
+                    ai[r][c] = ai[r][c] + __shfl_xor(ai[r][c], off, 64);
+                }
+    }
+
+    double dv[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) dv[r] = 0.0;
+
+    if (valid && j == 0) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            if (!((act >> r) & 1u)) continue;
+            char* out_r = (char*)a.out + (size_t)r * a.out_rs;
+            if constexpr (EPI == EPI_PLAIN) {
+                store_site<P>(out_r, Vh, s, ar[r], ai[r]);
+            } else {
+                T xr[3], xi[3], hr[3], hi[3];
+                load_site<P>((const char*)a.x + (size_t)r * a.x_rs, Vh, s, xr, xi);
+                const T m2 = (T)(a.st ? a.st[r].m2 : a.m2[r]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    hr[c] = fma(m2, xr[c], -ar[r][c]);
+                    hi[c] = fma(m2, xi[c], -ai[r][c]);
+                }
+                if constexpr (EPI == EPI_RESID) {
+                    T br[3], bi[3];
+                    load_site<P>((const char*)a.b + (size_t)r * a.b_rs, Vh, s, br, bi);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        hr[c] = br[c] - hr[c];
+                        hi[c] = bi[c] - hi[c];
+                    }
+                    store_site<P>(out_r, Vh, s, hr, hi);
+                    double acc = 0.0;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        acc = fma((double)hr[c], (double)hr[c], acc);
+                        acc = fma((double)hi[c], (double)hi[c], acc);
+                    }
+                    dv[r] = acc;
+                } else {
+                    store_site<P>(out_r, Vh, s, hr, hi);
+                    if constexpr (EPI == EPI_XPAY_DOT) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            acc = fma((double)xr[c], (double)hr[c], acc);
+                            acc = fma((double)xi[c], (double)hi[c], acc);
+                        }
+                        dv[r] = acc;
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (EPI == EPI_XPAY_DOT || EPI == EPI_RESID) {
+        block_reduce_finalize<N, S>(dv, act, a.red, blk);
+    }
+}
+
+template <int P, int S, int N, int EPI, bool NT>
+static hipError_t run_hop(const HopArgs& a, hipStream_t stream) {
+    const uint32_t nb = hop_blocks(a.g.Vh, S);
+    hipLaunchKernelGGL((k_hop<P, S, N, EPI, NT>), dim3(nb), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+// Dispatch for this precision: N = 1 with S in {1, 2, 4} and both load
+// flavours; N > 1 with S = 1 and non-temporal link loads.
+template <int P, int EPI>
+static hipError_t dispatch_epi(int S, int N, bool nt, const HopArgs& a, hipStream_t st) {
+    if (N == 1) {
+        if (nt) {
+            if (S == 1) return run_hop<P, 1, 1, EPI, true>(a, st);
+            if (S == 2) return run_hop<P, 2, 1, EPI, true>(a, st);
+            if (S == 4) return run_hop<P, 4, 1, EPI, true>(a, st);
+        } else {
+            if (S == 1) return run_hop<P, 1, 1, EPI, false>(a, st);
+            if (S == 2) return run_hop<P, 2, 1, EPI, false>(a, st);
+            if (S == 4) return run_hop<P, 4, 1, EPI, false>(a, st);
+        }
+        return hipErrorInvalidValue;
+    }
+    if (S != 1) return hipErrorInvalidValue;
+    switch (N) {
+        case 2: return run_hop<P, 1, 2, EPI, true>(a, st);
+        case 4: return run_hop<P, 1, 4, EPI, true>(a, st);
+        case 8: return run_hop<P, 1, 8, EPI, true>(a, st);
+        case 12: return run_hop<P, 1, 12, EPI, true>(a, st);
+        case 16: return run_hop<P, 1, 16, EPI, true>(a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+
+#define HOP_FN_NAME_(p) launch_hop_p##p
+#define HOP_FN_NAME(p) HOP_FN_NAME_(p)
+
+hipError_t HOP_FN_NAME(HOP_PREC)(int S, int N, int epi, bool nt, const HopArgs& a,
+                                  hipStream_t st) {
+    constexpr int P = HOP_PREC;
+    switch (epi) {
+        case EPI_PLAIN: return dispatch_epi<P, EPI_PLAIN>(S, N, nt, a, st);
+        case EPI_XPAY: return dispatch_epi<P, EPI_XPAY>(S, N, nt, a, st);
+        case EPI_XPAY_DOT: return dispatch_epi<P, EPI_XPAY_DOT>(S, N, nt, a, st);
+        case EPI_RESID:
+            if constexpr (P == P64) return dispatch_epi<P, EPI_RESID>(S, N, nt, a, st);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace stag

@@ -1,0 +1,165 @@
+// Host-side objects of libstag (context, gauge, field, solver engine).
+#pragma once
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdarg>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/stag.h"
+#include "launch.h"
+
+namespace stag {
+
+struct Serve;  // serving loop (serve.cpp)
+
+// Launch shape of the two hop stages for one (precision, block size) pair.
+struct HopTune {
+    int S1 = 1, S2 = 1;  // lanes per site of stage 1 (D_oe) and stage 2 (D_eo + xpay)
+    int nt = 1;          // non-temporal link loads
+    int swizzle = 1;     // XCD-aware block order
+};
+
+}  // namespace stag
+
+namespace stag {
+// Per-kernel-kind timing collected with HIP events on the launch stream.
+enum KernelKind : int {
+    KK_HOP1 = 0,      // inner-precision hop, stage 1 (D_oe)
+    KK_HOP2 = 1,      // inner-precision hop, stage 2 (D_eo + xpay + dot)
+    KK_HOP1_64 = 2,   // fp64 hop stage 1 of a true-residual recompute
+    KK_HOP2_64 = 3,   // fp64 hop stage 2 of a true-residual recompute
+    KK_UPDATE = 4,    // fused axpy + norm
+    KK_XPAY = 5,      // direction update
+    KK_OTHER = 6,
+    KK_COUNT = 7,
+};
+struct Timing {
+    bool on = false;
+    bool no_graph_events = false;  // the runtime refused event nodes in a capture
+    long long count[KK_COUNT] = {0};
+    double ms[KK_COUNT] = {0};
+    std::vector<hipEvent_t> pool;
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::mutex mu;
+};
+}  // namespace stag
+
+struct stag_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t budget = 0;
+    std::atomic<size_t> used{0};
+    std::mutex mu;                 // guards the object lists and the workspace pool
+    std::string err;
+    std::mutex err_mu;
+    std::vector<stag_gauge*> gauges;
+    std::vector<stag_field*> fields;
+    std::vector<struct stag_engine*> engines;
+    std::map<long long, stag::HopTune> tune;  // key: (prec, N, Vh bucket)
+    std::mutex tune_mu;
+    stag::Serve* serve = nullptr;
+    stag::Timing timing;
+};
+
+struct stag_gauge {
+    stag_ctx* ctx = nullptr;
+    int L[4] = {0, 0, 0, 0};
+    stag::Geom g{};
+    int mask = 0;
+    void* G[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+    float* gscale[2] = {nullptr, nullptr};  // P16S
+    size_t bytes = 0;
+};
+
+struct stag_field {
+    stag_ctx* ctx = nullptr;
+    const stag_gauge* gauge = nullptr;
+    int parity = 0, prec = 0, nrhs = 0;
+    void* data = nullptr;
+    size_t rs = 0;  // bytes per right-hand side
+};
+
+// Solver workspace + device state for one (gauge, inner precision, N) shape.
+struct stag_engine {
+    stag_ctx* ctx = nullptr;
+    const stag_gauge* gauge = nullptr;
+    int prec = 0;  // inner precision (P64 = plain CG)
+    int N = 1;
+    bool in_use = false;
+    uint32_t Vh = 0;
+    // fp64 vectors [N]
+    void *x64 = nullptr, *r64 = nullptr, *t64 = nullptr, *d64 = nullptr, *Ad64 = nullptr;
+    // low-precision vectors [N]
+    void *y32 = nullptr, *rs = nullptr, *d = nullptr, *t = nullptr, *Ad = nullptr;
+    size_t rs64 = 0, rsP = 0, rs32 = 0;
+    stag::RhsState* st = nullptr;    // device [N]
+    stag::RhsState* host[2] = {nullptr, nullptr};  // pinned poll buffers
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    double* partials = nullptr;
+    unsigned* counter = nullptr;
+    size_t bytes = 0;
+    // One graph of K iterations, or two alternating instances when the
+    // solve is timed (each with its own event-record nodes, read back after
+    // its replay completed and before it is launched again).
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    std::vector<stag::Timing::Rec> gev[2];
+    int graph_k = 0;
+    int graph_n = 0;
+    stag::HopTune tune_lo, tune_64;
+};
+
+namespace stag {
+
+int set_error(stag_ctx* ctx, int code, const char* fmt, ...);
+int dev_alloc(stag_ctx* ctx, size_t bytes, void** p);
+void dev_free(stag_ctx* ctx, void* p, size_t bytes);
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+Geom make_geom(const int L[4]);
+HopTune get_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh);
+void set_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh, const HopTune& t);
+
+// Engines (solver.cpp)
+int engine_acquire(stag_ctx* ctx, const stag_gauge* g, int prec, int N, stag_engine** out);
+void engine_release(stag_engine* e);
+void engine_destroy(stag_engine* e);
+void engine_drop_graphs(stag_engine* e);
+
+// One whole solve of n <= N right-hand sides held in canonical device
+// buffers b_dev / x_dev (complex128 [n][Vh][3]) or fields.
+int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, size_t b_rs,
+                 void* x64_out, size_t x_rs, const stag_cg_params& p, stag_cg_stats* stats,
+                 hipStream_t stream);
+
+// Event timing helpers (no-ops when timing is off).
+hipError_t timing_begin(stag_ctx* ctx, hipStream_t s, hipEvent_t* ev);
+hipError_t timing_end(stag_ctx* ctx, hipStream_t s, int kind, hipEvent_t start);
+void timing_collect(stag_ctx* ctx);  // accumulate every completed record
+
+hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, const HopTune& t,
+                       const void* in, size_t in_rs, void* out, size_t out_rs, int p_out,
+                       const void* x, size_t x_rs, const void* b, size_t b_rs, const double* m2,
+                       RhsState* st, unsigned run_mask, const Reduce* red, hipStream_t stream);
+
+}  // namespace stag

@@ -1,0 +1,433 @@
+// Device helpers for the libstag kernels: storage codecs per precision,
+// coalesced loads, deterministic block reductions with a last-block
+// finalisation of the CG scalars.
+#pragma once
+
+#include "common.h"
+#include "launch.h"
+
+// Contractions are written out as fma() where wanted; no implicit ones, so
+// every instantiation of a kernel rounds identically.
+#pragma clang fp contract(off)
+
+namespace stag {
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+
+template <bool NT, typename T>
+__device__ __forceinline__ T ldg(const T* p) {
+    if constexpr (NT) {
+        return __builtin_nontemporal_load(p);
+    } else {
+        return *p;
+    }
+}
+
+template <int P>
+struct Real {
+    using T = float;
+};
+template <>
+struct Real<P64> {
+    using T = double;
+};
+
+// ------------------------------------------------------------------ fp16 + scale
+
+__device__ __forceinline__ float h2f_lo(unsigned w) {
+    return __half2float(__ushort_as_half((unsigned short)(w & 0xffffu)));
+}
+__device__ __forceinline__ float h2f_hi(unsigned w) {
+    return __half2float(__ushort_as_half((unsigned short)(w >> 16)));
+}
+__device__ __forceinline__ unsigned f2h_pair(float lo, float hi) {
+    unsigned a = __half_as_ushort(__float2half_rn(lo));
+    unsigned b = __half_as_ushort(__float2half_rn(hi));
+    return a | (b << 16);
+}
+
+// Encode one site (three complex colours) to the 16-byte record; the values
+// are replaced by what the record decodes to (so norms see stored values).
+__device__ __forceinline__ u4v f16s_encode(float (&re)[3], float (&im)[3]) {
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s = fmaxf(s, fmaxf(fabsf(re[c]), fabsf(im[c])));
+    u4v w;
+    if (s == 0.f) {
+        w.x = w.y = w.z = 0u;
+        w.w = 0u;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) re[c] = im[c] = 0.f;
+        return w;
+    }
+    unsigned q[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        q[c] = f2h_pair(__fdiv_rn(re[c], s), __fdiv_rn(im[c], s));
+        re[c] = h2f_lo(q[c]) * s;
+        im[c] = h2f_hi(q[c]) * s;
+    }
+    w.x = q[0];
+    w.y = q[1];
+    w.z = q[2];
+    w.w = __float_as_uint(s);
+    return w;
+}
+
+__device__ __forceinline__ void f16s_decode(u4v w, float (&re)[3], float (&im)[3]) {
+    float s = __uint_as_float(w.w);
+    re[0] = h2f_lo(w.x) * s;
+    im[0] = h2f_hi(w.x) * s;
+    re[1] = h2f_lo(w.y) * s;
+    im[1] = h2f_hi(w.y) * s;
+    re[2] = h2f_lo(w.z) * s;
+    im[2] = h2f_hi(w.z) * s;
+}
+
+// ------------------------------------------------------------------ spinor access
+
+// Load the colour vector of site s from one right-hand side block.
+template <int P, bool NT = false>
+__device__ __forceinline__ void load_site(const void* f, uint32_t Vh, uint32_t s,
+                                          typename Real<P>::T (&re)[3],
+                                          typename Real<P>::T (&im)[3]) {
+    if constexpr (P == P64) {
+        const d2v* p = (const d2v*)f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            d2v v = ldg<NT>(p + (size_t)c * Vh + s);
+            re[c] = v.x;
+            im[c] = v.y;
+        }
+    } else if constexpr (P == P32) {
+        const f2v* p = (const f2v*)f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            f2v v = ldg<NT>(p + (size_t)c * Vh + s);
+            re[c] = v.x;
+            im[c] = v.y;
+        }
+    } else {
+        u4v w = ldg<NT>((const u4v*)f + s);
+        f16s_decode(w, re, im);
+    }
+}
+
+// Store (rounding to the storage precision); re/im are replaced by the
+// stored values.
+template <int P>
+__device__ __forceinline__ void store_site(void* f, uint32_t Vh, uint32_t s,
+                                           typename Real<P>::T (&re)[3],
+                                           typename Real<P>::T (&im)[3]) {
+    if constexpr (P == P64) {
+        d2v* p = (d2v*)f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            d2v v;
+            v.x = re[c];
+            v.y = im[c];
+            p[(size_t)c * Vh + s] = v;
+        }
+    } else if constexpr (P == P32) {
+        f2v* p = (f2v*)f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            f2v v;
+            v.x = re[c];
+            v.y = im[c];
+            p[(size_t)c * Vh + s] = v;
+        }
+    } else {
+        ((u4v*)f)[s] = f16s_encode(re, im);
+    }
+}
+
+// ------------------------------------------------------------------ gauge access
+
+// Load the 18 complex entries of hop pair mu (forward link then backward
+// link, each row-major) of output site s.
+template <int P, bool NT>
+__device__ __forceinline__ void load_pair(const void* G, const float* gscale, uint32_t Vh,
+                                          uint32_t s, int mu, typename Real<P>::T (&lr)[18],
+                                          typename Real<P>::T (&li)[18]) {
+    if constexpr (P == P64) {
+        const d2v* g = (const d2v*)G + (size_t)(18 * mu) * Vh + s;
+#pragma unroll
+        for (int e = 0; e < 18; ++e) {
+            d2v v = ldg<NT>(g + (size_t)e * Vh);
+            lr[e] = v.x;
+            li[e] = v.y;
+        }
+    } else if constexpr (P == P32) {
+        const f4v* g = (const f4v*)G + (size_t)(9 * mu) * Vh + s;
+#pragma unroll
+        for (int w = 0; w < 9; ++w) {
+            f4v v = ldg<NT>(g + (size_t)w * Vh);
+            lr[2 * w] = v.x;
+            li[2 * w] = v.y;
+            lr[2 * w + 1] = v.z;
+            li[2 * w + 1] = v.w;
+        }
+    } else {
+        const u2v* g = (const u2v*)G + (size_t)(9 * mu) * Vh + s;
+        float sc = gscale[s];
+#pragma unroll
+        for (int w = 0; w < 9; ++w) {
+            u2v v = ldg<NT>(g + (size_t)w * Vh);
+            lr[2 * w] = h2f_lo(v.x) * sc;
+            li[2 * w] = h2f_hi(v.x) * sc;
+            lr[2 * w + 1] = h2f_lo(v.y) * sc;
+            li[2 * w + 1] = h2f_hi(v.y) * sc;
+        }
+    }
+}
+
+// acc += L v for the 3x3 complex matrix starting at entry `o` of (lr, li).
+template <typename T>
+__device__ __forceinline__ void matvec_acc(const T (&lr)[18], const T (&li)[18], int o,
+                                           const T (&vr)[3], const T (&vi)[3], T (&ar)[3],
+                                           T (&ai)[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const T ur = lr[o + 3 * a + b], ui = li[o + 3 * a + b];
+            ar[a] = fma(ur, vr[b], ar[a]);
+            ar[a] = fma(-ui, vi[b], ar[a]);
+            ai[a] = fma(ur, vi[b], ai[a]);
+            ai[a] = fma(ui, vr[b], ai[a]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launch geometry
+
+// Map the hardware block index to a logical tile so that each of the eight
+// XCDs (which receive blocks round-robin) works on one contiguous eighth of
+// the sites; neighbouring tiles then share that XCD's L2.
+__device__ __forceinline__ uint32_t logical_block(int swizzle) {
+    const uint32_t k = blockIdx.x, nb = gridDim.x;
+    if (!swizzle || nb < 16) return k;
+    const uint32_t q = nb >> 3, rem = nb & 7, x = k & 7, i = k >> 3;
+    return x * q + (x < rem ? x : rem) + i;
+}
+
+// ------------------------------------------------------------------ reductions
+
+// Per-RHS finalisation of a reduced sum (run by one thread).
+__device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum, double* out) {
+    if (kind == FIN_STORE) {
+        if (out) *out = sum;
+        return;
+    }
+    RhsState& s = *sp;
+    switch (kind) {
+        case FIN_ALPHA:
+            s.pAp = sum;
+            if (!(sum > 0.0) || !isfinite(sum)) {
+                s.flags = F_BREAKDOWN;
+            } else {
+                s.alpha = s.rr / sum;
+            }
+            break;
+        case FIN_CG: {
+            s.rr_old = s.rr;
+            s.rr = sum;
+            s.iters += 1;
+            s.beta = sum / s.rr_old;
+            if (!isfinite(sum)) {
+                s.flags = F_BREAKDOWN;
+            } else if (sum <= s.rr_stop) {
+                s.flags = F_CONV;
+            } else if (s.iters >= s.max_iter) {
+                s.flags = F_CONV | F_MAXIT;
+            }
+            break;
+        }
+        case FIN_MIXED: {
+            s.rr_old = s.rr;
+            s.rr = sum;
+            s.iters += 1;
+            s.beta = sum / s.rr_old;
+            const double rn = sqrt(sum);
+            s.rmax = fmax(s.rmax, rn);
+            if (rn < s.rmin) {
+                s.rmin = rn;
+                s.since = 0;
+            } else {
+                s.since += 1;
+            }
+            if (!isfinite(sum)) {
+                s.flags = F_BREAKDOWN;
+            } else if (rn < s.delta * s.rmax || sum <= s.rr_stop) {
+                s.flags = F_RU;
+            } else if (s.since >= s.stall_iters) {
+                s.flags = F_STALL;
+            } else if (s.iters >= s.max_iter) {
+                s.flags = F_RU | F_MAXIT;
+            }
+            break;
+        }
+        case FIN_TRUE:
+            s.rr_true = sum;
+            break;
+        case FIN_INIT:
+            s.bb = sum;
+            s.rr_stop = s.tol2 * sum;
+            s.rr = s.rr_old = s.rr_true = s.best_true = sum;
+            s.rmax = s.rmin = sqrt(sum);
+            s.since = 0;
+            if (!isfinite(sum)) {
+                s.flags = F_BADINPUT;
+            } else if (sum == 0.0 || sum <= s.rr_stop) {
+                s.flags = F_DONE;
+            } else {
+                s.flags = F_ACTIVE;
+            }
+            break;
+        case FIN_RU_END: {
+            const double rt = s.rr_true;
+            const bool stall = (s.flags & F_STALL) != 0;
+            s.updates += 1;
+            if (!isfinite(rt)) {
+                s.flags = F_BREAKDOWN;
+                break;
+            }
+            if (rt <= s.rr_stop) {
+                s.rr = rt;
+                s.flags = F_DONE;
+                break;
+            }
+            if (s.flags & F_MAXIT) {
+                s.rr = rt;
+                s.flags = F_MAXIT;
+                break;
+            }
+            if (stall) {
+                s.restarts += 1;
+                if (rt < 0.25 * s.best_true) {
+                    s.stall_count = 0;
+                } else {
+                    s.stall_count += 1;
+                }
+            }
+            s.best_true = fmin(s.best_true, rt);
+            if (stall && s.stall_count >= s.max_stall) {
+                s.rr = rt;
+                s.flags = F_ESTALL;
+                break;
+            }
+            s.rr = rt;
+            s.rmax = s.rmin = sqrt(rt);
+            s.since = 0;
+            s.flags = F_ACTIVE;
+            break;
+        }
+        case FIN_CG_CHECK: {
+            const double rt = s.rr_true;
+            s.updates += 1;
+            if (!isfinite(rt)) {
+                s.flags = F_BREAKDOWN;
+            } else if (rt <= s.rr_stop) {
+                s.flags = F_DONE;
+            } else if (s.flags & F_MAXIT) {
+                s.flags = F_MAXIT;
+            } else {
+                s.rr = rt;
+                s.restarts += 1;
+                s.flags = F_ACTIVE;
+            }
+            break;
+        }
+        default:
+            break;
+    }
+}
+
+// Reduction partials are taken over fixed chunks of 64 consecutive sites,
+// whatever the launch shape, and each chunk is summed by the same butterfly
+// over the site index; the last block to finish then sums the chunk
+// partials in index order. The result is therefore independent of how many
+// lanes serve a site and of how many right-hand sides share the kernel.
+constexpr int kChunk = 64;
+
+// v[r] is the value of the site handled by this thread (meaningful on the
+// first lane of each site, i.e. threadIdx.x % S == 0); the block covers
+// kBlock / S consecutive sites starting at blk * (kBlock / S). `act` has bit
+// r set for the RHS the kernel processed (uniform over the grid). Every
+// block must call this.
+template <int N, int S>
+__device__ __forceinline__ void block_reduce_finalize(double (&v)[N], unsigned act,
+                                                      const Reduce& R, uint32_t blk) {
+    constexpr int SPB = kBlock / S;          // sites per block
+    constexpr int CPB = SPB / kChunk;        // chunks per block (>= 1)
+    __shared__ double sv[N][SPB];
+    __shared__ double red[16];
+    __shared__ bool last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if constexpr (S == 1) {
+        // one wave is one chunk: reduce straight from registers
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            double x = v[r];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+            const uint32_t ch = blk * CPB + wave;
+            if (lane == 0 && ch < (uint32_t)R.nparts) R.partials[(size_t)r * R.nparts + ch] = x;
+        }
+    } else {
+        if (threadIdx.x % S == 0) {
+#pragma unroll
+            for (int r = 0; r < N; ++r) sv[r][threadIdx.x / S] = v[r];
+        }
+        __syncthreads();
+        if (wave < CPB) {
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                double x = sv[r][wave * kChunk + lane];
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+                const uint32_t ch = blk * CPB + wave;
+                if (lane == 0 && ch < (uint32_t)R.nparts) R.partials[(size_t)r * R.nparts + ch] = x;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned total = gridDim.x * gridDim.y;
+        const unsigned prev = atomicAdd(R.counter, 1u);
+        last = (prev == total - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // fixed-order final sum: thread i takes parts i, i + B, i + 2B, ...
+    constexpr int B = kBlock, NW = kBlock / 64;
+    for (int r = 0; r < N; ++r) {
+        if (!((act >> r) & 1u)) continue;
+        const volatile double* pp = R.partials + (size_t)r * R.nparts;
+        double x = 0.0;
+        for (int i = threadIdx.x; i < R.nparts; i += B) x += pp[i];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) red[wave] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < NW; ++w) t += red[w];
+            finalize_one(R.kind, R.st ? R.st + r : nullptr, t, R.out ? R.out + r : nullptr);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicExch(R.counter, 0u);
+    }
+}
+
+}  // namespace stag

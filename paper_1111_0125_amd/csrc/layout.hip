@@ -1,0 +1,176 @@
+// Layout kernels: canonical complex128 host layouts <-> internal storage.
+//
+// Gauge packing folds the staggered phases into the links (Sec.2: the phase
+// eta_mu(x) is multiplied into U_mu in advance), builds the eight hop links
+// of every output site (backward links daggered and negated, so the Dirac
+// operator of Eq.5 becomes a plain sum), splits by parity and writes the
+// word-major layout of common.h, rounding to the storage precision.
+#include "kern.h"
+#include "launch.h"
+
+namespace stag {
+
+__device__ __forceinline__ double eta_of(int mu, int x, int y, int z) {
+    // eta_mu(x) = (-1)^(x_0 + ... + x_{mu-1})
+    int s = 0;
+    if (mu > 0) s += x;
+    if (mu > 1) s += y;
+    if (mu > 2) s += z;
+    return (s & 1) ? -1.0 : 1.0;
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_gauge_pack(const d2v* __restrict__ U, void* G,
+                                                       float* gscale, Geom g, int p_out) {
+    const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= g.Vh) return;
+    int c[4];
+    site_coords(g, s, p_out, c[0], c[1], c[2], c[3]);
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];
+    auto lex_of = [&](const int* q) -> size_t {
+        return (size_t)q[0] + (size_t)Lx * ((size_t)q[1] + (size_t)Ly * ((size_t)q[2] + (size_t)Lz * q[3]));
+    };
+    // gather the 8 hop links (72 complex) in fp64
+    double lr[72], li[72];
+    const size_t lex = lex_of(c);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        int b[4] = {c[0], c[1], c[2], c[3]};
+        b[mu] = (b[mu] == 0) ? g.L[mu] - 1 : b[mu] - 1;
+        const double ef = eta_of(mu, c[0], c[1], c[2]);
+        const double eb = eta_of(mu, b[0], b[1], b[2]);
+        const d2v* uf = U + (lex * 4 + mu) * 9;
+        const d2v* ub = U + (lex_of(b) * 4 + mu) * 9;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const d2v f = uf[i * 3 + k];
+                lr[18 * mu + 3 * i + k] = ef * f.x;
+                li[18 * mu + 3 * i + k] = ef * f.y;
+                // -(eb U)^dagger: entry (i, k) = -eb conj(U[k][i])
+                const d2v v = ub[k * 3 + i];
+                lr[18 * mu + 9 + 3 * i + k] = -eb * v.x;
+                li[18 * mu + 9 + 3 * i + k] = eb * v.y;
+            }
+    }
+    const size_t Vh = g.Vh;
+    if constexpr (P == P64) {
+        d2v* o = (d2v*)G;
+#pragma unroll
+        for (int e = 0; e < 72; ++e) {
+            d2v v;
+            v.x = lr[e];
+            v.y = li[e];
+            o[(size_t)e * Vh + s] = v;
+        }
+    } else if constexpr (P == P32) {
+        f4v* o = (f4v*)G;
+#pragma unroll
+        for (int w = 0; w < 36; ++w) {
+            f4v v;
+            v.x = (float)lr[2 * w];
+            v.y = (float)li[2 * w];
+            v.z = (float)lr[2 * w + 1];
+            v.w = (float)li[2 * w + 1];
+            o[(size_t)w * Vh + s] = v;
+        }
+    } else {
+        // one fp32 scale per output site over the 144 reals it reads
+        float sc = 0.f;
+#pragma unroll
+        for (int e = 0; e < 72; ++e) sc = fmaxf(sc, fmaxf(fabsf((float)lr[e]), fabsf((float)li[e])));
+        gscale[s] = sc;
+        u2v* o = (u2v*)G;
+#pragma unroll
+        for (int w = 0; w < 36; ++w) {
+            u2v v;
+            if (sc == 0.f) {
+                v.x = v.y = 0u;
+            } else {
+                v.x = f2h_pair(__fdiv_rn((float)lr[2 * w], sc), __fdiv_rn((float)li[2 * w], sc));
+                v.y = f2h_pair(__fdiv_rn((float)lr[2 * w + 1], sc), __fdiv_rn((float)li[2 * w + 1], sc));
+            }
+            o[(size_t)w * Vh + s] = v;
+        }
+    }
+}
+
+hipError_t launch_gauge_pack(int prec, const void* U_dev, void* G, float* gscale, const Geom& g,
+                             int p_out, hipStream_t st) {
+    const dim3 grid((g.Vh + kBlock - 1) / kBlock), block(kBlock);
+    const d2v* U = (const d2v*)U_dev;
+    switch (prec) {
+        case P64: hipLaunchKernelGGL((k_gauge_pack<P64>), grid, block, 0, st, U, G, gscale, g, p_out); break;
+        case P32: hipLaunchKernelGGL((k_gauge_pack<P32>), grid, block, 0, st, U, G, gscale, g, p_out); break;
+        case P16S: hipLaunchKernelGGL((k_gauge_pack<P16S>), grid, block, 0, st, U, G, gscale, g, p_out); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Canonical spinors: complex128 [nrhs][Vh][3].
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_import(const d2v* __restrict__ src, void* dst,
+                                                   size_t dst_rs, uint32_t Vh) {
+    using T = typename Real<P>::T;
+    const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= Vh) return;
+    const d2v* p = src + ((size_t)r * Vh + s) * 3;
+    T re[3], im[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const d2v v = p[c];
+        re[c] = (T)v.x;
+        im[c] = (T)v.y;
+    }
+    store_site<P>((char*)dst + (size_t)r * dst_rs, Vh, s, re, im);
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_export(const void* src, size_t src_rs, d2v* dst,
+                                                   uint32_t Vh) {
+    using T = typename Real<P>::T;
+    const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= Vh) return;
+    T re[3], im[3];
+    load_site<P>((const char*)src + (size_t)r * src_rs, Vh, s, re, im);
+    d2v* p = dst + ((size_t)r * Vh + s) * 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        d2v v;
+        v.x = (double)re[c];
+        v.y = (double)im[c];
+        p[c] = v;
+    }
+}
+
+hipError_t launch_import(int prec, const void* src_dev, void* dst, size_t dst_rs, uint32_t Vh,
+                         int nrhs, hipStream_t st) {
+    const dim3 grid((Vh + kBlock - 1) / kBlock, nrhs), block(kBlock);
+    const d2v* src = (const d2v*)src_dev;
+    switch (prec) {
+        case P64: hipLaunchKernelGGL((k_import<P64>), grid, block, 0, st, src, dst, dst_rs, Vh); break;
+        case P32: hipLaunchKernelGGL((k_import<P32>), grid, block, 0, st, src, dst, dst_rs, Vh); break;
+        case P16S: hipLaunchKernelGGL((k_import<P16S>), grid, block, 0, st, src, dst, dst_rs, Vh); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_export(int prec, const void* src, size_t src_rs, void* dst_dev, uint32_t Vh,
+                         int nrhs, hipStream_t st) {
+    const dim3 grid((Vh + kBlock - 1) / kBlock, nrhs), block(kBlock);
+    d2v* dst = (d2v*)dst_dev;
+    switch (prec) {
+        case P64: hipLaunchKernelGGL((k_export<P64>), grid, block, 0, st, src, src_rs, dst, Vh); break;
+        case P32: hipLaunchKernelGGL((k_export<P32>), grid, block, 0, st, src, src_rs, dst, Vh); break;
+        case P16S: hipLaunchKernelGGL((k_export<P16S>), grid, block, 0, st, src, src_rs, dst, Vh); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace stag

@@ -1,0 +1,59 @@
+"""CPU checks of the C-ABI boundary: the library loads, exports every symbol
+include/stag.h declares, and rejects bad arguments on the host before any
+device work (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stag.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(stag_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_boundary_calls():
+    names = declared_functions()
+    for must in ("stag_dslash", "stag_apply_A", "stag_cg_solve"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1111_0125_amd as s
+    missing = [n for n in declared_functions() if not hasattr(s.lib, n)]
+    assert not missing, missing
+
+
+def test_null_and_bad_arguments_rejected_on_host():
+    import paper_1111_0125_amd as s
+    lib = s.lib
+    assert lib.stag_version() >= 10000
+    assert lib.stag_create(0, 0, None) == s.STAG_EINVAL
+    assert lib.stag_destroy(None) == s.STAG_OK
+    assert lib.stag_gauge_create(None, None, None, 0, 1, None) == s.STAG_EINVAL
+    assert lib.stag_field_create(None, None, 0, 0, 1, None) == s.STAG_EINVAL
+    assert lib.stag_field_import(None, None, 0, None) == s.STAG_EINVAL
+    assert lib.stag_dslash(None, None, None, None, None) == s.STAG_EINVAL
+    assert lib.stag_apply_A(None, None, None, None, None, None) == s.STAG_EINVAL
+    assert lib.stag_cg_solve(None, None, None, None, None, None, None, None) == s.STAG_EINVAL
+    assert isinstance(lib.stag_last_error(None), bytes)
+
+
+def test_create_without_gpu_fails_cleanly():
+    import paper_1111_0125_amd as s
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    h = ctypes.c_void_p()
+    rc = s.lib.stag_create(0, 0, ctypes.byref(h))
+    assert rc in (s.STAG_EDEVICE, s.STAG_EINVAL)
+    assert s.lib.stag_last_error(None)

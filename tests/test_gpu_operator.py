@@ -1,0 +1,176 @@
+"""GPU parity of the Dirac operator and of A against the CPU oracle, through
+the C ABI (Python binding)."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import stag as ostag
+from tests.gpu_common import links, log, oracle_apply_A, oracle_dslash, rel_max
+
+pytestmark = pytest.mark.gpu
+
+LATTICES = [(2, 2, 2, 2), (4, 4, 4, 4), (4, 6, 4, 8), (2, 4, 6, 8), (8, 8, 8, 8), (16, 16, 16, 8)]
+TOL = {"f64": 1e-12, "f32": 1e-6, "f16s": 1e-3}
+
+
+@pytest.fixture(scope="module")
+def stag():
+    import paper_1111_0125_amd as s
+    return s
+
+
+@pytest.fixture(scope="module")
+def ctx(stag):
+    c = stag.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("L", LATTICES)
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+def test_dslash_parity(stag, ctx, L, prec):
+    log("dslash", L, prec)
+    U = links(L, "haar", 3)
+    g = ctx.gauge(L, U, precisions=(prec,))
+    for p_in in (0, 1):
+        v = synth.gaussian_rhs(L, 2, 4 + p_in)
+        fi = ctx.field(g, p_in, prec, 2).load(v)
+        fo = ctx.field(g, 1 - p_in, prec, 2)
+        stag.stag_dslash(ctx, g, fi, fo)
+        got = fo.store()
+        ref = oracle_dslash(U, v, L, p_in)
+        err = rel_max(got, ref)
+        log("  p_in", p_in, "rel err", err)
+        assert err <= TOL[prec]
+        fi.destroy()
+        fo.destroy()
+    g.destroy()
+
+
+@pytest.mark.parametrize("L", LATTICES)
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+def test_apply_A_parity(stag, ctx, L, prec):
+    log("apply_A", L, prec)
+    U = links(L, "haar", 5)
+    g = ctx.gauge(L, U, precisions=(prec,))
+    nrhs = 3
+    masses = [0.1, 0.05, 0.3]
+    v = synth.gaussian_rhs(L, nrhs, 6)
+    fi = ctx.field(g, 0, prec, nrhs).load(v)
+    fo = ctx.field(g, 0, prec, nrhs)
+    stag.stag_apply_A(ctx, g, masses, fi, fo)
+    got = fo.store()
+    ref = oracle_apply_A(U, v, L, masses)
+    err = rel_max(got, ref)
+    log("  rel err", err)
+    assert err <= TOL[prec]
+    for f in (fi, fo):
+        f.destroy()
+    g.destroy()
+
+
+def test_free_field_eigenvector_f64(stag, ctx):
+    """A plane wave on the even sites of a free lattice (p and p + pi give
+    one even-site vector) is an eigenvector with eigenvalue m^2 + 4 sum sin^2 p."""
+    L, m = (8, 4, 6, 4), 0.2
+    g = ctx.gauge(L, synth.unit_links(L), precisions=("f64",))
+    n = (1, 3, 2, 1)
+    x, y, z, t = ostag.coords(L)
+    ph = 2 * np.pi * (n[0] * x / L[0] + n[1] * y / L[1] + n[2] * z / L[2] + n[3] * t / L[3])
+    wave = np.broadcast_to(np.exp(1j * ph), (L[3], L[2], L[1], L[0]))
+    full = np.stack([wave, 2 * wave, -wave], axis=-1)
+    v = ostag.from_full(full, L, 0)[None]
+    lam = m * m + 4 * sum(np.sin(2 * np.pi * n[k] / L[k]) ** 2 for k in range(4))
+    fi = ctx.field(g, 0, "f64", 1).load(v)
+    fo = ctx.field(g, 0, "f64", 1)
+    stag.stag_apply_A(ctx, g, [m], fi, fo)
+    assert rel_max(fo.store(), lam * v) <= 1e-12
+
+
+def test_f16s_import_export_bit_exact(stag, ctx):
+    """The fp16 + per-site scale encoder gives exactly the oracle quantiser's values."""
+    L = (4, 4, 4, 8)
+    g = ctx.gauge(L, links(L, "haar", 7), precisions=("f16s",))
+    v = synth.gaussian_rhs(L, 3, 8) * np.array([1.0, 1e-3, 1e4])[:, None, None]
+    v[1, 5] = 0.0  # a zero site encodes scale 0
+    f = ctx.field(g, 0, "f16s", 3).load(v)
+    got = f.store()
+    ref = ostag.q_f16s(v).astype(np.complex128)
+    assert np.array_equal(got, ref)
+    f32 = ctx.field(g, 0, "f32", 3).load(v)
+    assert np.array_equal(f32.store(), v.astype(np.complex64).astype(np.complex128))
+
+
+def test_gauge_covariance_on_gpu_output(stag, ctx):
+    L, m = (4, 6, 4, 8), 0.1
+    U = links(L, "haar", 9)
+    gfield = synth.random_gauge(L, 10)
+    Ug = synth.gauge_transform_links(U, gfield)
+    ge = gfield.reshape(-1, 3, 3)[ostag.parity(L).reshape(-1) == 0]
+    v = synth.gaussian_rhs(L, 1, 11)
+    gv = (ge @ v[0][..., None])[..., 0][None]
+    out = []
+    for UU, vv in ((U, v), (Ug, gv)):
+        g = ctx.gauge(L, UU, precisions=("f64",))
+        fi = ctx.field(g, 0, "f64", 1).load(vv)
+        fo = ctx.field(g, 0, "f64", 1)
+        stag.stag_apply_A(ctx, g, [m], fi, fo)
+        out.append(fo.store())
+    rot = (ge @ out[0][0][..., None])[..., 0]
+    assert rel_max(out[1][0], rot) <= 1e-12
+
+
+def test_hermiticity_on_gpu(stag, ctx):
+    L, m = (8, 8, 8, 8), 0.05
+    g = ctx.gauge(L, links(L, "haar", 12), precisions=("f64",))
+    v = synth.gaussian_rhs(L, 2, 13)
+    fi = ctx.field(g, 0, "f64", 2).load(v)
+    fo = ctx.field(g, 0, "f64", 2)
+    stag.stag_apply_A(ctx, g, [m, m], fi, fo)
+    Av = fo.store()
+    lhs = np.vdot(v[0].ravel(), Av[1].ravel())
+    rhs = np.conj(np.vdot(v[1].ravel(), Av[0].ravel()))
+    assert abs(lhs - rhs) / abs(lhs) < 1e-12
+
+
+@pytest.mark.parametrize("nrhs", [1, 2, 5, 12, 16])
+def test_block_operator_matches_single(stag, ctx, nrhs):
+    """The multi-RHS operator (shared link loads) equals single applications."""
+    L = (8, 4, 4, 8)
+    U = links(L, "haar", 14)
+    g = ctx.gauge(L, U, precisions=("f64", "f32"))
+    v = synth.gaussian_rhs(L, nrhs, 15)
+    masses = np.linspace(0.05, 0.5, nrhs)
+    for prec in ("f64", "f32"):
+        fi = ctx.field(g, 0, prec, nrhs).load(v)
+        fo = ctx.field(g, 0, prec, nrhs)
+        stag.stag_apply_A(ctx, g, masses, fi, fo)
+        blk = fo.store()
+        for r in range(nrhs):
+            si = ctx.field(g, 0, prec, 1).load(v[r:r + 1])
+            so = ctx.field(g, 0, prec, 1)
+            stag.stag_apply_A(ctx, g, [masses[r]], si, so)
+            assert rel_max(blk[r], so.store()[0]) <= (1e-14 if prec == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("name", ["c4_24x24x24x48", "c3_32x32x32x64"])
+def test_apply_A_full_size(stag, ctx, name):
+    """A at the full benchmark lattices against the C oracle, all precisions."""
+    cfg = synth.CONFIGS[name]
+    L = cfg["L"]
+    log("full-size A", name)
+    U = synth.config_links(name)
+    g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"))
+    v = synth.gaussian_rhs(L, 1, cfg["rhs_seed"])
+    ref = oracle_apply_A(U, v, L, cfg["mass"])
+    for prec in ("f64", "f32", "f16s"):
+        fi = ctx.field(g, 0, prec, 1).load(v)
+        fo = ctx.field(g, 0, prec, 1)
+        stag.stag_apply_A(ctx, g, [cfg["mass"]], fi, fo)
+        err = rel_max(fo.store(), ref)
+        log("  ", prec, err)
+        assert err <= TOL[prec]
+        fi.destroy()
+        fo.destroy()
+    g.destroy()
