@@ -203,6 +203,39 @@ int stag_cg_solve(stag_ctx* ctx, const stag_gauge* gauge, const double* mass,
                   stag_cg_stats* stats, void* stream);
 
 
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of solve requests (each a CG solve as in
+ * stag_cg_solve, Sec.2 Fig.1 / Sec.3.2). A scheduler thread of the context
+ * admits requests in arrival order into a batch per (gauge, inner
+ * precision) when the context's HBM budget allows (requests that do not fit
+ * wait), starts their right-hand sides in free slots between K-iteration
+ * blocks while other slots are mid-solve, and frees each slot when its
+ * right-hand side has finished. Batches of different gauges run on separate
+ * streams and overlap on the device. A right-hand side's result does not
+ * depend on what else is being solved.
+ *
+ * stag_solver_submit: copies b_host (complex128 [nrhs][Vh][3], even sites)
+ *   before returning; never waits for the GPU. mass > 0, 0 < tol < 1,
+ *   inner_prec STAG_F64 / STAG_F32 / STAG_F16S (the gauge must hold F64 and
+ *   that copy), 1 <= nrhs <= STAG_MAX_RHS. Thread-safe. Errors: EINVAL,
+ *   EBUSY (queue full).
+ * stag_solver_poll: STAG_PENDING until every right-hand side of the ticket
+ *   has finished; then writes x_host (complex128 [nrhs][Vh][3], may be NULL),
+ *   stats[nrhs] (may be NULL) and the submit-to-finish latency in seconds
+ *   (may be NULL), releases the ticket and returns STAG_OK or the first
+ *   failing per-RHS status. ENOTFOUND for an unknown or collected ticket.
+ *   Thread-safe.
+ * stag_solver_config: slots per batch (rounded up to 1, 2, 4, 8, 12 or 16),
+ *   iterations per block (<= 0: automatic) and queue capacity; only before
+ *   the first submit (EBUSY after).
+ * stag_destroy cancels pending tickets.
+ */
+int stag_solver_submit(stag_ctx* ctx, const stag_gauge* gauge, double mass, int nrhs,
+                       const double* b_host, double tol, int inner_prec, stag_ticket* out);
+int stag_solver_poll(stag_ctx* ctx, stag_ticket ticket, double* x_host, stag_cg_stats* stats,
+                     double* latency_s);
+int stag_solver_config(stag_ctx* ctx, int slots_per_batch, int graph_k, int queue_cap);
+
 /* ---------------------------------------------------------------- tuning
  * Launch shape of the two hop stages of A: S1 / S2 = lanes per output site
  * (1, 2 or 4) for stage 1 (D_oe) and stage 2 (D_eo with the m^2 update),
@@ -236,6 +269,15 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* gauge, int prec, int nrhs, stag_t
 #define STAG_K_XPAY 5     /* direction update d = r + beta d */
 #define STAG_K_OTHER 6
 int stag_timing_enable(stag_ctx* ctx, int on);
+/* stag_time_kernels: average duration in microseconds of the three kernels
+ * of one CG iteration exactly as stag_cg_solve launches them (same buffers,
+ * launch shape and arithmetic) for `prec` (STAG_F64: plain CG, else mixed)
+ * and nrhs right-hand sides: us[0] = D_oe stage (with the deferred direction
+ * update), us[1] = D_eo stage with m^2 update and <d, A d>, us[2] = fused
+ * update with |r|^2. Each is timed over `reps` back-to-back launches between
+ * two HIP events on the context's stream. Synchronous. */
+int stag_time_kernels(stag_ctx* ctx, const stag_gauge* gauge, int prec, int nrhs, int reps,
+                      double* us);
 int stag_timing_read(stag_ctx* ctx, int kind, int64_t* count, double* total_ms);
 
 #ifdef __cplusplus

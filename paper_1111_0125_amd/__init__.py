@@ -120,7 +120,12 @@ def _load():
         "stag_tune_get": ([vp, ip, ip, ctypes.c_int64, ctypes.POINTER(TuneCfg)], ip),
         "stag_tune_set": ([vp, ip, ip, ctypes.c_int64, ctypes.POINTER(TuneCfg)], ip),
         "stag_tune": ([vp, vp, ip, ip, ctypes.POINTER(TuneCfg), ctypes.POINTER(dp)], ip),
+        "stag_solver_submit": ([vp, vp, dp, ip, vp, dp, ip, ctypes.POINTER(ctypes.c_int64)], ip),
+        "stag_solver_poll": ([vp, ctypes.c_int64, vp, ctypes.POINTER(CgStats),
+                              ctypes.POINTER(dp)], ip),
+        "stag_solver_config": ([vp, ip, ip, ip], ip),
         "stag_timing_enable": ([vp, ip], ip),
+        "stag_time_kernels": ([vp, vp, ip, ip, ip, ctypes.POINTER(dp)], ip),
         "stag_timing_read": ([vp, ip, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(dp)], ip),
     }
     for name, (args, res) in sig.items():
@@ -338,3 +343,44 @@ def stag_timing_read(ctx: Context, kind):
     ms = ctypes.c_double()
     ctx.check(lib.stag_timing_read(ctx.h, int(kind), ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+def stag_solver_config(ctx: Context, slots_per_batch=16, graph_k=0, queue_cap=4096):
+    return ctx.check(lib.stag_solver_config(ctx.h, int(slots_per_batch), int(graph_k),
+                                            int(queue_cap)))
+
+
+def stag_solver_submit(ctx: Context, gauge: Gauge, mass, b, tol=1e-8, inner="f32") -> int:
+    """Queue a solve of A x = b (b: complex128 (nrhs, Vh, 3) host array); returns a ticket."""
+    b = np.ascontiguousarray(b, dtype=np.complex128)
+    if b.ndim != 3 or b.shape[1:] != (gauge.vh, 3):
+        raise ValueError(f"b must have shape (nrhs, {gauge.vh}, 3)")
+    t = ctypes.c_int64()
+    ctx.check(lib.stag_solver_submit(ctx.h, gauge.h, float(mass), int(b.shape[0]),
+                                     ctypes.c_void_p(b.ctypes.data), float(tol),
+                                     PREC[inner] if isinstance(inner, str) else int(inner),
+                                     ctypes.byref(t)))
+    return t.value
+
+
+def stag_solver_poll(ctx: Context, ticket: int, nrhs: int, vh: int, want_x=True):
+    """None while pending; else (status, x or None, stats list, latency seconds)."""
+    x = np.empty((nrhs, vh, 3), dtype=np.complex128) if want_x else None
+    stats = (CgStats * nrhs)()
+    lat = ctypes.c_double()
+    rc = lib.stag_solver_poll(ctx.h, int(ticket),
+                              ctypes.c_void_p(x.ctypes.data) if want_x else None, stats,
+                              ctypes.byref(lat))
+    if rc == STAG_PENDING:
+        return None
+    if rc in (STAG_EINVAL, STAG_ENOTFOUND, STAG_EDEVICE, STAG_ENOMEM):
+        raise StagError(rc, ctx.last_error())
+    return rc, x, [s.as_dict() for s in stats], lat.value
+
+
+def stag_time_kernels(ctx: Context, gauge: Gauge, prec="f32", nrhs=1, reps=200):
+    """Average microseconds of the CG iteration's kernels: (D_oe stage, D_eo stage, update)."""
+    us = (ctypes.c_double * 3)()
+    ctx.check(lib.stag_time_kernels(ctx.h, gauge.h, PREC[prec] if isinstance(prec, str) else prec,
+                                    int(nrhs), int(reps), us))
+    return tuple(us)

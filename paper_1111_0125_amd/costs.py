@@ -25,15 +25,21 @@ FLOPS_PER_SITE_XPAY = 12        # m^2 x - t over 3 complex numbers
 FLOPS_PER_SITE_DOT = 12         # Re<x, h> over 3 complex numbers
 
 
-def hop_bytes_per_site(prec: str, stage: int, nrhs: int = 1) -> int:
+def hop_bytes_per_site(prec: str, stage: int, nrhs: int = 1, lazy: bool = False) -> int:
     """Compulsory bytes per output site of one hop launch.
 
     stage 1 (D_oe, plain output): 8 links + nrhs x (read input + write output)
     stage 2 (D_eo, m^2 update + dot): 8 links + nrhs x (read t, read x, write)
+    lazy (inside a CG iteration, the direction update d = r + beta d is
+    formed in the kernel): stage 1 also reads r; stage 2 also reads r and
+    writes the new d.
     """
     links = 8 * LINK_BYTES[prec] + SITE_SCALE_BYTES[prec]
-    vec = SPINOR_BYTES[prec] * (2 if stage == 1 else 3)
-    return links + nrhs * vec
+    if stage == 1:
+        nvec = 3 if lazy else 2
+    else:
+        nvec = 5 if lazy else 3
+    return links + nrhs * nvec * SPINOR_BYTES[prec]
 
 
 def a_bytes_per_site(prec: str, nrhs: int = 1) -> int:
@@ -53,14 +59,13 @@ def update_bytes_per_site(prec: str, mixed: bool) -> int:
     return 2 * SPINOR_BYTES["f32"] + 4 * SPINOR_BYTES[prec]
 
 
-def xpay_bytes_per_site(prec: str) -> int:
-    return 3 * SPINOR_BYTES[prec]
-
-
-def cg_iteration_bytes_per_site(prec: str, mixed: bool) -> int:
-    return a_bytes_per_site(prec) + update_bytes_per_site(prec, mixed) + xpay_bytes_per_site(prec)
+def cg_iteration_bytes_per_site(prec: str, mixed: bool, nrhs: int = 1) -> int:
+    """One CG iteration as run (three kernels: lazy stage 1, lazy stage 2, update)."""
+    return (hop_bytes_per_site(prec, 1, nrhs, lazy=True) + hop_bytes_per_site(prec, 2, nrhs, lazy=True)
+            + nrhs * update_bytes_per_site(prec, mixed))
 
 
 def cg_iteration_flops_per_site() -> int:
-    # A + <d,Ad> + 2 axpy + |r|^2 + xpay  (paper-style count, 12 flops per complex-vector op)
+    # A + <d,Ad> + 2 axpy + |r|^2 + the deferred xpay (paper-style count, 12 flops
+    # per complex-vector op)
     return 2 * FLOPS_PER_SITE_D + FLOPS_PER_SITE_XPAY + 5 * 12

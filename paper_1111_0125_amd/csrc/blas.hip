@@ -106,18 +106,6 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
                 for (int c = 0; c < 3; ++c)
                     acc += (double)sr[c] * (double)sr[c] + (double)si[c] * (double)si[c];
                 dv[r] = acc;
-            } else if constexpr (OP == OP_XPAY) {
-                // d = q(r + beta d)
-                const T be = (T)a.st[r].beta;
-                T rr[3], ri[3], dr[3], di[3];
-                load_site<P>(slot(a, 0, r), Vh, s, rr, ri);
-                load_site<P>(slot(a, 1, r), Vh, s, dr, di);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    dr[c] = fma(be, dr[c], rr[c]);
-                    di[c] = fma(be, di[c], ri[c]);
-                }
-                store_site<P>(slot(a, 1, r), Vh, s, dr, di);
             } else if constexpr (OP == OP_RU_BEGIN) {
                 // x64 += y; y = 0
                 double xr[3], xi[3];
@@ -132,8 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
                 store_site<P64>(slot(a, 0, r), Vh, s, xr, xi);
                 store_site<P32>(slot(a, 1, r), Vh, s, z, zi);
             } else if constexpr (OP == OP_RU_END) {
-                // rs = q(r64); d = restart ? rs : q(rs + beta' d), beta' = |r64|^2 / |rs_prev|^2
-                const bool restart = (a.st[r].flags & F_STALL) != 0;
+                // rs = q(r64): the low-precision residual restarts from the true one
                 double vr[3], vi[3];
                 load_site<P64>(slot(a, 0, r), Vh, s, vr, vi);
                 T sr[3], si[3];
@@ -143,33 +130,14 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
                     si[c] = (T)vi[c];
                 }
                 store_site<P>(slot(a, 1, r), Vh, s, sr, si);
-                if (restart) {
-                    store_site<P>(slot(a, 2, r), Vh, s, sr, si);
-                } else {
-                    const T be = (T)(a.st[r].rr_true / a.st[r].rr_old);
-                    T dr[3], di[3];
-                    load_site<P>(slot(a, 2, r), Vh, s, dr, di);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        dr[c] = fma(be, dr[c], sr[c]);
-                        di[c] = fma(be, di[c], si[c]);
-                    }
-                    store_site<P>(slot(a, 2, r), Vh, s, dr, di);
-                }
-            } else if constexpr (OP == OP_CG_CHECK) {
-                // restart direction d = r (the true residual)
-                double vr[3], vi[3];
-                load_site<P64>(slot(a, 0, r), Vh, s, vr, vi);
-                store_site<P64>(slot(a, 1, r), Vh, s, vr, vi);
             } else if constexpr (OP == OP_ZERO) {
                 T z[3] = {T(0), T(0), T(0)}, zi[3] = {T(0), T(0), T(0)};
                 store_site<P>(slot(a, 0, r), Vh, s, z, zi);
             }
         }
     }
-    if constexpr (OP == OP_INIT_B || OP == OP_UPD_CG || OP == OP_UPD_MIXED || OP == OP_RU_END ||
-                  OP == OP_CG_CHECK) {
-        block_reduce_finalize<N, 1>(dv, act, a.red, blk);
+    if constexpr (OP == OP_INIT_B || OP == OP_UPD_CG || OP == OP_UPD_MIXED) {
+        block_chunk_partials<N, 1>(dv, a.red, blk);
     }
 }
 
@@ -182,7 +150,6 @@ static hipError_t run_vec_n(int op, const VecArgs& a, hipStream_t st) {
         return hipGetLastError();
     switch (op) {
         STAG_VEC_CASE(OP_START)
-        STAG_VEC_CASE(OP_XPAY)
         STAG_VEC_CASE(OP_ZERO)
         default:
             break;
@@ -191,7 +158,6 @@ static hipError_t run_vec_n(int op, const VecArgs& a, hipStream_t st) {
         switch (op) {
             STAG_VEC_CASE(OP_INIT_B)
             STAG_VEC_CASE(OP_UPD_CG)
-            STAG_VEC_CASE(OP_CG_CHECK)
             default:
                 break;
         }
@@ -228,6 +194,53 @@ hipError_t launch_vec(int prec, int N, int op, const VecArgs& a, hipStream_t st)
         case P16S: return run_vec<P16S>(N, op, a, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+// ------------------------------------------------------------------ reduction finalisation
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_finalize(Reduce R, unsigned run_mask) {
+    sum_partials_finalize<N>(R, run_mask);
+}
+
+hipError_t launch_finalize(int N, const Reduce& R, unsigned run_mask, hipStream_t stream) {
+    switch (N) {
+#define STAG_FIN_CASE(n) \
+    case n: hipLaunchKernelGGL((k_finalize<n>), dim3(1), dim3(kBlock), 0, stream, R, run_mask); break;
+        STAG_FIN_CASE(1)
+        STAG_FIN_CASE(2)
+        STAG_FIN_CASE(4)
+        STAG_FIN_CASE(8)
+        STAG_FIN_CASE(12)
+        STAG_FIN_CASE(16)
+#undef STAG_FIN_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ state transitions
+
+template <int N>
+__global__ void k_state(RhsState* st, unsigned run_mask, int kind) {
+    const int r = threadIdx.x;
+    if (r < N && (st[r].flags & run_mask)) finalize_one(kind, st + r, 0.0, nullptr);
+}
+
+hipError_t launch_state(int N, int kind, RhsState* st, unsigned run_mask, hipStream_t stream) {
+    switch (N) {
+#define STAG_STATE_CASE(n) \
+    case n: hipLaunchKernelGGL((k_state<n>), dim3(1), dim3(64), 0, stream, st, run_mask, kind); break;
+        STAG_STATE_CASE(1)
+        STAG_STATE_CASE(2)
+        STAG_STATE_CASE(4)
+        STAG_STATE_CASE(8)
+        STAG_STATE_CASE(12)
+        STAG_STATE_CASE(16)
+#undef STAG_STATE_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ hop dispatch

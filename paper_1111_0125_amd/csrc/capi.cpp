@@ -102,8 +102,17 @@ void set_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh, const HopTune& t) {
 hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, const HopTune& t,
                        const void* in, size_t in_rs, void* out, size_t out_rs, int p_out,
                        const void* x, size_t x_rs, const void* b, size_t b_rs, const double* m2,
-                       RhsState* st, unsigned run_mask, const Reduce* red, hipStream_t stream) {
+                       RhsState* st, unsigned run_mask, const Reduce* red, hipStream_t stream,
+                       const void* lazy_r, size_t lazy_r_rs) {
+    // the deferred direction update reads beta from the RHS state
+    if (lazy_r && !st) return hipErrorInvalidValue;
+    // reductions and the m^2 update need their buffers
+    if ((epi == EPI_XPAY_DOT || epi == EPI_RESID) && (!red || !red->partials)) return hipErrorInvalidValue;
+    if (epi != EPI_PLAIN && !x) return hipErrorInvalidValue;
+    if (epi == EPI_RESID && !b) return hipErrorInvalidValue;
     HopArgs a{};
+    a.lazy_r = lazy_r;
+    a.lazy_r_rs = lazy_r_rs;
     a.gauge = g->G[prec][p_out];
     a.gscale = prec == P16S ? g->gscale[p_out] : nullptr;
     a.in = in;

@@ -139,6 +139,7 @@ enum StateFlag : unsigned {
     F_MAXIT = 64u,       // iteration cap reached
     F_ESTALL = 128u,     // repeated stall restarts without progress
     F_BADINPUT = 256u,   // |b|^2 not finite
+    F_NEW = 512u,        // slot being started (from x = 0)
 };
 
 struct RhsState {
@@ -166,7 +167,7 @@ struct RhsState {
     int pad;
 };
 
-// Finalisation performed by the last block of a reduction kernel.
+// Finalisation applied to a reduced sum (by the one-block finalize kernel).
 enum FinKind : int {
     FIN_STORE = 0,     // out[r] = sum
     FIN_ALPHA = 1,     // pAp -> alpha (or breakdown)
@@ -179,8 +180,7 @@ enum FinKind : int {
 };
 
 struct Reduce {
-    double* partials;   // [nrhs][nparts]
-    unsigned* counter;  // zero between launches (the last block resets it)
+    double* partials;   // [nrhs][nparts]: one partial per 64-site chunk
     RhsState* st;       // [nrhs]
     double* out;        // FIN_STORE destination [nrhs]
     int kind;

@@ -19,6 +19,27 @@
 
 namespace stag {
 
+// The operand at site n: the stored input, or, for a deferred direction
+// update, d_new = q(r + beta d) formed from the stored r and d.
+template <int P>
+__device__ __forceinline__ void load_operand(const HopArgs& a, const char* in_r, int r, uint32_t n,
+                                             typename Real<P>::T (&vr)[3],
+                                             typename Real<P>::T (&vi)[3]) {
+    using T = typename Real<P>::T;
+    load_site<P>(in_r, a.g.Vh, n, vr, vi);
+    if (a.lazy_r) {
+        const T be = (T)a.st[r].beta;
+        T rr[3], ri[3];
+        load_site<P>((const char*)a.lazy_r + (size_t)r * a.lazy_r_rs, a.g.Vh, n, rr, ri);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            vr[c] = fma(be, vr[c], rr[c]);
+            vi[c] = fma(be, vi[c], ri[c]);
+        }
+        round_site<P>(vr, vi);
+    }
+}
+
 template <int P, int S, int N, int EPI, bool NT>
 __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
     using T = typename Real<P>::T;
@@ -61,10 +82,19 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                 if (!((act >> r) & 1u)) continue;
                 const char* in_r = (const char*)a.in + (size_t)r * a.in_rs;
                 T vr[3], vi[3], pr[3] = {T(0), T(0), T(0)}, pi[3] = {T(0), T(0), T(0)};
-                load_site<P>(in_r, Vh, nf, vr, vi);
-                matvec_acc(lr, li, 0, vr, vi, pr, pi);
-                load_site<P>(in_r, Vh, nb, vr, vi);
-                matvec_acc(lr, li, 9, vr, vi, pr, pi);
+                // the deferred direction is the input of stage 1 only; stage 2
+                // gathers t as stored
+                if constexpr (EPI == EPI_PLAIN) {
+                    load_operand<P>(a, in_r, r, nf, vr, vi);
+                    matvec_acc(lr, li, 0, vr, vi, pr, pi);
+                    load_operand<P>(a, in_r, r, nb, vr, vi);
+                    matvec_acc(lr, li, 9, vr, vi, pr, pi);
+                } else {
+                    load_site<P>(in_r, Vh, nf, vr, vi);
+                    matvec_acc(lr, li, 0, vr, vi, pr, pi);
+                    load_site<P>(in_r, Vh, nb, vr, vi);
+                    matvec_acc(lr, li, 9, vr, vi, pr, pi);
+                }
                 if constexpr (S == 1) {
                     // k = 0, 2 start a pair sum; k = 1, 3 complete it;
                     // k = 3 also adds the two pair sums
@@ -133,7 +163,8 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                 store_site<P>(out_r, Vh, s, ar[r], ai[r]);
             } else {
                 T xr[3], xi[3], hr[3], hi[3];
-                load_site<P>((const char*)a.x + (size_t)r * a.x_rs, Vh, s, xr, xi);
+                load_operand<P>(a, (const char*)a.x + (size_t)r * a.x_rs, r, s, xr, xi);
+                if (a.lazy_r) store_site<P>((char*)a.x + (size_t)r * a.x_rs, Vh, s, xr, xi);
                 const T m2 = (T)(a.st ? a.st[r].m2 : a.m2[r]);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -172,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
         }
     }
     if constexpr (EPI == EPI_XPAY_DOT || EPI == EPI_RESID) {
-        block_reduce_finalize<N, S>(dv, act, a.red, blk);
+        block_chunk_partials<N, S>(dv, a.red, blk);
     }
 }
 

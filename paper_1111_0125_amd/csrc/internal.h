@@ -89,34 +89,85 @@ struct stag_field {
     size_t rs = 0;  // bytes per right-hand side
 };
 
-// Solver workspace + device state for one (gauge, inner precision, N) shape.
+namespace stag {
+// K-iteration graphs of one engine for one kernel block size: one instance,
+// or two alternating ones when the run is timed (each with its own
+// event-record nodes, read back after its replay completed and before it
+// is launched again).
+struct GraphSet {
+    hipGraphExec_t g[2] = {nullptr, nullptr};
+    std::vector<Timing::Rec> ev[2];
+    int n = 0;
+};
+}  // namespace stag
+
+// Solver workspace + device state for N right-hand-side slots of one
+// (gauge, inner precision).
 struct stag_engine {
     stag_ctx* ctx = nullptr;
     const stag_gauge* gauge = nullptr;
     int prec = 0;  // inner precision (P64 = plain CG)
-    int N = 1;
+    int N = 1;     // slots
     bool in_use = false;
     uint32_t Vh = 0;
     // fp64 vectors [N]
     void *x64 = nullptr, *r64 = nullptr, *t64 = nullptr, *d64 = nullptr, *Ad64 = nullptr;
+    void* b64 = nullptr;  // engine-owned right-hand sides (serving), else null
     // low-precision vectors [N]
     void *y32 = nullptr, *rs = nullptr, *d = nullptr, *t = nullptr, *Ad = nullptr;
     size_t rs64 = 0, rsP = 0, rs32 = 0;
-    stag::RhsState* st = nullptr;    // device [N]
-    stag::RhsState* host[2] = {nullptr, nullptr};  // pinned poll buffers
+    stag::RhsState* st = nullptr;                  // device [N]
+    stag::RhsState* host[2] = {nullptr, nullptr};  // pinned poll buffers [N]
+    stag::RhsState* hstage = nullptr;              // pinned slot-start staging [N]
     hipEvent_t ev[2] = {nullptr, nullptr};
     double* partials = nullptr;
     unsigned* counter = nullptr;
     size_t bytes = 0;
-    // One graph of K iterations, or two alternating instances when the
-    // solve is timed (each with its own event-record nodes, read back after
-    // its replay completed and before it is launched again).
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
-    std::vector<stag::Timing::Rec> gev[2];
-    int graph_k = 0;
-    int graph_n = 0;
+    std::map<long long, stag::GraphSet> graphs;    // key: (K, kernel N, timed)
+    hipStream_t cap_stream = nullptr;              // idle stream the graphs are captured on
     stag::HopTune tune_lo, tune_64;
 };
+
+namespace stag {
+
+// Host-side state of a sequence of K-iteration blocks on one engine.
+struct EngineRun {
+    stag_engine* e = nullptr;
+    hipStream_t s = nullptr;
+    const void* b = nullptr;  // right-hand sides, slot-strided
+    size_t b_rs = 0;
+    int K = 16;
+    bool use_graph = true;
+    bool timed = false;
+    long long launched = 0;   // blocks enqueued (block j polls into buffer j % 2)
+    long long polled = 0;     // polls processed
+    long long last_poll = -1; // index of the last processed poll
+    std::vector<long long> fix_after;    // polls <= this are stale for fix-up decisions
+    std::vector<long long> start_after;  // polls <= this predate the slot's start
+    int busy_hi = 0;          // slots [0, busy_hi) may be busy
+    GraphSet* block_graph[2] = {nullptr, nullptr};
+    int block_inst[2] = {0, 0};
+};
+
+struct SlotInit {
+    int slot;
+    double mass;
+    stag_cg_params params;
+};
+
+void run_init(EngineRun& R, stag_engine* e, hipStream_t s, const void* b, size_t b_rs, int K,
+              bool use_graph);
+int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots);
+int run_enqueue_block(EngineRun& R);
+int run_process_poll(EngineRun& R, bool blocking, const RhsState** h);
+void fill_stats(const RhsState& s, double secs, stag_cg_stats* out);
+bool flags_terminal(unsigned f);
+int status_of_flags(unsigned f);
+int default_graph_k(uint32_t Vh);
+int engine_create(stag_ctx* ctx, const stag_gauge* g, int prec, int N, bool own_b,
+                  stag_engine** out);
+
+}  // namespace stag
 
 namespace stag {
 
@@ -160,6 +211,7 @@ void timing_collect(stag_ctx* ctx);  // accumulate every completed record
 hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, const HopTune& t,
                        const void* in, size_t in_rs, void* out, size_t out_rs, int p_out,
                        const void* x, size_t x_rs, const void* b, size_t b_rs, const double* m2,
-                       RhsState* st, unsigned run_mask, const Reduce* red, hipStream_t stream);
+                       RhsState* st, unsigned run_mask, const Reduce* red, hipStream_t stream,
+                       const void* lazy_r = nullptr, size_t lazy_r_rs = 0);
 
 }  // namespace stag

@@ -146,6 +146,12 @@ __device__ __forceinline__ void store_site(void* f, uint32_t Vh, uint32_t s,
     }
 }
 
+// Round a colour vector to what the storage precision would hold.
+template <int P>
+__device__ __forceinline__ void round_site(typename Real<P>::T (&re)[3], typename Real<P>::T (&im)[3]) {
+    if constexpr (P == P16S) (void)f16s_encode(re, im);
+}
+
 // ------------------------------------------------------------------ gauge access
 
 // Load the 18 complex entries of hop pair mu (forward link then backward
@@ -281,6 +287,7 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
             s.rr = s.rr_old = s.rr_true = s.best_true = sum;
             s.rmax = s.rmin = sqrt(sum);
             s.since = 0;
+            s.beta = 0.0;  // first direction d = r
             if (!isfinite(sum)) {
                 s.flags = F_BADINPUT;
             } else if (sum == 0.0 || sum <= s.rr_stop) {
@@ -307,6 +314,9 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
                 s.flags = F_MAXIT;
                 break;
             }
+            // Eq.6: the next direction is r + beta d with beta = |r_true|^2 / |r_prev|^2;
+            // a stall restarts the direction from r (beta = 0)
+            s.beta = stall ? 0.0 : rt / s.rr_old;
             if (stall) {
                 s.restarts += 1;
                 if (rt < 0.25 * s.best_true) {
@@ -339,6 +349,7 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
             } else {
                 s.rr = rt;
                 s.restarts += 1;
+                s.beta = 0.0;  // restart the direction from the true residual
                 s.flags = F_ACTIVE;
             }
             break;
@@ -350,24 +361,21 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
 
 // Reduction partials are taken over fixed chunks of 64 consecutive sites,
 // whatever the launch shape, and each chunk is summed by the same butterfly
-// over the site index; the last block to finish then sums the chunk
-// partials in index order. The result is therefore independent of how many
-// lanes serve a site and of how many right-hand sides share the kernel.
+// over the site index; a separate one-block kernel (k_finalize) then sums
+// the chunk partials in index order. The result is therefore independent of
+// how many lanes serve a site and of how many right-hand sides share the
+// kernel. No block waits for another and no atomics are used: on this chip
+// cross-block atomics serialise (tens of ns per block), which made an
+// in-kernel "last block finalises" tail cost several microseconds.
 constexpr int kChunk = 64;
 
 // v[r] is the value of the site handled by this thread (meaningful on the
 // first lane of each site, i.e. threadIdx.x % S == 0); the block covers
-// kBlock / S consecutive sites starting at blk * (kBlock / S). `act` has bit
-// r set for the RHS the kernel processed (uniform over the grid). Every
-// block must call this.
+// kBlock / S consecutive sites starting at blk * (kBlock / S).
 template <int N, int S>
-__device__ __forceinline__ void block_reduce_finalize(double (&v)[N], unsigned act,
-                                                      const Reduce& R, uint32_t blk) {
+__device__ __forceinline__ void block_chunk_partials(double (&v)[N], const Reduce& R, uint32_t blk) {
     constexpr int SPB = kBlock / S;          // sites per block
     constexpr int CPB = SPB / kChunk;        // chunks per block (>= 1)
-    __shared__ double sv[N][SPB];
-    __shared__ double red[16];
-    __shared__ bool last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if constexpr (S == 1) {
         // one wave is one chunk: reduce straight from registers
@@ -380,6 +388,7 @@ __device__ __forceinline__ void block_reduce_finalize(double (&v)[N], unsigned a
             if (lane == 0 && ch < (uint32_t)R.nparts) R.partials[(size_t)r * R.nparts + ch] = x;
         }
     } else {
+        __shared__ double sv[N][SPB];
         if (threadIdx.x % S == 0) {
 #pragma unroll
             for (int r = 0; r < N; ++r) sv[r][threadIdx.x / S] = v[r];
@@ -396,23 +405,21 @@ __device__ __forceinline__ void block_reduce_finalize(double (&v)[N], unsigned a
             }
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned total = gridDim.x * gridDim.y;
-        const unsigned prev = atomicAdd(R.counter, 1u);
-        last = (prev == total - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // fixed-order final sum: thread i takes parts i, i + B, i + 2B, ...
-    constexpr int B = kBlock, NW = kBlock / 64;
+}
+
+// Fixed-order sum of the chunk partials of every RHS whose flags match
+// run_mask, then the finalisation; run by one block of kBlock threads after
+// the producing kernel has finished.
+template <int N>
+__device__ __forceinline__ void sum_partials_finalize(const Reduce& R, unsigned run_mask) {
+    __shared__ double red[kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NW = kBlock / 64;
     for (int r = 0; r < N; ++r) {
-        if (!((act >> r) & 1u)) continue;
-        const volatile double* pp = R.partials + (size_t)r * R.nparts;
+        if (R.st && !(R.st[r].flags & run_mask)) continue;  // uniform over the block
+        const double* pp = R.partials + (size_t)r * R.nparts;
         double x = 0.0;
-        for (int i = threadIdx.x; i < R.nparts; i += B) x += pp[i];
+        for (int i = threadIdx.x; i < R.nparts; i += kBlock) x += pp[i];
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
         if (lane == 0) red[wave] = x;
@@ -423,10 +430,6 @@ __device__ __forceinline__ void block_reduce_finalize(double (&v)[N], unsigned a
             finalize_one(R.kind, R.st ? R.st + r : nullptr, t, R.out ? R.out + r : nullptr);
         }
         __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        atomicExch(R.counter, 0u);
     }
 }
 

@@ -26,6 +26,13 @@ struct HopArgs {
     size_t x_rs;
     const void* b;         // RESID: right-hand side
     size_t b_rs;
+    // Deferred direction update (solver iterations): when lazy_r is set the
+    // operand is d_new = r + beta d with d the stored previous direction
+    // (beta from the RHS state), rounded to the storage precision. Stage 1
+    // forms it at every neighbour it gathers; stage 2 forms it at its own
+    // site, uses it as x and stores it over d.
+    const void* lazy_r;
+    size_t lazy_r_rs;
     double m2[16];         // mass^2 per right-hand side (used when st is null)
     RhsState* st;          // null: every RHS is processed
     unsigned run_mask;     // process RHS r iff st[r].flags & run_mask
@@ -41,10 +48,8 @@ enum VecOp : int {
     OP_START = 1,      // d = q(r64); if rs: rs = q(r64); if y: y = 0
     OP_UPD_CG = 2,     // x += a d, r -= a Ad, |r|^2 -> FIN_CG           (fp64)
     OP_UPD_MIXED = 3,  // y += a d, rs = q(rs - a Ad), |rs|^2 -> FIN_MIXED
-    OP_XPAY = 4,       // d = q(r + beta d)
     OP_RU_BEGIN = 5,   // x64 += y, y = 0
-    OP_RU_END = 6,     // rs = q(r64), d = restart ? rs : q(rs + beta' d) -> FIN_RU_END
-    OP_CG_CHECK = 7,   // d = r for a restart, decision -> FIN_CG_CHECK
+    OP_RU_END = 6,     // rs = q(r64) after a true-residual recompute
     OP_ZERO = 8,       // f0 = 0
 };
 
@@ -61,6 +66,13 @@ struct VecArgs {
 hipError_t launch_hop(int prec, int S, int N, int epi, bool nt, const HopArgs& a,
                       hipStream_t stream);
 hipError_t launch_vec(int prec, int N, int op, const VecArgs& a, hipStream_t stream);
+// One-block fixed-order sum of a reduction kernel's chunk partials and its
+// finalisation (R.kind), for the RHS whose flags match run_mask; launched
+// right after the kernel that wrote the partials, with the same run_mask.
+hipError_t launch_finalize(int N, const Reduce& R, unsigned run_mask, hipStream_t stream);
+// One-block state transition (FIN_RU_END, FIN_CG_CHECK) of the RHS whose
+// flags match run_mask.
+hipError_t launch_state(int N, int kind, RhsState* st, unsigned run_mask, hipStream_t stream);
 
 // Layout conversion kernels (canonical complex128 <-> internal storage).
 hipError_t launch_gauge_pack(int prec, const void* U_dev, void* G, float* gscale, const Geom& g,

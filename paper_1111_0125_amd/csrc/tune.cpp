@@ -153,18 +153,16 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, stag_tune_
     const size_t rs = spinor_rhs_bytes(prec, Vh);
     void *in = nullptr, *t = nullptr, *out = nullptr;
     double* partials = nullptr;
-    unsigned* counter = nullptr;
     RhsState* st = nullptr;
     hipStream_t s = ctx->stream;
     auto cleanup = [&]() {
-        void* ps[] = {in, t, out, partials, counter, st};
+        void* ps[] = {in, t, out, partials, st};
         for (void* p : ps)
             if (p) (void)hipFree(p);
     };
     if (hipMalloc(&in, rs * N) != hipSuccess || hipMalloc(&t, rs * N) != hipSuccess ||
         hipMalloc(&out, rs * N) != hipSuccess ||
         hipMalloc((void**)&partials, sizeof(double) * N * num_chunks(Vh)) != hipSuccess ||
-        hipMalloc((void**)&counter, 256) != hipSuccess ||
         hipMalloc((void**)&st, sizeof(RhsState) * N) != hipSuccess) {
         (void)hipGetLastError();
         cleanup();
@@ -178,12 +176,10 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, stag_tune_
         hst[r].rr = 1.0;
     }
     (void)hipMemset(in, 0, rs * N);
-    (void)hipMemset(counter, 0, 256);
     (void)hipMemcpy(st, hst.data(), sizeof(RhsState) * N, hipMemcpyHostToDevice);
     (void)hipDeviceSynchronize();  // the null-stream writes above must land before s runs
     Reduce red{};
     red.partials = partials;
-    red.counter = counter;
     red.st = st;
     red.kind = FIN_STORE;
     red.nparts = (int)num_chunks(Vh);

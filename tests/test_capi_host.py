@@ -20,7 +20,8 @@ def declared_functions():
 
 def test_header_declares_boundary_calls():
     names = declared_functions()
-    for must in ("stag_dslash", "stag_apply_A", "stag_cg_solve"):
+    for must in ("stag_dslash", "stag_apply_A", "stag_cg_solve", "stag_solver_submit",
+                 "stag_solver_poll"):
         assert must in names
 
 
@@ -42,6 +43,9 @@ def test_null_and_bad_arguments_rejected_on_host():
     assert lib.stag_dslash(None, None, None, None, None) == s.STAG_EINVAL
     assert lib.stag_apply_A(None, None, None, None, None, None) == s.STAG_EINVAL
     assert lib.stag_cg_solve(None, None, None, None, None, None, None, None) == s.STAG_EINVAL
+    assert lib.stag_solver_submit(None, None, 0.1, 1, None, 1e-8, 1, None) == s.STAG_EINVAL
+    assert lib.stag_solver_poll(None, 1, None, None, None) == s.STAG_EINVAL
+    assert lib.stag_tune(None, None, 0, 1, None, None) == s.STAG_EINVAL
     assert isinstance(lib.stag_last_error(None), bytes)
 
 
