@@ -103,6 +103,100 @@ def a_apply_bandwidth(stag, torch, costs, synth, reps=50):
     return out
 
 
+def batched_c4(stag, torch, synth):
+    """24^3 x 48, exp(i 0.5 H) links, m = 0.01, 12 right-hand sides to 1e-8:
+    one block solve (links loaded once per site for all 12) against one
+    single-RHS solve repeated 12 times."""
+    name = "c4_24x24x24x48"
+    cfg = synth.CONFIGS[name]
+    L, m, tol, n = cfg["L"], cfg["mass"], cfg["tol"], cfg["nrhs"]
+    log("generating", name)
+    U = synth.config_links(name)
+    b = synth.config_rhs(name)
+    with stag.Context(0) as ctx:
+        g = ctx.gauge(L, U, precisions=("f64", "f32"))
+        stag.stag_tune(ctx, g, "f32", n)
+        stag.stag_tune(ctx, g, "f32", 1)
+        fb = ctx.field(g, 0, "f64", n).load(b)
+        fx = ctx.field(g, 0, "f64", n)
+        p = stag.cg_params(tol=tol, inner="f32")
+        stag.stag_cg_solve(ctx, g, [m] * n, fb, fx, p)  # warm-up (graphs, workspace)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = stag.stag_cg_solve(ctx, g, [m] * n, fb, fx, p)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        f1 = ctx.field(g, 0, "f64", 1).load(b[:1])
+        x1 = ctx.field(g, 0, "f64", 1)
+        stag.stag_cg_solve(ctx, g, [m], f1, x1, p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc1, st1 = stag.stag_cg_solve(ctx, g, [m], f1, x1, p)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter() - t0
+    out = {"nrhs": n, "block_solve_s": round(tb, 4), "solves_per_s": round(n / tb, 3),
+           "single_solve_s": round(t1, 4), "sequential_12_s_est": round(12 * t1, 4),
+           "block_speedup": round(12 * t1 / tb, 3), "status": rc,
+           "max_iters": max(s["iters"] for s in st),
+           "max_true_rel_res": max(s["true_rel_res"] for s in st)}
+    log("batched", out)
+    return out
+
+
+def serving(stag, synth, n_requests=40, rate=None, full=False, seed=2011):
+    """A Poisson stream of solve requests over resident gauge fields,
+    continuously batched per gauge; solves/s and submit-to-finish latency."""
+    import numpy as np
+    sizes = [(8, 8, 8, 8), (16, 16, 16, 32)]
+    if full:
+        sizes += [(24, 24, 24, 48), (32, 32, 32, 64)]
+    masses = [0.01, 0.02, 0.05, 0.1]
+    tols = [1e-6, 1e-8, 1e-10]
+    log("serving: generating", sizes)
+    # the same smooth-link recipe as the 16^3 x 32 workload (exp(i 0.3 H))
+    links = [synth.exp_ih_links(L, 15 + i, 0.3) for i, L in enumerate(sizes)]
+    rate = rate or (50.0 if not full else 5.0)
+    reqs = synth.request_stream(seed, n_requests, rate, sizes, masses, tols, max_nrhs=8)
+    lat, nrhs_done = [], 0
+    with stag.Context(0) as ctx:
+        gauges = [ctx.gauge(L, U, precisions=("f64", "f32")) for L, U in zip(sizes, links)]
+        del links
+        pending = {}
+        t0 = time.perf_counter()
+        i = 0
+        while i < len(reqs) or pending:
+            now = time.perf_counter() - t0
+            while i < len(reqs) and reqs[i]["t"] <= now:
+                q = reqs[i]
+                L = sizes[q["lattice"]]
+                b = synth.gaussian_rhs(L, q["nrhs"], q["rhs_seed"])
+                tid = stag.stag_solver_submit(ctx, gauges[q["lattice"]], q["mass"], b, q["tol"], "f32")
+                pending[tid] = (q["nrhs"], gauges[q["lattice"]].vh)
+                i += 1
+            for tid in list(pending):
+                nr, vh = pending[tid]
+                r = stag.stag_solver_poll(ctx, tid, nr, vh, want_x=False)
+                if r is not None:
+                    rc, _, st, latency = r
+                    if rc != 0:
+                        raise RuntimeError(f"serving request failed: {rc} {st}")
+                    lat.append(latency)
+                    nrhs_done += nr
+                    del pending[tid]
+            time.sleep(0.0005)
+        wall = time.perf_counter() - t0
+    lat = np.array(lat)
+    out = {"requests": len(reqs), "rhs": nrhs_done, "wall_s": round(wall, 3),
+           "solves_per_s": round(nrhs_done / wall, 3), "requests_per_s": round(len(reqs) / wall, 3),
+           "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+           "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+           "arrival_rate_per_s": rate,
+           "lattices": ["x".join(map(str, L)) for L in sizes],
+           "masses": masses, "tols": tols, "inner": "f32"}
+    log("serving", out)
+    return out
+
+
 def cpu_baseline(synth, L, U, b, mass, gpu_fp64_iters, target_s):
     """The fp64 C oracle's Fig.1 CG on the same system, timed on this host
     for a bounded number of iterations and scaled to a full solve."""
@@ -136,6 +230,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the fp64 / f16s comparison solves and the 32^3x64 A-apply")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serving stream over all four lattice sizes (long)")
+    ap.add_argument("--serve-requests", type=int, default=40)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -243,6 +340,9 @@ def main():
 
     if not args.no_extras:
         result["a_apply_32x32x32x64"] = a_apply_bandwidth(stag, torch, costs, synth)
+        result["batched_24x24x24x48_12rhs"] = batched_c4(stag, torch, synth)
+        result["serving"] = serving(stag, synth, n_requests=args.serve_requests,
+                                    full=args.serve_full)
 
     if not args.no_cpu:
         if fp64_iters is None:

@@ -242,9 +242,12 @@ int stag_solver_config(stag_ctx* ctx, int slots_per_batch, int graph_k, int queu
  * nt = non-temporal link loads, swizzle = XCD-aware block order. Every
  * shape computes bit-identical results; only speed differs.
  * stag_tune_get / stag_tune_set: the shape used for (prec, nrhs, vh).
- * stag_tune: time every shape on the gauge's actual links and keep the
- * fastest (synchronous; allocates temporary vectors). best / best_ms may be
- * NULL. Errors: EINVAL, ENOMEM, EDEVICE.
+ * stag_tune: time the solver's own iteration kernels (see
+ * stag_time_kernels) in every shape on the gauge's actual links and keep
+ * the fastest (synchronous; uses a solver workspace for nrhs right-hand
+ * sides, allocated if none is free). best / best_ms may be NULL; best_ms is
+ * the time of the two hop stages in milliseconds. Errors: EINVAL, ENOMEM,
+ * EDEVICE.
  */
 typedef struct stag_tune_cfg {
     int S1, S2, nt, swizzle;
@@ -269,13 +272,15 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* gauge, int prec, int nrhs, stag_t
 #define STAG_K_XPAY 5     /* direction update d = r + beta d */
 #define STAG_K_OTHER 6
 int stag_timing_enable(stag_ctx* ctx, int on);
-/* stag_time_kernels: average duration in microseconds of the three kernels
- * of one CG iteration exactly as stag_cg_solve launches them (same buffers,
- * launch shape and arithmetic) for `prec` (STAG_F64: plain CG, else mixed)
- * and nrhs right-hand sides: us[0] = D_oe stage (with the deferred direction
- * update), us[1] = D_eo stage with m^2 update and <d, A d>, us[2] = fused
- * update with |r|^2. Each is timed over `reps` back-to-back launches between
- * two HIP events on the context's stream. Synchronous. */
+/* stag_time_kernels: average execution time in microseconds of the three
+ * kernels of one CG iteration exactly as stag_cg_solve launches them (same
+ * buffers, launch shape and arithmetic) for `prec` (STAG_F64: plain CG, else
+ * mixed) and nrhs right-hand sides: us[0] = D_oe stage (with the deferred
+ * direction update and the finalisation of the previous |r|^2), us[1] = D_eo
+ * stage with m^2 update and <d, A d>, us[2] = fused update with |r|^2 (and
+ * the finalisation of alpha). Each is the mean over `reps` (1..100000)
+ * launches of the time between events recorded at the start and the end of
+ * the kernel (hipExtLaunchKernel) on the context's stream. Synchronous. */
 int stag_time_kernels(stag_ctx* ctx, const stag_gauge* gauge, int prec, int nrhs, int reps,
                       double* us);
 int stag_timing_read(stag_ctx* ctx, int kind, int64_t* count, double* total_ms);

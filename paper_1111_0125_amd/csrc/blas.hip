@@ -1,21 +1,15 @@
 // Vector kernels of the CG iteration (Fig.1 and Sec.3.2): fused axpy + norm
 // updates with fp64 reductions, the direction update, and the pieces of the
 // reliable / group-wise update. One thread per site handles every active
-// right-hand side of the block; the CG scalars are read from, and written
-// to, the device-resident per-RHS state.
+// right-hand side of the block; the CG scalars come from the device-resident
+// per-RHS state, optionally finalised at kernel start from the partials of
+// the reduction that precedes the kernel.
+#include <hip/hip_ext.h>
+
 #include "kern.h"
 #include "launch.h"
 
 namespace stag {
-
-template <int N>
-__device__ __forceinline__ unsigned active_mask(const VecArgs& a) {
-    unsigned act = 0;
-#pragma unroll
-    for (int r = 0; r < N; ++r)
-        if (!a.st || (a.st[r].flags & a.run_mask)) act |= 1u << r;
-    return act;
-}
 
 __device__ __forceinline__ char* slot(const VecArgs& a, int k, int r) {
     return (char*)a.f[k] + (size_t)r * a.rs[k];
@@ -28,7 +22,23 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
     const uint32_t s = blk * kBlock + threadIdx.x;
     const uint32_t Vh = a.Vh;
     const bool valid = s < Vh;
-    const unsigned act = active_mask<N>(a);
+    // the state of every RHS, in LDS: finalised here from the previous
+    // reduction's partials when a.fin is set, else copied as it is
+    __shared__ RhsState ls[N];
+    unsigned act = (1u << N) - 1u;
+    if (a.st) {
+        if (a.fin.partials) {
+            Reduce F = a.fin;
+            F.st = a.st;
+            finalize_block<N>(F, a.run_mask, ls);
+        } else {
+            load_state<N>(a.st, ls);
+        }
+        act = 0;
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+            if (ls[r].flags & a.run_mask) act |= 1u << r;
+    }
     double dv[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) dv[r] = 0.0;
@@ -65,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
                 }
             } else if constexpr (OP == OP_UPD_CG) {
                 // x += alpha d; r -= alpha Ad; |r|^2   (all fp64)
-                const double al = a.st[r].alpha;
+                const double al = ls[r].alpha;
                 double xr[3], xi[3], rr[3], ri[3], dr[3], di[3], qr[3], qi[3];
                 load_site<P64>(slot(a, 0, r), Vh, s, xr, xi);
                 load_site<P64>(slot(a, 1, r), Vh, s, rr, ri);
@@ -85,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
                 dv[r] = acc;
             } else if constexpr (OP == OP_UPD_MIXED) {
                 // y += alpha d (fp32); rs = q(rs - alpha Ad); |rs|^2 of the stored rs
-                const float al = (float)a.st[r].alpha;
+                const float al = (float)ls[r].alpha;
                 float yr[3], yi[3];
                 T sr[3], si[3], dr[3], di[3], qr[3], qi[3];
                 load_site<P32>(slot(a, 0, r), Vh, s, yr, yi);
@@ -142,11 +152,15 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
 }
 
 template <int P, int N>
-static hipError_t run_vec_n(int op, const VecArgs& a, hipStream_t st) {
+static hipError_t run_vec_n(int op, const VecArgs& a, hipStream_t st, const LaunchEvents* ev) {
     const dim3 grid(vec_blocks(a.Vh)), block(kBlock);
-#define STAG_VEC_CASE(OPV)                                                   \
-    case OPV:                                                                \
-        hipLaunchKernelGGL((k_vec<P, N, OPV>), grid, block, 0, st, a);       \
+#define STAG_VEC_CASE(OPV)                                                                 \
+    case OPV:                                                                              \
+        if (ev)                                                                            \
+            hipExtLaunchKernelGGL((k_vec<P, N, OPV>), grid, block, 0, st, ev->start,        \
+                                  ev->stop, 0, a);                                          \
+        else                                                                               \
+            hipLaunchKernelGGL((k_vec<P, N, OPV>), grid, block, 0, st, a);                 \
         return hipGetLastError();
     switch (op) {
         STAG_VEC_CASE(OP_START)
@@ -175,23 +189,24 @@ static hipError_t run_vec_n(int op, const VecArgs& a, hipStream_t st) {
 }
 
 template <int P>
-static hipError_t run_vec(int N, int op, const VecArgs& a, hipStream_t st) {
+static hipError_t run_vec(int N, int op, const VecArgs& a, hipStream_t st, const LaunchEvents* ev) {
     switch (N) {
-        case 1: return run_vec_n<P, 1>(op, a, st);
-        case 2: return run_vec_n<P, 2>(op, a, st);
-        case 4: return run_vec_n<P, 4>(op, a, st);
-        case 8: return run_vec_n<P, 8>(op, a, st);
-        case 12: return run_vec_n<P, 12>(op, a, st);
-        case 16: return run_vec_n<P, 16>(op, a, st);
+        case 1: return run_vec_n<P, 1>(op, a, st, ev);
+        case 2: return run_vec_n<P, 2>(op, a, st, ev);
+        case 4: return run_vec_n<P, 4>(op, a, st, ev);
+        case 8: return run_vec_n<P, 8>(op, a, st, ev);
+        case 12: return run_vec_n<P, 12>(op, a, st, ev);
+        case 16: return run_vec_n<P, 16>(op, a, st, ev);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_vec(int prec, int N, int op, const VecArgs& a, hipStream_t st) {
+hipError_t launch_vec(int prec, int N, int op, const VecArgs& a, hipStream_t st,
+                      const LaunchEvents* ev) {
     switch (prec) {
-        case P64: return run_vec<P64>(N, op, a, st);
-        case P32: return run_vec<P32>(N, op, a, st);
-        case P16S: return run_vec<P16S>(N, op, a, st);
+        case P64: return run_vec<P64>(N, op, a, st, ev);
+        case P32: return run_vec<P32>(N, op, a, st, ev);
+        case P16S: return run_vec<P16S>(N, op, a, st, ev);
         default: return hipErrorInvalidValue;
     }
 }
@@ -200,7 +215,8 @@ hipError_t launch_vec(int prec, int N, int op, const VecArgs& a, hipStream_t st)
 
 template <int N>
 __global__ __launch_bounds__(kBlock) void k_finalize(Reduce R, unsigned run_mask) {
-    sum_partials_finalize<N>(R, run_mask);
+    __shared__ RhsState ls[N];
+    finalize_block<N>(R, run_mask, ls);
 }
 
 hipError_t launch_finalize(int N, const Reduce& R, unsigned run_mask, hipStream_t stream) {
@@ -245,16 +261,19 @@ hipError_t launch_state(int N, int kind, RhsState* st, unsigned run_mask, hipStr
 
 // ------------------------------------------------------------------ hop dispatch
 
-hipError_t launch_hop_p0(int S, int N, int epi, bool nt, const HopArgs& a, hipStream_t st);
-hipError_t launch_hop_p1(int S, int N, int epi, bool nt, const HopArgs& a, hipStream_t st);
-hipError_t launch_hop_p2(int S, int N, int epi, bool nt, const HopArgs& a, hipStream_t st);
+hipError_t launch_hop_p0(int S, int N, int epi, bool nt, const HopArgs& a, hipStream_t st,
+                         const LaunchEvents* ev);
+hipError_t launch_hop_p1(int S, int N, int epi, bool nt, const HopArgs& a, hipStream_t st,
+                         const LaunchEvents* ev);
+hipError_t launch_hop_p2(int S, int N, int epi, bool nt, const HopArgs& a, hipStream_t st,
+                         const LaunchEvents* ev);
 
 hipError_t launch_hop(int prec, int S, int N, int epi, bool nt, const HopArgs& a,
-                      hipStream_t st) {
+                      hipStream_t st, const LaunchEvents* ev) {
     switch (prec) {
-        case P64: return launch_hop_p0(S, N, epi, nt, a, st);
-        case P32: return launch_hop_p1(S, N, epi, nt, a, st);
-        case P16S: return launch_hop_p2(S, N, epi, nt, a, st);
+        case P64: return launch_hop_p0(S, N, epi, nt, a, st, ev);
+        case P32: return launch_hop_p1(S, N, epi, nt, a, st, ev);
+        case P16S: return launch_hop_p2(S, N, epi, nt, a, st, ev);
         default: return hipErrorInvalidValue;
     }
 }

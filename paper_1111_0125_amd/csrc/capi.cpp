@@ -103,9 +103,12 @@ hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, con
                        const void* in, size_t in_rs, void* out, size_t out_rs, int p_out,
                        const void* x, size_t x_rs, const void* b, size_t b_rs, const double* m2,
                        RhsState* st, unsigned run_mask, const Reduce* red, hipStream_t stream,
-                       const void* lazy_r, size_t lazy_r_rs) {
-    // the deferred direction update reads beta from the RHS state
+                       const void* lazy_r, size_t lazy_r_rs, const Reduce* fin,
+                       const LaunchEvents* ev) {
+    // the deferred direction update reads beta from the RHS state, and a
+    // finalisation at kernel start needs the state and the partials
     if (lazy_r && !st) return hipErrorInvalidValue;
+    if (fin && (!st || !fin->partials || fin->nparts < 1)) return hipErrorInvalidValue;
     // reductions and the m^2 update need their buffers
     if ((epi == EPI_XPAY_DOT || epi == EPI_RESID) && (!red || !red->partials)) return hipErrorInvalidValue;
     if (epi != EPI_PLAIN && !x) return hipErrorInvalidValue;
@@ -130,8 +133,9 @@ hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, con
     a.swizzle = t.swizzle;
     a.g = g->g;
     if (red) a.red = *red;
+    if (fin) a.fin = *fin;
     if (N > 1) S = 1;
-    return launch_hop(prec, S, N, epi, t.nt != 0, a, stream);
+    return launch_hop(prec, S, N, epi, t.nt != 0, a, stream, ev);
 }
 
 }  // namespace stag

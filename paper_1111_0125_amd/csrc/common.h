@@ -179,10 +179,17 @@ enum FinKind : int {
     FIN_CG_CHECK = 7,  // accept or restart after a true-residual check (plain CG)
 };
 
+// A reduction: the producing kernel writes one fp64 partial per 64-site
+// chunk and right-hand side; its consumer sums them in a fixed order and
+// applies `kind` to the state. The consumer reads the state from st and
+// writes the result to st_out (st_out null: in place, one-block consumers
+// only), so a many-block consumer never reads what one of its own blocks
+// has already overwritten.
 struct Reduce {
     double* partials;   // [nrhs][nparts]: one partial per 64-site chunk
-    RhsState* st;       // [nrhs]
+    RhsState* st;       // [nrhs] state read
     double* out;        // FIN_STORE destination [nrhs]
+    RhsState* st_out;   // [nrhs] state written (null: st)
     int kind;
     int nparts;
 };

@@ -10,6 +10,8 @@
 // them (the block operator sharing gauge loads).
 //
 // This file is compiled once per storage precision (HOP_PREC).
+#include <hip/hip_ext.h>
+
 #include "kern.h"
 #include "launch.h"
 
@@ -23,12 +25,12 @@ namespace stag {
 // update, d_new = q(r + beta d) formed from the stored r and d.
 template <int P>
 __device__ __forceinline__ void load_operand(const HopArgs& a, const char* in_r, int r, uint32_t n,
-                                             typename Real<P>::T (&vr)[3],
+                                             double beta, typename Real<P>::T (&vr)[3],
                                              typename Real<P>::T (&vi)[3]) {
     using T = typename Real<P>::T;
     load_site<P>(in_r, a.g.Vh, n, vr, vi);
     if (a.lazy_r) {
-        const T be = (T)a.st[r].beta;
+        const T be = (T)beta;
         T rr[3], ri[3];
         load_site<P>((const char*)a.lazy_r + (size_t)r * a.lazy_r_rs, a.g.Vh, n, rr, ri);
 #pragma unroll
@@ -49,10 +51,23 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
     const int j = (int)(gt % S);
     const uint32_t Vh = a.g.Vh;
 
-    unsigned act = 0;
+    // the state of every RHS, in LDS: finalised here from the previous
+    // reduction's partials when a.fin is set, else copied as it is
+    __shared__ RhsState ls[N];
+    unsigned act = (1u << N) - 1u;
+    if (a.st) {
+        if (a.fin.partials) {
+            Reduce F = a.fin;
+            F.st = a.st;
+            finalize_block<N>(F, a.run_mask, ls);
+        } else {
+            load_state<N>(a.st, ls);
+        }
+        act = 0;
 #pragma unroll
-    for (int r = 0; r < N; ++r)
-        if (!a.st || (a.st[r].flags & a.run_mask)) act |= 1u << r;
+        for (int r = 0; r < N; ++r)
+            if (ls[r].flags & a.run_mask) act |= 1u << r;
+    }
 
     T ar[N][3], ai[N][3];
     [[maybe_unused]] T hr2[N][3], hi2[N][3];  // S = 1: sum of pairs 2 and 3 in progress
@@ -85,9 +100,10 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                 // the deferred direction is the input of stage 1 only; stage 2
                 // gathers t as stored
                 if constexpr (EPI == EPI_PLAIN) {
-                    load_operand<P>(a, in_r, r, nf, vr, vi);
+                    const double be = a.lazy_r ? ls[r].beta : 0.0;
+                    load_operand<P>(a, in_r, r, nf, be, vr, vi);
                     matvec_acc(lr, li, 0, vr, vi, pr, pi);
-                    load_operand<P>(a, in_r, r, nb, vr, vi);
+                    load_operand<P>(a, in_r, r, nb, be, vr, vi);
                     matvec_acc(lr, li, 9, vr, vi, pr, pi);
                 } else {
                     load_site<P>(in_r, Vh, nf, vr, vi);
@@ -163,9 +179,10 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                 store_site<P>(out_r, Vh, s, ar[r], ai[r]);
             } else {
                 T xr[3], xi[3], hr[3], hi[3];
-                load_operand<P>(a, (const char*)a.x + (size_t)r * a.x_rs, r, s, xr, xi);
+                load_operand<P>(a, (const char*)a.x + (size_t)r * a.x_rs, r, s,
+                                a.lazy_r ? ls[r].beta : 0.0, xr, xi);
                 if (a.lazy_r) store_site<P>((char*)a.x + (size_t)r * a.x_rs, Vh, s, xr, xi);
-                const T m2 = (T)(a.st ? a.st[r].m2 : a.m2[r]);
+                const T m2 = (T)(a.st ? ls[r].m2 : a.m2[r]);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     hr[c] = fma(m2, xr[c], -ar[r][c]);
@@ -208,35 +225,40 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
 }
 
 template <int P, int S, int N, int EPI, bool NT>
-static hipError_t run_hop(const HopArgs& a, hipStream_t stream) {
+static hipError_t run_hop(const HopArgs& a, hipStream_t stream, const LaunchEvents* ev) {
     const uint32_t nb = hop_blocks(a.g.Vh, S);
-    hipLaunchKernelGGL((k_hop<P, S, N, EPI, NT>), dim3(nb), dim3(kBlock), 0, stream, a);
+    if (ev)
+        hipExtLaunchKernelGGL((k_hop<P, S, N, EPI, NT>), dim3(nb), dim3(kBlock), 0, stream, ev->start,
+                              ev->stop, 0, a);
+    else
+        hipLaunchKernelGGL((k_hop<P, S, N, EPI, NT>), dim3(nb), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
 // Dispatch for this precision: N = 1 with S in {1, 2, 4} and both load
 // flavours; N > 1 with S = 1 and non-temporal link loads.
 template <int P, int EPI>
-static hipError_t dispatch_epi(int S, int N, bool nt, const HopArgs& a, hipStream_t st) {
+static hipError_t dispatch_epi(int S, int N, bool nt, const HopArgs& a, hipStream_t st,
+                               const LaunchEvents* ev) {
     if (N == 1) {
         if (nt) {
-            if (S == 1) return run_hop<P, 1, 1, EPI, true>(a, st);
-            if (S == 2) return run_hop<P, 2, 1, EPI, true>(a, st);
-            if (S == 4) return run_hop<P, 4, 1, EPI, true>(a, st);
+            if (S == 1) return run_hop<P, 1, 1, EPI, true>(a, st, ev);
+            if (S == 2) return run_hop<P, 2, 1, EPI, true>(a, st, ev);
+            if (S == 4) return run_hop<P, 4, 1, EPI, true>(a, st, ev);
         } else {
-            if (S == 1) return run_hop<P, 1, 1, EPI, false>(a, st);
-            if (S == 2) return run_hop<P, 2, 1, EPI, false>(a, st);
-            if (S == 4) return run_hop<P, 4, 1, EPI, false>(a, st);
+            if (S == 1) return run_hop<P, 1, 1, EPI, false>(a, st, ev);
+            if (S == 2) return run_hop<P, 2, 1, EPI, false>(a, st, ev);
+            if (S == 4) return run_hop<P, 4, 1, EPI, false>(a, st, ev);
         }
         return hipErrorInvalidValue;
     }
     if (S != 1) return hipErrorInvalidValue;
     switch (N) {
-        case 2: return run_hop<P, 1, 2, EPI, true>(a, st);
-        case 4: return run_hop<P, 1, 4, EPI, true>(a, st);
-        case 8: return run_hop<P, 1, 8, EPI, true>(a, st);
-        case 12: return run_hop<P, 1, 12, EPI, true>(a, st);
-        case 16: return run_hop<P, 1, 16, EPI, true>(a, st);
+        case 2: return run_hop<P, 1, 2, EPI, true>(a, st, ev);
+        case 4: return run_hop<P, 1, 4, EPI, true>(a, st, ev);
+        case 8: return run_hop<P, 1, 8, EPI, true>(a, st, ev);
+        case 12: return run_hop<P, 1, 12, EPI, true>(a, st, ev);
+        case 16: return run_hop<P, 1, 16, EPI, true>(a, st, ev);
         default: return hipErrorInvalidValue;
     }
 }
@@ -246,14 +268,14 @@ static hipError_t dispatch_epi(int S, int N, bool nt, const HopArgs& a, hipStrea
 #define HOP_FN_NAME(p) HOP_FN_NAME_(p)
 
 hipError_t HOP_FN_NAME(HOP_PREC)(int S, int N, int epi, bool nt, const HopArgs& a,
-                                  hipStream_t st) {
+                                  hipStream_t st, const LaunchEvents* ev) {
     constexpr int P = HOP_PREC;
     switch (epi) {
-        case EPI_PLAIN: return dispatch_epi<P, EPI_PLAIN>(S, N, nt, a, st);
-        case EPI_XPAY: return dispatch_epi<P, EPI_XPAY>(S, N, nt, a, st);
-        case EPI_XPAY_DOT: return dispatch_epi<P, EPI_XPAY_DOT>(S, N, nt, a, st);
+        case EPI_PLAIN: return dispatch_epi<P, EPI_PLAIN>(S, N, nt, a, st, ev);
+        case EPI_XPAY: return dispatch_epi<P, EPI_XPAY>(S, N, nt, a, st, ev);
+        case EPI_XPAY_DOT: return dispatch_epi<P, EPI_XPAY_DOT>(S, N, nt, a, st, ev);
         case EPI_RESID:
-            if constexpr (P == P64) return dispatch_epi<P, EPI_RESID>(S, N, nt, a, st);
+            if constexpr (P == P64) return dispatch_epi<P, EPI_RESID>(S, N, nt, a, st, ev);
             return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }

@@ -116,12 +116,20 @@ struct stag_engine {
     // low-precision vectors [N]
     void *y32 = nullptr, *rs = nullptr, *d = nullptr, *t = nullptr, *Ad = nullptr;
     size_t rs64 = 0, rsP = 0, rs32 = 0;
-    stag::RhsState* st = nullptr;                  // device [N]
+    // Device state [N]. st is the state between K-iteration blocks (what the
+    // host polls and what the fix-up kernels work on); inside a block the
+    // state moves st -> st1 -> st as each reduction is finalised by the
+    // kernel that consumes it.
+    stag::RhsState* st = nullptr;
+    stag::RhsState* st1 = nullptr;
     stag::RhsState* host[2] = {nullptr, nullptr};  // pinned poll buffers [N]
     stag::RhsState* hstage = nullptr;              // pinned slot-start staging [N]
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // Chunk partials [N][nparts]: partials holds <d, A d> (and every
+    // reduction outside the iteration), partials1 the |r|^2 of the update,
+    // so a consumer reads one while writing the other.
     double* partials = nullptr;
-    unsigned* counter = nullptr;
+    double* partials1 = nullptr;
     size_t bytes = 0;
     std::map<long long, stag::GraphSet> graphs;    // key: (K, kernel N, timed)
     hipStream_t cap_stream = nullptr;              // idle stream the graphs are captured on
@@ -194,6 +202,9 @@ void set_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh, const HopTune& t);
 // Engines (solver.cpp)
 int engine_acquire(stag_ctx* ctx, const stag_gauge* g, int prec, int N, stag_engine** out);
 void engine_release(stag_engine* e);
+// Average execution time (us) of the three iteration kernels of e under
+// tuning t (stage 1, stage 2, update), with the first nrhs slots active.
+int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps, double* us);
 void engine_destroy(stag_engine* e);
 void engine_drop_graphs(stag_engine* e);
 
@@ -212,6 +223,7 @@ hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, con
                        const void* in, size_t in_rs, void* out, size_t out_rs, int p_out,
                        const void* x, size_t x_rs, const void* b, size_t b_rs, const double* m2,
                        RhsState* st, unsigned run_mask, const Reduce* red, hipStream_t stream,
-                       const void* lazy_r = nullptr, size_t lazy_r_rs = 0);
+                       const void* lazy_r = nullptr, size_t lazy_r_rs = 0,
+                       const Reduce* fin = nullptr, const LaunchEvents* ev = nullptr);
 
 }  // namespace stag

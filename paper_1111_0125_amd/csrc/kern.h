@@ -1,6 +1,6 @@
 // Device helpers for the libstag kernels: storage codecs per precision,
-// coalesced loads, deterministic block reductions with a last-block
-// finalisation of the CG scalars.
+// coalesced loads, deterministic reductions whose consumers finalise the
+// CG scalars.
 #pragma once
 
 #include "common.h"
@@ -361,12 +361,14 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
 
 // Reduction partials are taken over fixed chunks of 64 consecutive sites,
 // whatever the launch shape, and each chunk is summed by the same butterfly
-// over the site index; a separate one-block kernel (k_finalize) then sums
-// the chunk partials in index order. The result is therefore independent of
-// how many lanes serve a site and of how many right-hand sides share the
-// kernel. No block waits for another and no atomics are used: on this chip
-// cross-block atomics serialise (tens of ns per block), which made an
-// in-kernel "last block finalises" tail cost several microseconds.
+// over the site index; the consumer of a reduction then sums the chunk
+// partials of each right-hand side with one wavefront in a fixed order
+// (wave_sum_partials). The result is therefore independent of how many
+// lanes serve a site, of how many right-hand sides share the kernel and of
+// which kernel forms the sum. No block waits for another and no atomics are
+// used: on this chip cross-block atomics serialise (tens of ns per block),
+// which made an in-kernel "last block finalises" tail cost several
+// microseconds.
 constexpr int kChunk = 64;
 
 // v[r] is the value of the site handled by this thread (meaningful on the
@@ -407,29 +409,72 @@ __device__ __forceinline__ void block_chunk_partials(double (&v)[N], const Reduc
     }
 }
 
-// Fixed-order sum of the chunk partials of every RHS whose flags match
-// run_mask, then the finalisation; run by one block of kBlock threads after
-// the producing kernel has finished.
-template <int N>
-__device__ __forceinline__ void sum_partials_finalize(const Reduce& R, unsigned run_mask) {
-    __shared__ double red[kBlock / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int NW = kBlock / 64;
-    for (int r = 0; r < N; ++r) {
-        if (R.st && !(R.st[r].flags & run_mask)) continue;  // uniform over the block
-        const double* pp = R.partials + (size_t)r * R.nparts;
-        double x = 0.0;
-        for (int i = threadIdx.x; i < R.nparts; i += kBlock) x += pp[i];
+// Fixed-order sum of one right-hand side's chunk partials by one
+// wavefront: lane l accumulates partials l, l + 64, l + 128, ... into four
+// interleaved running sums, combined as (s0 + s1) + (s2 + s3) and then
+// across the wave by a butterfly. Every lane returns the same value (each
+// exchange adds the same two numbers on both partners).
+__device__ __forceinline__ double wave_sum_partials(const double* pp, int nparts) {
+    const int lane = threadIdx.x & 63;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = lane;
+    for (; i + 192 < nparts; i += 256) {
+        s0 += pp[i];
+        s1 += pp[i + 64];
+        s2 += pp[i + 128];
+        s3 += pp[i + 192];
+    }
+    if (i < nparts) s0 += pp[i];
+    if (i + 64 < nparts) s1 += pp[i + 64];
+    if (i + 128 < nparts) s2 += pp[i + 128];
+    double x = (s0 + s1) + (s2 + s3);
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-        if (lane == 0) red[wave] = x;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int w = 0; w < NW; ++w) t += red[w];
-            finalize_one(R.kind, R.st ? R.st + r : nullptr, t, R.out ? R.out + r : nullptr);
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+static_assert(sizeof(RhsState) % 8 == 0, "RhsState is copied as 8-byte words");
+constexpr int kStateWords = (int)(sizeof(RhsState) / 8);
+
+// Copy the first N states to LDS (block-wide; ends with a barrier).
+template <int N>
+__device__ __forceinline__ void load_state(const RhsState* st, RhsState* ls) {
+    const unsigned long long* src = (const unsigned long long*)st;
+    unsigned long long* dst = (unsigned long long*)ls;
+    for (int i = threadIdx.x; i < N * kStateWords; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+}
+
+// Finalise reduction R for the first N right-hand sides, block-wide: the
+// states are read from R.st into LDS (ls), every RHS whose flags match
+// run_mask gets its partials summed (wave w takes RHS w, w + 4, ...) and
+// R.kind applied to its LDS copy; then block 0 writes all N states to
+// R.st_out (or back to R.st). Every block of a many-block consumer computes
+// the same states, bit for bit, and uses its LDS copy; R.st is never
+// written by such a kernel, so late blocks read the same input. With R.st
+// null only FIN_STORE is meaningful: block 0 stores the sums to R.out.
+template <int N>
+__device__ __forceinline__ void finalize_block(const Reduce& R, unsigned run_mask, RhsState* ls) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nw = blockDim.x >> 6;
+    if (!R.st) {
+        for (int r = wave; r < N; r += nw) {
+            const double sum = wave_sum_partials(R.partials + (size_t)r * R.nparts, R.nparts);
+            if (lane == 0 && blockIdx.x == 0 && R.out) R.out[r] = sum;
         }
-        __syncthreads();
+        return;
+    }
+    load_state<N>(R.st, ls);
+    for (int r = wave; r < N; r += nw) {
+        if (!(ls[r].flags & run_mask)) continue;  // uniform over the wave
+        const double sum = wave_sum_partials(R.partials + (size_t)r * R.nparts, R.nparts);
+        if (lane == 0) finalize_one(R.kind, ls + r, sum, blockIdx.x == 0 && R.out ? R.out + r : nullptr);
+    }
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        unsigned long long* dst = (unsigned long long*)(R.st_out ? R.st_out : R.st);
+        const unsigned long long* src = (const unsigned long long*)ls;
+        for (int i = threadIdx.x; i < N * kStateWords; i += blockDim.x) dst[i] = src[i];
     }
 }
 

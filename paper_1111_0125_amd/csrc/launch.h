@@ -39,7 +39,12 @@ struct HopArgs {
     int p_out;
     int swizzle;
     Geom g;
-    Reduce red;
+    Reduce red;            // XPAY_DOT / RESID: where the chunk partials go
+    // Reduction finalised at kernel start (fin.partials null: none): every
+    // block sums fin's partials, applies fin.kind to an LDS copy of st and
+    // uses that; block 0 writes it to fin.st_out (fin.st is ignored, st is
+    // the input state).
+    Reduce fin;
 };
 
 // Vector (BLAS-like) kernels of the CG iteration; one thread per site.
@@ -60,12 +65,21 @@ struct VecArgs {
     RhsState* st;
     unsigned run_mask;
     int swizzle;
-    Reduce red;
+    Reduce red;        // INIT_B / UPD_*: where the chunk partials go
+    Reduce fin;        // finalised at kernel start, as in HopArgs
+};
+
+// Optional events recorded at the start and the end of one kernel's
+// execution (hipExtLaunchKernel), for timing single launches.
+struct LaunchEvents {
+    hipEvent_t start;
+    hipEvent_t stop;
 };
 
 hipError_t launch_hop(int prec, int S, int N, int epi, bool nt, const HopArgs& a,
-                      hipStream_t stream);
-hipError_t launch_vec(int prec, int N, int op, const VecArgs& a, hipStream_t stream);
+                      hipStream_t stream, const LaunchEvents* ev = nullptr);
+hipError_t launch_vec(int prec, int N, int op, const VecArgs& a, hipStream_t stream,
+                      const LaunchEvents* ev = nullptr);
 // One-block fixed-order sum of a reduction kernel's chunk partials and its
 // finalisation (R.kind), for the RHS whose flags match run_mask; launched
 // right after the kernel that wrote the partials, with the same run_mask.

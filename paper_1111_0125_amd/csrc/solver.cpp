@@ -3,12 +3,13 @@
 // updates, direction carried over as in Eq.6), for a block of right-hand
 // sides ("slots") that share every link load.
 //
-// All CG scalars live on the device (RhsState) and are produced by the last
-// block of each reduction, so an iteration is three kernels with no host
-// round trip. The host enqueues blocks of K iterations (one HIP graph
-// replay), polls the per-slot flags one block behind the device, and
-// enqueues the fp64 true-residual work only when a flag asks for it; those
-// kernels are predicated on the flags, so a redundant enqueue is a no-op.
+// All CG scalars live on the device (RhsState); each reduction is finalised
+// at the start of the kernel that consumes it, so an iteration is three
+// kernels with no host round trip. The host enqueues blocks of K iterations
+// (one HIP graph replay), polls the per-slot flags one block behind the
+// device, and enqueues the fp64 true-residual work only when a flag asks for
+// it; those kernels are predicated on the flags, so a redundant enqueue is a
+// no-op.
 //
 // Slots are independent: a slot can start (from x = 0) at any block
 // boundary while others are mid-solve, and its arithmetic does not depend on
@@ -44,7 +45,7 @@ void engine_destroy(stag_engine* e) {
     stag_ctx* ctx = e->ctx;
     engine_drop_graphs(e);
     void* bufs[] = {e->x64, e->r64, e->t64, e->d64, e->Ad64, e->y32, e->rs, e->d, e->t, e->Ad,
-                    e->b64, e->st, e->partials};
+                    e->b64, e->st, e->st1, e->partials, e->partials1};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     for (int i = 0; i < 2; ++i) {
@@ -76,7 +77,9 @@ int engine_create(stag_ctx* ctx, const stag_gauge* g, int prec, int N, bool own_
     };
     std::vector<Req> reqs = {
         {&e->x64, N * e->rs64}, {&e->r64, N * e->rs64}, {&e->t64, N * e->rs64},
-        {(void**)&e->st, state_bytes(N)}, {(void**)&e->partials, N * nparts * sizeof(double)},
+        {(void**)&e->st, state_bytes(N)}, {(void**)&e->st1, state_bytes(N)},
+        {(void**)&e->partials, N * nparts * sizeof(double)},
+        {(void**)&e->partials1, N * nparts * sizeof(double)},
     };
     if (own_b) reqs.push_back({&e->b64, N * e->rs64});
     if (prec == P64) {
@@ -125,6 +128,7 @@ int engine_create(stag_ctx* ctx, const stag_gauge* g, int prec, int N, bool own_
     // which does not order against the non-blocking streams the solves use:
     // wait for it here.
     hipError_t err = hipMemset(e->st, 0, state_bytes(N));
+    if (err == hipSuccess) err = hipMemset(e->st1, 0, state_bytes(N));
     if (err == hipSuccess && e->d64) err = hipMemset(e->d64, 0, N * e->rs64);
     if (err == hipSuccess && e->d) err = hipMemset(e->d, 0, N * e->rsP);
     if (err == hipSuccess && e->y32) err = hipMemset(e->y32, 0, N * e->rs32);
@@ -203,37 +207,50 @@ hipError_t timed_launch(const Ctx& c, int kind, F&& fn) {
     return timing_end(c.e->ctx, c.s, kind, a);
 }
 
-Reduce make_red(stag_engine* e, int kind) {
+Reduce make_red(stag_engine* e, int kind, double* partials = nullptr) {
     Reduce r{};
-    r.partials = e->partials;
+    r.partials = partials ? partials : e->partials;
     r.st = e->st;
     r.out = nullptr;
+    r.st_out = nullptr;
     r.kind = kind;
     r.nparts = (int)num_chunks(e->Vh);
     return r;
 }
 
+// Optional pieces of a kernel launch inside the solver.
+struct Opt {
+    RhsState* st = nullptr;          // state read (null: e->st)
+    const Reduce* fin = nullptr;     // reduction finalised at kernel start
+    bool finalize = true;            // finalise this kernel's reduction right after it
+    double* partials = nullptr;      // where this kernel's partials go (null: e->partials)
+};
+
+// A hop stage. With Opt::finalize, a reduction it produces (XPAY_DOT,
+// RESID) is finalised in place on e->st by a one-block kernel right after.
 hipError_t hop(const Ctx& c, int prec, int stage, int epi, const void* in, void* out,
-               const void* x, int kind, unsigned run, const void* lazy_r = nullptr) {
+               const void* x, int kind, unsigned run, const void* lazy_r = nullptr,
+               const Opt& o = Opt()) {
     stag_engine* e = c.e;
     const HopTune& t = prec == P64 && e->prec != P64 ? e->tune_64 : e->tune_lo;
     int S = stage == 1 ? t.S1 : t.S2;
     if (c.nk > 1) S = 1;
     const size_t rs = spinor_rhs_bytes(prec, e->Vh);
-    Reduce red = make_red(e, kind);
+    Reduce red = make_red(e, kind, o.partials);
+    RhsState* st = o.st ? o.st : e->st;
     const int p_out = stage == 1 ? 1 : 0;
     const int kk = prec == e->prec && run == F_ACTIVE ? (stage == 1 ? KK_HOP1 : KK_HOP2)
                                                        : (stage == 1 ? KK_HOP1_64 : KK_HOP2_64);
     hipError_t err = timed_launch(c, kk, [&]() {
         return enqueue_hop(e->gauge, prec, S, c.nk, epi, t, in, rs, out, rs, p_out, x, rs, c.b,
-                           c.b_rs, nullptr, e->st, run, &red, c.s, lazy_r, rs);
+                           c.b_rs, nullptr, st, run, &red, c.s, lazy_r, rs, o.fin);
     });
-    if (err != hipSuccess || !(epi == EPI_XPAY_DOT || epi == EPI_RESID)) return err;
+    if (err != hipSuccess || !o.finalize || !(epi == EPI_XPAY_DOT || epi == EPI_RESID)) return err;
     return timed_launch(c, KK_OTHER, [&]() { return launch_finalize(c.nk, red, run, c.s); });
 }
 
 hipError_t vec(const Ctx& c, int prec, int op, std::initializer_list<std::pair<void*, size_t>> f,
-               int kind, unsigned run) {
+               int kind, unsigned run, const Opt& o = Opt()) {
     stag_engine* e = c.e;
     VecArgs a{};
     int k = 0;
@@ -243,40 +260,78 @@ hipError_t vec(const Ctx& c, int prec, int op, std::initializer_list<std::pair<v
         ++k;
     }
     a.Vh = e->Vh;
-    a.st = e->st;
+    a.st = o.st ? o.st : e->st;
     a.run_mask = run;
     a.swizzle = e->tune_lo.swizzle;
-    a.red = make_red(e, kind);
+    a.red = make_red(e, kind, o.partials);
+    if (o.fin) a.fin = *o.fin;
     const int kk = op == OP_UPD_CG || op == OP_UPD_MIXED ? KK_UPDATE : KK_OTHER;
     hipError_t err = timed_launch(c, kk, [&]() { return launch_vec(prec, c.nk, op, a, c.s); });
-    if (err != hipSuccess || !(op == OP_INIT_B || op == OP_UPD_CG || op == OP_UPD_MIXED)) return err;
+    if (err != hipSuccess || !o.finalize || !(op == OP_INIT_B || op == OP_UPD_CG || op == OP_UPD_MIXED))
+        return err;
     return timed_launch(c, KK_OTHER, [&]() { return launch_finalize(c.nk, a.red, run, c.s); });
 }
 
-// One CG iteration (Fig.1): three work kernels and two one-block reduction
-// finalisations (alpha after stage 2, beta and the decisions after the
-// update). The direction update
-// d = r + beta d of the previous iteration is deferred into the two hop
-// stages (stage 1 forms it at the neighbours it gathers, stage 2 at its own
-// site, storing it), so no separate pass over d is needed.
-hipError_t enqueue_iteration(const Ctx& c) {
+// Kernel launches of one K-iteration block.
+constexpr int kKernelsPerIteration = 3;
+inline size_t block_launches(int K) { return (size_t)K * kKernelsPerIteration + 1; }
+
+// K CG iterations (Fig.1; Sec.3.2 for a low-precision inner solve), three
+// kernels each:
+//   stage 1  t = D_oe d, where d = r + beta d (the previous iteration's
+//            direction update, deferred) is formed at every neighbour;
+//   stage 2  d stored, Ad = m^2 d - D_eo t, chunk partials of <d, Ad>;
+//   update   alpha = |r|^2 / <d, Ad> finalised at kernel start, x (or y)
+//            += alpha d, r -= alpha Ad, chunk partials of |r|^2.
+// The |r|^2 of one update is finalised (beta, convergence and update
+// triggers) at the start of the next iteration's stage 1, and by a one-block
+// kernel after the last iteration, which leaves the state in e->st. A
+// many-block kernel that finalises reads one state buffer and its block 0
+// writes the other (update: st -> st1, stage 1: st1 -> st), and the two
+// reductions use separate partial buffers, so no kernel reads what it
+// writes.
+hipError_t enqueue_iterations(const Ctx& c, int K) {
     stag_engine* e = c.e;
-    hipError_t err;
-    if (e->prec == P64) {
-        if ((err = hop(c, P64, 1, EPI_PLAIN, e->d64, e->t64, nullptr, FIN_STORE, F_ACTIVE, e->r64)))
-            return err;
-        if ((err = hop(c, P64, 2, EPI_XPAY_DOT, e->t64, e->Ad64, e->d64, FIN_ALPHA, F_ACTIVE, e->r64)))
-            return err;
-        return vec(c, P64, OP_UPD_CG,
-                   {{e->x64, e->rs64}, {e->r64, e->rs64}, {e->d64, e->rs64}, {e->Ad64, e->rs64}},
-                   FIN_CG, F_ACTIVE);
-    }
+    const bool mixed = e->prec != P64;
     const int P = e->prec;
-    if ((err = hop(c, P, 1, EPI_PLAIN, e->d, e->t, nullptr, FIN_STORE, F_ACTIVE, e->rs))) return err;
-    if ((err = hop(c, P, 2, EPI_XPAY_DOT, e->t, e->Ad, e->d, FIN_ALPHA, F_ACTIVE, e->rs))) return err;
-    return vec(c, P, OP_UPD_MIXED,
-               {{e->y32, e->rs32}, {e->rs, e->rsP}, {e->d, e->rsP}, {e->Ad, e->rsP}}, FIN_MIXED,
-               F_ACTIVE);
+    const int kind_r = mixed ? FIN_MIXED : FIN_CG;
+    void* d = mixed ? e->d : e->d64;
+    void* t = mixed ? e->t : e->t64;
+    void* ad = mixed ? e->Ad : e->Ad64;
+    void* r = mixed ? e->rs : e->r64;
+    Reduce pend_r = make_red(e, kind_r, e->partials1);
+    pend_r.st = e->st1;
+    pend_r.st_out = e->st;
+    Reduce pend_a = make_red(e, FIN_ALPHA, e->partials);
+    pend_a.st = e->st;
+    pend_a.st_out = e->st1;
+    hipError_t err;
+    for (int k = 0; k < K; ++k) {
+        Opt o1;
+        if (k > 0) {
+            o1.st = e->st1;
+            o1.fin = &pend_r;
+        }
+        if ((err = hop(c, P, 1, EPI_PLAIN, d, t, nullptr, FIN_STORE, F_ACTIVE, r, o1))) return err;
+        Opt o2;
+        o2.finalize = false;
+        if ((err = hop(c, P, 2, EPI_XPAY_DOT, t, ad, d, FIN_ALPHA, F_ACTIVE, r, o2))) return err;
+        Opt ou;
+        ou.fin = &pend_a;
+        ou.finalize = false;
+        ou.partials = e->partials1;
+        if (mixed) {
+            err = vec(c, P, OP_UPD_MIXED,
+                      {{e->y32, e->rs32}, {e->rs, e->rsP}, {e->d, e->rsP}, {e->Ad, e->rsP}},
+                      kind_r, F_ACTIVE, ou);
+        } else {
+            err = vec(c, P64, OP_UPD_CG,
+                      {{e->x64, e->rs64}, {e->r64, e->rs64}, {e->d64, e->rs64}, {e->Ad64, e->rs64}},
+                      kind_r, F_ACTIVE, ou);
+        }
+        if (err) return err;
+    }
+    return timed_launch(c, KK_OTHER, [&]() { return launch_finalize(c.nk, pend_r, F_ACTIVE, c.s); });
 }
 
 hipError_t state_step(const Ctx& c, int kind, unsigned run) {
@@ -417,7 +472,7 @@ static int get_graphs(EngineRun& R, int nk, GraphSet** out) {
     for (int inst = 0; inst < ninst && ok; ++inst) {
         Ctx cc{e, cs, R.b, R.b_rs, nk, R.timed, nullptr, 0};
         if (R.timed) {
-            gs.ev[inst].resize((size_t)R.K * 5);  // five kernels per iteration
+            gs.ev[inst].resize(block_launches(R.K));
             for (auto& r : gs.ev[inst]) {
                 r.a = r.b = nullptr;
                 if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) ok = false;
@@ -433,8 +488,7 @@ static int get_graphs(EngineRun& R, int nk, GraphSet** out) {
             ok = false;
             break;
         }
-        hipError_t cerr = hipSuccess;
-        for (int k = 0; k < R.K && cerr == hipSuccess; ++k) cerr = enqueue_iteration(cc);
+        hipError_t cerr = enqueue_iterations(cc, R.K);
         hipError_t eerr = hipStreamEndCapture(cs, &graph);
         hipError_t ierr = hipErrorInvalidValue;
         if (cerr == hipSuccess && eerr == hipSuccess && graph)
@@ -488,7 +542,7 @@ int run_enqueue_block(EngineRun& R) {
         R.block_inst[buf] = inst;
     } else {
         Ctx c{e, R.s, R.b, R.b_rs, nk, R.timed, nullptr, 0};
-        for (int k = 0; k < R.K; ++k) RCK(enqueue_iteration(c));
+        RCK(enqueue_iterations(c, R.K));
         R.block_graph[buf] = nullptr;
     }
     RCK(hipMemcpyAsync(e->host[buf], e->st, state_bytes(e->N), hipMemcpyDeviceToHost, R.s));
@@ -619,23 +673,20 @@ int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, siz
 
 // ------------------------------------------------------------------ kernel timing
 
-using namespace stag;
+namespace stag {
 
-extern "C" int stag_time_kernels(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, int reps,
-                                 double* us_out) {
-    if (!ctx) return STAG_EINVAL;
-    if (!g || !us_out || prec < 0 || prec > 2 || nrhs < 1 || nrhs > STAG_MAX_RHS || reps < 1)
-        return set_error(ctx, STAG_EINVAL, "stag_time_kernels: bad argument");
-    if (!(g->mask & (1 << prec)) || !(g->mask & STAG_MASK_F64))
-        return set_error(ctx, STAG_EINVAL, "stag_time_kernels: gauge lacks a needed copy");
-    DeviceGuard dg(ctx->device);
-    const int N = pick_n(nrhs);
-    stag_engine* e = nullptr;
-    int rc = engine_acquire(ctx, g, prec, N, &e);
-    if (rc) return rc;
+// Average execution time (microseconds, from events recorded at the start
+// and the end of each kernel) of the three iteration kernels of engine e
+// with tuning t, over `reps` launches each: stage 1 (finalising the
+// previous |r|^2), stage 2, update (finalising alpha). All of the first
+// nrhs slots are active with alpha = beta = 0, so d = r and every vector
+// stays put, and the finalisations are FIN_STORE, so the state, and with it
+// the work, is the same on every launch. The state is cleared afterwards.
+int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps, double* us) {
+    stag_ctx* ctx = e->ctx;
+    const stag_gauge* g = e->gauge;
+    const int N = e->N, prec = e->prec;
     hipStream_t s = ctx->stream;
-    // every slot active with alpha = beta = 0 (so d = r and the vectors stay
-    // put); reductions store their sums instead of changing the state
     for (int r = 0; r < N; ++r) {
         RhsState& st = e->hstage[r];
         std::memset(&st, 0, sizeof(st));
@@ -645,8 +696,11 @@ extern "C" int stag_time_kernels(stag_ctx* ctx, const stag_gauge* g, int prec, i
     }
     double* sink = nullptr;
     hipError_t err = hipMemcpyAsync(e->st, e->hstage, sizeof(RhsState) * N, hipMemcpyHostToDevice, s);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(e->st1, e->hstage, sizeof(RhsState) * N, hipMemcpyHostToDevice, s);
     if (err == hipSuccess) err = hipMallocAsync((void**)&sink, sizeof(double) * N, s);
     const size_t bytes[] = {N * e->rs64, N * e->rsP, N * e->rs32};
+    const size_t pbytes = sizeof(double) * N * num_chunks(e->Vh);
     void* zero64[] = {e->x64, e->r64, e->t64, e->d64, e->Ad64};
     void* zeroP[] = {e->rs, e->d, e->t, e->Ad};
     for (void* p : zero64)
@@ -654,15 +708,24 @@ extern "C" int stag_time_kernels(stag_ctx* ctx, const stag_gauge* g, int prec, i
     for (void* p : zeroP)
         if (err == hipSuccess && p) err = hipMemsetAsync(p, 0, bytes[1], s);
     if (err == hipSuccess && e->y32) err = hipMemsetAsync(e->y32, 0, bytes[2], s);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (err == hipSuccess) err = hipEventCreate(&e0);
-    if (err == hipSuccess) err = hipEventCreate(&e1);
-    Ctx c{e, s, nullptr, 0, N, false, nullptr, 0};
+    if (err == hipSuccess) err = hipMemsetAsync(e->partials, 0, pbytes, s);
+    if (err == hipSuccess) err = hipMemsetAsync(e->partials1, 0, pbytes, s);
+    std::vector<LaunchEvents> ev((size_t)reps, LaunchEvents{nullptr, nullptr});
+    for (auto& v : ev) {
+        if (err == hipSuccess) err = hipEventCreate(&v.start);
+        if (err == hipSuccess) err = hipEventCreate(&v.stop);
+    }
     const bool mixed = prec != P64;
-    auto one = [&](int which) -> hipError_t {
+    Reduce pend_r = make_red(e, FIN_STORE, e->partials1);
+    pend_r.st = e->st1;
+    pend_r.st_out = e->st;
+    pend_r.out = sink;
+    Reduce pend_a = make_red(e, FIN_STORE, e->partials);
+    pend_a.st = e->st;
+    pend_a.st_out = e->st1;
+    pend_a.out = sink;
+    auto one = [&](int which, const LaunchEvents* le) -> hipError_t {
         Reduce red = make_red(e, FIN_STORE);
-        red.out = sink;
-        const HopTune& t = e->tune_lo;
         const size_t rs = mixed ? e->rsP : e->rs64;
         void* dd = mixed ? e->d : e->d64;
         void* rr = mixed ? e->rs : e->r64;
@@ -670,10 +733,11 @@ extern "C" int stag_time_kernels(stag_ctx* ctx, const stag_gauge* g, int prec, i
         void* ad = mixed ? e->Ad : e->Ad64;
         if (which == 0)
             return enqueue_hop(g, prec, N > 1 ? 1 : t.S1, N, EPI_PLAIN, t, dd, rs, tt, rs, 1, nullptr,
-                               0, nullptr, 0, nullptr, e->st, F_ACTIVE, nullptr, s, rr, rs);
+                               0, nullptr, 0, nullptr, e->st1, F_ACTIVE, nullptr, s, rr, rs, &pend_r,
+                               le);
         if (which == 1)
             return enqueue_hop(g, prec, N > 1 ? 1 : t.S2, N, EPI_XPAY_DOT, t, tt, rs, ad, rs, 0, dd,
-                               rs, nullptr, 0, nullptr, e->st, F_ACTIVE, &red, s, rr, rs);
+                               rs, nullptr, 0, nullptr, e->st, F_ACTIVE, &red, s, rr, rs, nullptr, le);
         VecArgs a{};
         if (mixed) {
             void* f[] = {e->y32, e->rs, e->d, e->Ad};
@@ -692,31 +756,57 @@ extern "C" int stag_time_kernels(stag_ctx* ctx, const stag_gauge* g, int prec, i
         a.Vh = e->Vh;
         a.st = e->st;
         a.run_mask = F_ACTIVE;
-        a.swizzle = e->tune_lo.swizzle;
-        a.red = red;
-        return launch_vec(prec, N, mixed ? OP_UPD_MIXED : OP_UPD_CG, a, s);
+        a.swizzle = t.swizzle;
+        a.red = make_red(e, FIN_STORE, e->partials1);
+        a.fin = pend_a;
+        return launch_vec(prec, N, mixed ? OP_UPD_MIXED : OP_UPD_CG, a, s, le);
     };
     for (int which = 0; which < 3 && err == hipSuccess; ++which) {
-        for (int i = 0; i < 3 && err == hipSuccess; ++i) err = one(which);  // warm-up
-        if (err == hipSuccess) err = hipEventRecord(e0, s);
-        for (int i = 0; i < reps && err == hipSuccess; ++i) err = one(which);
-        if (err == hipSuccess) err = hipEventRecord(e1, s);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        us_out[which] = ms * 1e3 / reps;
+        for (int i = 0; i < 3 && err == hipSuccess; ++i) err = one(which, nullptr);  // warm-up
+        for (int i = 0; i < reps && err == hipSuccess; ++i) err = one(which, &ev[(size_t)i]);
+        if (err == hipSuccess) err = hipStreamSynchronize(s);
+        double tot = 0.0;
+        for (int i = 0; i < reps && err == hipSuccess; ++i) {
+            float ms = 0.f;
+            err = hipEventElapsedTime(&ms, ev[(size_t)i].start, ev[(size_t)i].stop);
+            tot += ms;
+        }
+        us[which] = tot * 1e3 / reps;
     }
     if (sink) (void)hipFreeAsync(sink, s);
     (void)hipStreamSynchronize(s);
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
+    for (auto& v : ev) {
+        if (v.start) (void)hipEventDestroy(v.start);
+        if (v.stop) (void)hipEventDestroy(v.stop);
+    }
     // the state was overwritten: mark every slot free for the next solve
     (void)hipMemsetAsync(e->st, 0, sizeof(RhsState) * N, s);
+    (void)hipMemsetAsync(e->st1, 0, sizeof(RhsState) * N, s);
     (void)hipStreamSynchronize(s);
-    engine_release(e);
     if (err != hipSuccess) {
         (void)hipGetLastError();
-        return set_error(ctx, STAG_EDEVICE, "stag_time_kernels: %s", hipGetErrorString(err));
+        return set_error(ctx, STAG_EDEVICE, "kernel timing: %s", hipGetErrorString(err));
     }
     return STAG_OK;
+}
+
+}  // namespace stag
+
+using namespace stag;
+
+extern "C" int stag_time_kernels(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, int reps,
+                                 double* us_out) {
+    if (!ctx) return STAG_EINVAL;
+    if (!g || !us_out || prec < 0 || prec > 2 || nrhs < 1 || nrhs > STAG_MAX_RHS || reps < 1 ||
+        reps > 100000)
+        return set_error(ctx, STAG_EINVAL, "stag_time_kernels: bad argument");
+    if (!(g->mask & (1 << prec)) || !(g->mask & STAG_MASK_F64))
+        return set_error(ctx, STAG_EINVAL, "stag_time_kernels: gauge lacks a needed copy");
+    DeviceGuard dg(ctx->device);
+    stag_engine* e = nullptr;
+    int rc = engine_acquire(ctx, g, prec, pick_n(nrhs), &e);
+    if (rc) return rc;
+    rc = time_iteration_kernels(e, e->tune_lo, nrhs, reps, us_out);
+    engine_release(e);
+    return rc;
 }

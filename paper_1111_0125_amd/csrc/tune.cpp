@@ -150,105 +150,54 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, stag_tune_
     DeviceGuard dg(ctx->device);
     const int N = pick_n(nrhs);
     const uint32_t Vh = g->g.Vh;
-    const size_t rs = spinor_rhs_bytes(prec, Vh);
-    void *in = nullptr, *t = nullptr, *out = nullptr;
-    double* partials = nullptr;
-    RhsState* st = nullptr;
-    hipStream_t s = ctx->stream;
-    auto cleanup = [&]() {
-        void* ps[] = {in, t, out, partials, st};
-        for (void* p : ps)
-            if (p) (void)hipFree(p);
-    };
-    if (hipMalloc(&in, rs * N) != hipSuccess || hipMalloc(&t, rs * N) != hipSuccess ||
-        hipMalloc(&out, rs * N) != hipSuccess ||
-        hipMalloc((void**)&partials, sizeof(double) * N * num_chunks(Vh)) != hipSuccess ||
-        hipMalloc((void**)&st, sizeof(RhsState) * N) != hipSuccess) {
-        (void)hipGetLastError();
-        cleanup();
-        return set_error(ctx, STAG_ENOMEM, "stag_tune: workspace allocation failed");
-    }
-    std::vector<RhsState> hst(N);
-    std::memset(hst.data(), 0, sizeof(RhsState) * N);
-    for (int r = 0; r < N; ++r) {
-        hst[r].m2 = 0.01;
-        hst[r].flags = F_ACTIVE;
-        hst[r].rr = 1.0;
-    }
-    (void)hipMemset(in, 0, rs * N);
-    (void)hipMemcpy(st, hst.data(), sizeof(RhsState) * N, hipMemcpyHostToDevice);
-    (void)hipDeviceSynchronize();  // the null-stream writes above must land before s runs
-    Reduce red{};
-    red.partials = partials;
-    red.st = st;
-    red.kind = FIN_STORE;
-    red.nparts = (int)num_chunks(Vh);
-    double* outv = nullptr;
-    (void)hipMalloc((void**)&outv, sizeof(double) * N);
-    red.out = outv;
-
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    // time the solver's own iteration kernels (deferred direction update,
+    // finalisations at kernel start) on a solver workspace of this shape
+    stag_engine* e = nullptr;
+    int rc = engine_acquire(ctx, g, prec, N, &e);
+    if (rc) return rc;
     const int reps = Vh >= 262144 ? 10 : 30;
-    auto time_stage = [&](int stage, const HopTune& tu, int S) -> double {
-        auto launch = [&]() -> hipError_t {
-            if (stage == 1)
-                return enqueue_hop(g, prec, S, N, EPI_PLAIN, tu, in, rs, t, rs, 1, nullptr, 0,
-                                   nullptr, 0, nullptr, nullptr, 0, nullptr, s);
-            return enqueue_hop(g, prec, S, N, EPI_XPAY_DOT, tu, t, rs, out, rs, 0, in, rs, nullptr,
-                               0, nullptr, st, F_ACTIVE, &red, s);
-        };
-        if (launch() != hipSuccess) return 1e30;
-        (void)hipEventRecord(e0, s);
-        for (int i = 0; i < reps; ++i) (void)launch();
-        (void)hipEventRecord(e1, s);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        (void)hipGetLastError();
-        return ms / reps;
+    auto time_cfg = [&](const HopTune& tu, double* us) -> int {
+        return time_iteration_kernels(e, tu, nrhs, reps, us);
     };
     HopTune bestT;
-    double best1 = 1e30, best2 = 1e30;
+    double best1 = 1e30, best2 = 1e30, best3 = 1e30;
     const int Ss[] = {1, 2, 4};
-    for (int nt = 0; nt <= 1; ++nt)
-        for (int sw = 0; sw <= 1; ++sw)
+    for (int nt = 0; nt <= 1 && rc == STAG_OK; ++nt)
+        for (int sw = 0; sw <= 1 && rc == STAG_OK; ++sw)
             for (int S : Ss) {
                 if (N > 1 && S != 1) continue;
                 HopTune tu;
                 tu.nt = nt;
                 tu.swizzle = sw;
                 tu.S1 = tu.S2 = S;
-                const double t1 = time_stage(1, tu, S);
-                const double t2 = time_stage(2, tu, S);
-                // one (nt, swizzle) pair serves both stages; S is per stage
-                if (t1 + t2 < best1 + best2) {
-                    best1 = t1;
-                    best2 = t2;
+                double us[3];
+                if ((rc = time_cfg(tu, us))) break;
+                // one (nt, swizzle) pair serves all kernels; S is per stage
+                if (us[0] + us[1] + us[2] < best1 + best2 + best3) {
+                    best1 = us[0];
+                    best2 = us[1];
+                    best3 = us[2];
                     bestT = tu;
                 }
             }
     // refine S per stage with the chosen (nt, swizzle)
     for (int S : Ss) {
-        if (N > 1 && S != 1) continue;
+        if (rc != STAG_OK || (N > 1 && S != 1)) break;
         HopTune tu = bestT;
-        const double t1 = time_stage(1, tu, S);
-        if (t1 < best1) {
-            best1 = t1;
+        tu.S1 = tu.S2 = S;
+        double us[3];
+        if ((rc = time_cfg(tu, us))) break;
+        if (us[0] < best1) {
+            best1 = us[0];
             bestT.S1 = S;
         }
-        const double t2 = time_stage(2, tu, S);
-        if (t2 < best2) {
-            best2 = t2;
+        if (us[1] < best2) {
+            best2 = us[1];
             bestT.S2 = S;
         }
     }
-    (void)hipStreamSynchronize(s);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (outv) (void)hipFree(outv);
-    cleanup();
+    engine_release(e);
+    if (rc) return rc;
     set_tune(ctx, prec, N, Vh, bestT);
     apply_tune_to_engines(ctx);
     if (best) {
@@ -257,7 +206,7 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, stag_tune_
         best->nt = bestT.nt;
         best->swizzle = bestT.swizzle;
     }
-    if (best_ms) *best_ms = best1 + best2;
+    if (best_ms) *best_ms = (best1 + best2) * 1e-3;
     return STAG_OK;
 }
 
