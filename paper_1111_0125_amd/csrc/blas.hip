@@ -1,9 +1,10 @@
-// Vector kernels of the CG iteration (Fig.1 and Sec.3.2): fused axpy + norm
-// updates with fp64 reductions, the direction update, and the pieces of the
-// reliable / group-wise update. One thread per site handles every active
-// right-hand side of the block; the CG scalars come from the device-resident
-// per-RHS state, optionally finalised at kernel start from the partials of
-// the reduction that precedes the kernel.
+// Vector kernels of the CG iteration (Fig.1 and Sec.3.2): the start of a
+// solve and the fused axpy + norm updates with fp64 reductions. One thread
+// per site handles every active right-hand side of the block; the CG
+// scalars come from the device-resident per-RHS state, optionally finalised
+// at kernel start from the partials of the reduction that precedes the
+// kernel. Also the reduction finalisation kernel and the issue helper that
+// launches a kernel or appends it to a graph.
 #include <hip/hip_ext.h>
 
 #include "kern.h"
@@ -116,30 +117,6 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
                 for (int c = 0; c < 3; ++c)
                     acc += (double)sr[c] * (double)sr[c] + (double)si[c] * (double)si[c];
                 dv[r] = acc;
-            } else if constexpr (OP == OP_RU_BEGIN) {
-                // x64 += y; y = 0
-                double xr[3], xi[3];
-                float yr[3], yi[3], z[3] = {0.f, 0.f, 0.f}, zi[3] = {0.f, 0.f, 0.f};
-                load_site<P64>(slot(a, 0, r), Vh, s, xr, xi);
-                load_site<P32>(slot(a, 1, r), Vh, s, yr, yi);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    xr[c] += (double)yr[c];
-                    xi[c] += (double)yi[c];
-                }
-                store_site<P64>(slot(a, 0, r), Vh, s, xr, xi);
-                store_site<P32>(slot(a, 1, r), Vh, s, z, zi);
-            } else if constexpr (OP == OP_RU_END) {
-                // rs = q(r64): the low-precision residual restarts from the true one
-                double vr[3], vi[3];
-                load_site<P64>(slot(a, 0, r), Vh, s, vr, vi);
-                T sr[3], si[3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    sr[c] = (T)vr[c];
-                    si[c] = (T)vi[c];
-                }
-                store_site<P>(slot(a, 1, r), Vh, s, sr, si);
             } else if constexpr (OP == OP_ZERO) {
                 T z[3] = {T(0), T(0), T(0)}, zi[3] = {T(0), T(0), T(0)};
                 store_site<P>(slot(a, 0, r), Vh, s, z, zi);
@@ -151,62 +128,51 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
     }
 }
 
+template <int P, int N, int OP>
+static hipError_t issue_vec(const VecArgs& a, const Issue& is) {
+    VecArgs arg = a;
+    void* args[] = {&arg};
+    return issue_kernel(is, reinterpret_cast<const void*>(&k_vec<P, N, OP>), vec_blocks(a.Vh), kBlock,
+                        args);
+}
+
 template <int P, int N>
-static hipError_t run_vec_n(int op, const VecArgs& a, hipStream_t st, const LaunchEvents* ev) {
-    const dim3 grid(vec_blocks(a.Vh)), block(kBlock);
-#define STAG_VEC_CASE(OPV)                                                                 \
-    case OPV:                                                                              \
-        if (ev)                                                                            \
-            hipExtLaunchKernelGGL((k_vec<P, N, OPV>), grid, block, 0, st, ev->start,        \
-                                  ev->stop, 0, a);                                          \
-        else                                                                               \
-            hipLaunchKernelGGL((k_vec<P, N, OPV>), grid, block, 0, st, a);                 \
-        return hipGetLastError();
+static hipError_t run_vec_n(int op, const VecArgs& a, const Issue& is) {
     switch (op) {
-        STAG_VEC_CASE(OP_START)
-        STAG_VEC_CASE(OP_ZERO)
-        default:
-            break;
+        case OP_START: return issue_vec<P, N, OP_START>(a, is);
+        case OP_ZERO: return issue_vec<P, N, OP_ZERO>(a, is);
+        default: break;
     }
     if constexpr (P == P64) {
         switch (op) {
-            STAG_VEC_CASE(OP_INIT_B)
-            STAG_VEC_CASE(OP_UPD_CG)
-            default:
-                break;
+            case OP_INIT_B: return issue_vec<P, N, OP_INIT_B>(a, is);
+            case OP_UPD_CG: return issue_vec<P, N, OP_UPD_CG>(a, is);
+            default: break;
         }
     } else {
-        switch (op) {
-            STAG_VEC_CASE(OP_UPD_MIXED)
-            STAG_VEC_CASE(OP_RU_BEGIN)
-            STAG_VEC_CASE(OP_RU_END)
-            default:
-                break;
-        }
+        if (op == OP_UPD_MIXED) return issue_vec<P, N, OP_UPD_MIXED>(a, is);
     }
-#undef STAG_VEC_CASE
     return hipErrorInvalidValue;
 }
 
 template <int P>
-static hipError_t run_vec(int N, int op, const VecArgs& a, hipStream_t st, const LaunchEvents* ev) {
+static hipError_t run_vec(int N, int op, const VecArgs& a, const Issue& is) {
     switch (N) {
-        case 1: return run_vec_n<P, 1>(op, a, st, ev);
-        case 2: return run_vec_n<P, 2>(op, a, st, ev);
-        case 4: return run_vec_n<P, 4>(op, a, st, ev);
-        case 8: return run_vec_n<P, 8>(op, a, st, ev);
-        case 12: return run_vec_n<P, 12>(op, a, st, ev);
-        case 16: return run_vec_n<P, 16>(op, a, st, ev);
+        case 1: return run_vec_n<P, 1>(op, a, is);
+        case 2: return run_vec_n<P, 2>(op, a, is);
+        case 4: return run_vec_n<P, 4>(op, a, is);
+        case 8: return run_vec_n<P, 8>(op, a, is);
+        case 12: return run_vec_n<P, 12>(op, a, is);
+        case 16: return run_vec_n<P, 16>(op, a, is);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_vec(int prec, int N, int op, const VecArgs& a, hipStream_t st,
-                      const LaunchEvents* ev) {
+hipError_t launch_vec(int prec, int N, int op, const VecArgs& a, const Issue& is) {
     switch (prec) {
-        case P64: return run_vec<P64>(N, op, a, st, ev);
-        case P32: return run_vec<P32>(N, op, a, st, ev);
-        case P16S: return run_vec<P16S>(N, op, a, st, ev);
+        case P64: return run_vec<P64>(N, op, a, is);
+        case P32: return run_vec<P32>(N, op, a, is);
+        case P16S: return run_vec<P16S>(N, op, a, is);
         default: return hipErrorInvalidValue;
     }
 }
@@ -219,61 +185,61 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Reduce R, unsigned run_mask
     finalize_block<N>(R, run_mask, ls);
 }
 
-hipError_t launch_finalize(int N, const Reduce& R, unsigned run_mask, hipStream_t stream) {
-    switch (N) {
-#define STAG_FIN_CASE(n) \
-    case n: hipLaunchKernelGGL((k_finalize<n>), dim3(1), dim3(kBlock), 0, stream, R, run_mask); break;
-        STAG_FIN_CASE(1)
-        STAG_FIN_CASE(2)
-        STAG_FIN_CASE(4)
-        STAG_FIN_CASE(8)
-        STAG_FIN_CASE(12)
-        STAG_FIN_CASE(16)
-#undef STAG_FIN_CASE
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ state transitions
-
 template <int N>
-__global__ void k_state(RhsState* st, unsigned run_mask, int kind) {
-    const int r = threadIdx.x;
-    if (r < N && (st[r].flags & run_mask)) finalize_one(kind, st + r, 0.0, nullptr);
+static hipError_t issue_finalize(const Reduce& R, unsigned run_mask, const Issue& is) {
+    Reduce r = R;
+    unsigned m = run_mask;
+    void* args[] = {&r, &m};
+    return issue_kernel(is, reinterpret_cast<const void*>(&k_finalize<N>), 1, kBlock, args);
 }
 
-hipError_t launch_state(int N, int kind, RhsState* st, unsigned run_mask, hipStream_t stream) {
+hipError_t launch_finalize(int N, const Reduce& R, unsigned run_mask, const Issue& is) {
     switch (N) {
-#define STAG_STATE_CASE(n) \
-    case n: hipLaunchKernelGGL((k_state<n>), dim3(1), dim3(64), 0, stream, st, run_mask, kind); break;
-        STAG_STATE_CASE(1)
-        STAG_STATE_CASE(2)
-        STAG_STATE_CASE(4)
-        STAG_STATE_CASE(8)
-        STAG_STATE_CASE(12)
-        STAG_STATE_CASE(16)
-#undef STAG_STATE_CASE
+        case 1: return issue_finalize<1>(R, run_mask, is);
+        case 2: return issue_finalize<2>(R, run_mask, is);
+        case 4: return issue_finalize<4>(R, run_mask, is);
+        case 8: return issue_finalize<8>(R, run_mask, is);
+        case 12: return issue_finalize<12>(R, run_mask, is);
+        case 16: return issue_finalize<16>(R, run_mask, is);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ issue
+
+hipError_t issue_kernel(const Issue& is, const void* func, uint32_t grid, uint32_t block,
+                        void** args) {
+    if (is.gb) {
+        hipKernelNodeParams p{};
+        p.func = const_cast<void*>(func);
+        p.gridDim = dim3(grid);
+        p.blockDim = dim3(block);
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;  // copied into the node
+        p.extra = nullptr;
+        hipGraphNode_t node = nullptr;
+        const hipGraphNode_t dep = is.gb->last;
+        hipError_t err = hipGraphAddKernelNode(&node, is.gb->graph, dep ? &dep : nullptr, dep ? 1 : 0, &p);
+        if (err == hipSuccess) is.gb->last = node;
+        return err;
+    }
+    if (is.ev_start || is.ev_stop)
+        return hipExtLaunchKernel(func, dim3(grid), dim3(block), args, 0, is.stream, is.ev_start,
+                                  is.ev_stop, 0);
+    return hipLaunchKernel(func, dim3(grid), dim3(block), args, 0, is.stream);
 }
 
 // ------------------------------------------------------------------ hop dispatch
 
-hipError_t launch_hop_p0(int S, int N, int epi, bool nt, const HopArgs& a, hipStream_t st,
-                         const LaunchEvents* ev);
-hipError_t launch_hop_p1(int S, int N, int epi, bool nt, const HopArgs& a, hipStream_t st,
-                         const LaunchEvents* ev);
-hipError_t launch_hop_p2(int S, int N, int epi, bool nt, const HopArgs& a, hipStream_t st,
-                         const LaunchEvents* ev);
+hipError_t launch_hop_p0(int S, int N, int epi, bool nt, const HopArgs& a, const Issue& is);
+hipError_t launch_hop_p1(int S, int N, int epi, bool nt, const HopArgs& a, const Issue& is);
+hipError_t launch_hop_p2(int S, int N, int epi, bool nt, const HopArgs& a, const Issue& is);
 
-hipError_t launch_hop(int prec, int S, int N, int epi, bool nt, const HopArgs& a,
-                      hipStream_t st, const LaunchEvents* ev) {
+hipError_t launch_hop(int prec, int S, int N, int epi, bool nt, const HopArgs& a, const Issue& is) {
     switch (prec) {
-        case P64: return launch_hop_p0(S, N, epi, nt, a, st, ev);
-        case P32: return launch_hop_p1(S, N, epi, nt, a, st, ev);
-        case P16S: return launch_hop_p2(S, N, epi, nt, a, st, ev);
+        case P64: return launch_hop_p0(S, N, epi, nt, a, is);
+        case P32: return launch_hop_p1(S, N, epi, nt, a, is);
+        case P16S: return launch_hop_p2(S, N, epi, nt, a, is);
         default: return hipErrorInvalidValue;
     }
 }

@@ -102,9 +102,9 @@ void set_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh, const HopTune& t) {
 hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, const HopTune& t,
                        const void* in, size_t in_rs, void* out, size_t out_rs, int p_out,
                        const void* x, size_t x_rs, const void* b, size_t b_rs, const double* m2,
-                       RhsState* st, unsigned run_mask, const Reduce* red, hipStream_t stream,
+                       RhsState* st, unsigned run_mask, const Reduce* red, const Issue& is,
                        const void* lazy_r, size_t lazy_r_rs, const Reduce* fin,
-                       const LaunchEvents* ev) {
+                       const HopExtra* ex) {
     // the deferred direction update reads beta from the RHS state, and a
     // finalisation at kernel start needs the state and the partials
     if (lazy_r && !st) return hipErrorInvalidValue;
@@ -134,8 +134,19 @@ hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, con
     a.g = g->g;
     if (red) a.red = *red;
     if (fin) a.fin = *fin;
+    if (ex) {
+        // x + y and q(r) belong to the fp64 stages of a reliable update
+        if (prec != P64 || (ex->aux && (epi != EPI_RESID || (ex->aux_prec != P32 && ex->aux_prec != P16S))))
+            return hipErrorInvalidValue;
+        if (ex->lazy_y && epi != EPI_PLAIN && epi != EPI_RESID) return hipErrorInvalidValue;
+        a.lazy_y = ex->lazy_y;
+        a.lazy_y_rs = ex->lazy_y_rs;
+        a.aux = ex->aux;
+        a.aux_rs = ex->aux_rs;
+        a.aux_prec = ex->aux_prec;
+    }
     if (N > 1) S = 1;
-    return launch_hop(prec, S, N, epi, t.nt != 0, a, stream, ev);
+    return launch_hop(prec, S, N, epi, t.nt != 0, a, is);
 }
 
 }  // namespace stag
@@ -517,7 +528,7 @@ int stag_dslash(stag_ctx* ctx, const stag_gauge* g, const stag_field* in, stag_f
         const char* ip = (const char*)in->data + (size_t)done * in->rs;
         char* op = (char*)out->data + (size_t)done * out->rs;
         HIPCK(ctx, enqueue_hop(g, in->prec, t.S1, Nk, EPI_PLAIN, t, ip, in->rs, op, out->rs,
-                               out->parity, nullptr, 0, nullptr, 0, nullptr, nullptr, 0, nullptr, s));
+                               out->parity, nullptr, 0, nullptr, 0, nullptr, nullptr, 0, nullptr, Issue{s}));
         done += Nk;
     }
     (void)N;
@@ -556,9 +567,9 @@ int stag_apply_A(stag_ctx* ctx, const stag_gauge* g, const double* mass, const s
         char* tp = (char*)t + (size_t)done * in->rs;
         char* op = (char*)out->data + (size_t)done * out->rs;
         HIPCK(ctx, enqueue_hop(g, in->prec, tu.S1, Nk, EPI_PLAIN, tu, ip, in->rs, tp, in->rs, 1,
-                               nullptr, 0, nullptr, 0, nullptr, nullptr, 0, nullptr, s));
+                               nullptr, 0, nullptr, 0, nullptr, nullptr, 0, nullptr, Issue{s}));
         HIPCK(ctx, enqueue_hop(g, in->prec, tu.S2, Nk, EPI_XPAY, tu, tp, in->rs, op, out->rs, 0, ip,
-                               in->rs, nullptr, 0, m2, nullptr, 0, nullptr, s));
+                               in->rs, nullptr, 0, m2, nullptr, 0, nullptr, Issue{s}));
         done += Nk;
     }
     HIPCK(ctx, hipFreeAsync(t, s));

@@ -175,8 +175,9 @@ enum FinKind : int {
     FIN_MIXED = 3,     // |r|^2 -> beta, update / stall triggers (mixed CG)
     FIN_TRUE = 4,      // rr_true = sum
     FIN_INIT = 5,      // bb = sum; start state of a solve from x = 0
-    FIN_RU_END = 6,    // state after a reliable / group-wise update (mixed CG)
-    FIN_CG_CHECK = 7,  // accept or restart after a true-residual check (plain CG)
+    FIN_RU_END = 6,    // rr_true = sum, then the state after a reliable / group-wise
+                       // update (mixed CG)
+    FIN_CG_CHECK = 7,  // rr_true = sum, then accept or restart (plain CG)
 };
 
 // A reduction: the producing kernel writes one fp64 partial per 64-site

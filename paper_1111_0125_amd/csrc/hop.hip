@@ -10,8 +10,6 @@
 // them (the block operator sharing gauge loads).
 //
 // This file is compiled once per storage precision (HOP_PREC).
-#include <hip/hip_ext.h>
-
 #include "kern.h"
 #include "launch.h"
 
@@ -39,6 +37,17 @@ __device__ __forceinline__ void load_operand(const HopArgs& a, const char* in_r,
             vi[c] = fma(be, vi[c], ri[c]);
         }
         round_site<P>(vr, vi);
+    }
+    if constexpr (P == P64) {
+        if (a.lazy_y) {
+            float yr[3], yi[3];
+            load_site<P32>((const char*)a.lazy_y + (size_t)r * a.lazy_y_rs, a.g.Vh, n, yr, yi);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                vr[c] = vr[c] + (T)yr[c];
+                vi[c] = vi[c] + (T)yi[c];
+            }
+        }
     }
 }
 
@@ -182,6 +191,14 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                 load_operand<P>(a, (const char*)a.x + (size_t)r * a.x_rs, r, s,
                                 a.lazy_r ? ls[r].beta : 0.0, xr, xi);
                 if (a.lazy_r) store_site<P>((char*)a.x + (size_t)r * a.x_rs, Vh, s, xr, xi);
+                if constexpr (P == P64) {
+                    if (a.lazy_y) {
+                        // x += y in fp64, y = 0 (the group-wise update of Sec.3.2)
+                        store_site<P>((char*)a.x + (size_t)r * a.x_rs, Vh, s, xr, xi);
+                        float z[3] = {0.f, 0.f, 0.f}, zi[3] = {0.f, 0.f, 0.f};
+                        store_site<P32>((char*)a.lazy_y + (size_t)r * a.lazy_y_rs, Vh, s, z, zi);
+                    }
+                }
                 const T m2 = (T)(a.st ? ls[r].m2 : a.m2[r]);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -204,6 +221,21 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                         acc = fma((double)hi[c], (double)hi[c], acc);
                     }
                     dv[r] = acc;
+                    if (a.aux) {
+                        // the inner residual restarts from the true one: rs = q(r)
+                        float qr[3], qi[3];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            qr[c] = (float)hr[c];
+                            qi[c] = (float)hi[c];
+                        }
+                        char* aux_r = (char*)a.aux + (size_t)r * a.aux_rs;
+                        if (a.aux_prec == P16S) {
+                            store_site<P16S>(aux_r, Vh, s, qr, qi);
+                        } else {
+                            store_site<P32>(aux_r, Vh, s, qr, qi);
+                        }
+                    }
                 } else {
                     store_site<P>(out_r, Vh, s, hr, hi);
                     if constexpr (EPI == EPI_XPAY_DOT) {
@@ -225,40 +257,36 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
 }
 
 template <int P, int S, int N, int EPI, bool NT>
-static hipError_t run_hop(const HopArgs& a, hipStream_t stream, const LaunchEvents* ev) {
-    const uint32_t nb = hop_blocks(a.g.Vh, S);
-    if (ev)
-        hipExtLaunchKernelGGL((k_hop<P, S, N, EPI, NT>), dim3(nb), dim3(kBlock), 0, stream, ev->start,
-                              ev->stop, 0, a);
-    else
-        hipLaunchKernelGGL((k_hop<P, S, N, EPI, NT>), dim3(nb), dim3(kBlock), 0, stream, a);
-    return hipGetLastError();
+static hipError_t run_hop(const HopArgs& a, const Issue& is) {
+    HopArgs arg = a;
+    void* args[] = {&arg};
+    return issue_kernel(is, reinterpret_cast<const void*>(&k_hop<P, S, N, EPI, NT>),
+                        hop_blocks(a.g.Vh, S), kBlock, args);
 }
 
 // Dispatch for this precision: N = 1 with S in {1, 2, 4} and both load
 // flavours; N > 1 with S = 1 and non-temporal link loads.
 template <int P, int EPI>
-static hipError_t dispatch_epi(int S, int N, bool nt, const HopArgs& a, hipStream_t st,
-                               const LaunchEvents* ev) {
+static hipError_t dispatch_epi(int S, int N, bool nt, const HopArgs& a, const Issue& is) {
     if (N == 1) {
         if (nt) {
-            if (S == 1) return run_hop<P, 1, 1, EPI, true>(a, st, ev);
-            if (S == 2) return run_hop<P, 2, 1, EPI, true>(a, st, ev);
-            if (S == 4) return run_hop<P, 4, 1, EPI, true>(a, st, ev);
+            if (S == 1) return run_hop<P, 1, 1, EPI, true>(a, is);
+            if (S == 2) return run_hop<P, 2, 1, EPI, true>(a, is);
+            if (S == 4) return run_hop<P, 4, 1, EPI, true>(a, is);
         } else {
-            if (S == 1) return run_hop<P, 1, 1, EPI, false>(a, st, ev);
-            if (S == 2) return run_hop<P, 2, 1, EPI, false>(a, st, ev);
-            if (S == 4) return run_hop<P, 4, 1, EPI, false>(a, st, ev);
+            if (S == 1) return run_hop<P, 1, 1, EPI, false>(a, is);
+            if (S == 2) return run_hop<P, 2, 1, EPI, false>(a, is);
+            if (S == 4) return run_hop<P, 4, 1, EPI, false>(a, is);
         }
         return hipErrorInvalidValue;
     }
     if (S != 1) return hipErrorInvalidValue;
     switch (N) {
-        case 2: return run_hop<P, 1, 2, EPI, true>(a, st, ev);
-        case 4: return run_hop<P, 1, 4, EPI, true>(a, st, ev);
-        case 8: return run_hop<P, 1, 8, EPI, true>(a, st, ev);
-        case 12: return run_hop<P, 1, 12, EPI, true>(a, st, ev);
-        case 16: return run_hop<P, 1, 16, EPI, true>(a, st, ev);
+        case 2: return run_hop<P, 1, 2, EPI, true>(a, is);
+        case 4: return run_hop<P, 1, 4, EPI, true>(a, is);
+        case 8: return run_hop<P, 1, 8, EPI, true>(a, is);
+        case 12: return run_hop<P, 1, 12, EPI, true>(a, is);
+        case 16: return run_hop<P, 1, 16, EPI, true>(a, is);
         default: return hipErrorInvalidValue;
     }
 }
@@ -268,14 +296,14 @@ static hipError_t dispatch_epi(int S, int N, bool nt, const HopArgs& a, hipStrea
 #define HOP_FN_NAME(p) HOP_FN_NAME_(p)
 
 hipError_t HOP_FN_NAME(HOP_PREC)(int S, int N, int epi, bool nt, const HopArgs& a,
-                                  hipStream_t st, const LaunchEvents* ev) {
+                                  const Issue& is) {
     constexpr int P = HOP_PREC;
     switch (epi) {
-        case EPI_PLAIN: return dispatch_epi<P, EPI_PLAIN>(S, N, nt, a, st, ev);
-        case EPI_XPAY: return dispatch_epi<P, EPI_XPAY>(S, N, nt, a, st, ev);
-        case EPI_XPAY_DOT: return dispatch_epi<P, EPI_XPAY_DOT>(S, N, nt, a, st, ev);
+        case EPI_PLAIN: return dispatch_epi<P, EPI_PLAIN>(S, N, nt, a, is);
+        case EPI_XPAY: return dispatch_epi<P, EPI_XPAY>(S, N, nt, a, is);
+        case EPI_XPAY_DOT: return dispatch_epi<P, EPI_XPAY_DOT>(S, N, nt, a, is);
         case EPI_RESID:
-            if constexpr (P == P64) return dispatch_epi<P, EPI_RESID>(S, N, nt, a, st, ev);
+            if constexpr (P == P64) return dispatch_epi<P, EPI_RESID>(S, N, nt, a, is);
             return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }

@@ -41,7 +41,6 @@ enum KernelKind : int {
 };
 struct Timing {
     bool on = false;
-    bool no_graph_events = false;  // the runtime refused event nodes in a capture
     long long count[KK_COUNT] = {0};
     double ms[KK_COUNT] = {0};
     std::vector<hipEvent_t> pool;
@@ -89,18 +88,6 @@ struct stag_field {
     size_t rs = 0;  // bytes per right-hand side
 };
 
-namespace stag {
-// K-iteration graphs of one engine for one kernel block size: one instance,
-// or two alternating ones when the run is timed (each with its own
-// event-record nodes, read back after its replay completed and before it
-// is launched again).
-struct GraphSet {
-    hipGraphExec_t g[2] = {nullptr, nullptr};
-    std::vector<Timing::Rec> ev[2];
-    int n = 0;
-};
-}  // namespace stag
-
 // Solver workspace + device state for N right-hand-side slots of one
 // (gauge, inner precision).
 struct stag_engine {
@@ -112,7 +99,8 @@ struct stag_engine {
     uint32_t Vh = 0;
     // fp64 vectors [N]
     void *x64 = nullptr, *r64 = nullptr, *t64 = nullptr, *d64 = nullptr, *Ad64 = nullptr;
-    void* b64 = nullptr;  // engine-owned right-hand sides (serving), else null
+    void* b64 = nullptr;  // the right-hand sides being solved [N]
+    bool serving = false; // owned by a serving batch (never lent to stag_cg_solve)
     // low-precision vectors [N]
     void *y32 = nullptr, *rs = nullptr, *d = nullptr, *t = nullptr, *Ad = nullptr;
     size_t rs64 = 0, rsP = 0, rs32 = 0;
@@ -131,8 +119,7 @@ struct stag_engine {
     double* partials = nullptr;
     double* partials1 = nullptr;
     size_t bytes = 0;
-    std::map<long long, stag::GraphSet> graphs;    // key: (K, kernel N, timed)
-    hipStream_t cap_stream = nullptr;              // idle stream the graphs are captured on
+    std::map<long long, hipGraphExec_t> graphs;    // one block of work; key: (K, kernel N)
     stag::HopTune tune_lo, tune_64;
 };
 
@@ -145,16 +132,14 @@ struct EngineRun {
     const void* b = nullptr;  // right-hand sides, slot-strided
     size_t b_rs = 0;
     int K = 16;
+    int F = 8;                // iterations between the predicated fix-ups
     bool use_graph = true;
     bool timed = false;
     long long launched = 0;   // blocks enqueued (block j polls into buffer j % 2)
     long long polled = 0;     // polls processed
     long long last_poll = -1; // index of the last processed poll
-    std::vector<long long> fix_after;    // polls <= this are stale for fix-up decisions
     std::vector<long long> start_after;  // polls <= this predate the slot's start
     int busy_hi = 0;          // slots [0, busy_hi) may be busy
-    GraphSet* block_graph[2] = {nullptr, nullptr};
-    int block_inst[2] = {0, 0};
 };
 
 struct SlotInit {
@@ -172,7 +157,7 @@ void fill_stats(const RhsState& s, double secs, stag_cg_stats* out);
 bool flags_terminal(unsigned f);
 int status_of_flags(unsigned f);
 int default_graph_k(uint32_t Vh);
-int engine_create(stag_ctx* ctx, const stag_gauge* g, int prec, int N, bool own_b,
+int engine_create(stag_ctx* ctx, const stag_gauge* g, int prec, int N, bool serving,
                   stag_engine** out);
 
 }  // namespace stag
@@ -219,11 +204,20 @@ hipError_t timing_begin(stag_ctx* ctx, hipStream_t s, hipEvent_t* ev);
 hipError_t timing_end(stag_ctx* ctx, hipStream_t s, int kind, hipEvent_t start);
 void timing_collect(stag_ctx* ctx);  // accumulate every completed record
 
+// Fields of HopArgs used only by the fp64 stages of a reliable update.
+struct HopExtra {
+    const void* lazy_y = nullptr;
+    size_t lazy_y_rs = 0;
+    void* aux = nullptr;
+    size_t aux_rs = 0;
+    int aux_prec = P32;
+};
+
 hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, const HopTune& t,
                        const void* in, size_t in_rs, void* out, size_t out_rs, int p_out,
                        const void* x, size_t x_rs, const void* b, size_t b_rs, const double* m2,
-                       RhsState* st, unsigned run_mask, const Reduce* red, hipStream_t stream,
+                       RhsState* st, unsigned run_mask, const Reduce* red, const Issue& is,
                        const void* lazy_r = nullptr, size_t lazy_r_rs = 0,
-                       const Reduce* fin = nullptr, const LaunchEvents* ev = nullptr);
+                       const Reduce* fin = nullptr, const HopExtra* ex = nullptr);
 
 }  // namespace stag

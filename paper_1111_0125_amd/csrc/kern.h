@@ -297,7 +297,8 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
             }
             break;
         case FIN_RU_END: {
-            const double rt = s.rr_true;
+            const double rt = sum;
+            s.rr_true = rt;
             const bool stall = (s.flags & F_STALL) != 0;
             s.updates += 1;
             if (!isfinite(rt)) {
@@ -338,7 +339,8 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
             break;
         }
         case FIN_CG_CHECK: {
-            const double rt = s.rr_true;
+            const double rt = sum;
+            s.rr_true = rt;
             s.updates += 1;
             if (!isfinite(rt)) {
                 s.flags = F_BREAKDOWN;

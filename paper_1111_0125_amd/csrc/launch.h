@@ -33,6 +33,16 @@ struct HopArgs {
     // site, uses it as x and stores it over d.
     const void* lazy_r;
     size_t lazy_r_rs;
+    // fp64 stages of a reliable / group-wise update (P64 only): with lazy_y
+    // set the operand is x + y, y being the fp32 correction of the inner
+    // solve; stage 2 also stores x + y over x and zeroes y at its own site.
+    // With aux set (RESID) the residual is also stored rounded to aux_prec
+    // (P32 or P16S), restarting the inner residual from it.
+    const void* lazy_y;
+    size_t lazy_y_rs;
+    void* aux;
+    size_t aux_rs;
+    int aux_prec;
     double m2[16];         // mass^2 per right-hand side (used when st is null)
     RhsState* st;          // null: every RHS is processed
     unsigned run_mask;     // process RHS r iff st[r].flags & run_mask
@@ -53,8 +63,6 @@ enum VecOp : int {
     OP_START = 1,      // d = q(r64); if rs: rs = q(r64); if y: y = 0
     OP_UPD_CG = 2,     // x += a d, r -= a Ad, |r|^2 -> FIN_CG           (fp64)
     OP_UPD_MIXED = 3,  // y += a d, rs = q(rs - a Ad), |rs|^2 -> FIN_MIXED
-    OP_RU_BEGIN = 5,   // x64 += y, y = 0
-    OP_RU_END = 6,     // rs = q(r64) after a true-residual recompute
     OP_ZERO = 8,       // f0 = 0
 };
 
@@ -69,24 +77,35 @@ struct VecArgs {
     Reduce fin;        // finalised at kernel start, as in HopArgs
 };
 
-// Optional events recorded at the start and the end of one kernel's
-// execution (hipExtLaunchKernel), for timing single launches.
-struct LaunchEvents {
-    hipEvent_t start;
-    hipEvent_t stop;
+// A graph under construction: kernels are appended as a chain of nodes.
+struct GraphBuild {
+    hipGraph_t graph = nullptr;
+    hipGraphNode_t last = nullptr;  // the node the next one depends on
 };
 
-hipError_t launch_hop(int prec, int S, int N, int epi, bool nt, const HopArgs& a,
-                      hipStream_t stream, const LaunchEvents* ev = nullptr);
-hipError_t launch_vec(int prec, int N, int op, const VecArgs& a, hipStream_t stream,
-                      const LaunchEvents* ev = nullptr);
+// Where a kernel goes: launched on `stream` (with events recorded at the
+// start and the end of its execution when ev_start / ev_stop are set), or,
+// with gb set, appended to that graph after its last node. Graphs are
+// built node by node rather than captured from a stream, so building one
+// does not interact with what other threads do meanwhile.
+struct Issue {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_start = nullptr;
+    hipEvent_t ev_stop = nullptr;
+    GraphBuild* gb = nullptr;
+};
+
+// Issue kernel `func` (host stub address) with grid x block threads;
+// args[i] points at the i-th kernel argument.
+hipError_t issue_kernel(const Issue& is, const void* func, uint32_t grid, uint32_t block,
+                        void** args);
+
+hipError_t launch_hop(int prec, int S, int N, int epi, bool nt, const HopArgs& a, const Issue& is);
+hipError_t launch_vec(int prec, int N, int op, const VecArgs& a, const Issue& is);
 // One-block fixed-order sum of a reduction kernel's chunk partials and its
-// finalisation (R.kind), for the RHS whose flags match run_mask; launched
+// finalisation (R.kind), for the RHS whose flags match run_mask; issued
 // right after the kernel that wrote the partials, with the same run_mask.
-hipError_t launch_finalize(int N, const Reduce& R, unsigned run_mask, hipStream_t stream);
-// One-block state transition (FIN_RU_END, FIN_CG_CHECK) of the RHS whose
-// flags match run_mask.
-hipError_t launch_state(int N, int kind, RhsState* st, unsigned run_mask, hipStream_t stream);
+hipError_t launch_finalize(int N, const Reduce& R, unsigned run_mask, const Issue& is);
 
 // Layout conversion kernels (canonical complex128 <-> internal storage).
 hipError_t launch_gauge_pack(int prec, const void* U_dev, void* G, float* gscale, const Geom& g,

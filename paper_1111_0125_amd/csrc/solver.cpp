@@ -6,10 +6,10 @@
 // All CG scalars live on the device (RhsState); each reduction is finalised
 // at the start of the kernel that consumes it, so an iteration is three
 // kernels with no host round trip. The host enqueues blocks of K iterations
-// (one HIP graph replay), polls the per-slot flags one block behind the
-// device, and enqueues the fp64 true-residual work only when a flag asks for
-// it; those kernels are predicated on the flags, so a redundant enqueue is a
-// no-op.
+// (one HIP graph replay) and polls the per-slot flags one block behind the
+// device. Every few iterations a block runs the fp64 fix-up (true-residual
+// check of plain CG, reliable + group-wise update of mixed CG), predicated
+// on the flags: it works only on the slots that asked for it.
 //
 // Slots are independent: a slot can start (from x = 0) at any block
 // boundary while others are mid-solve, and its arithmetic does not depend on
@@ -27,16 +27,8 @@ namespace stag {
 static size_t state_bytes(int N) { return sizeof(RhsState) * (size_t)N; }
 
 void engine_drop_graphs(stag_engine* e) {
-    for (auto& kv : e->graphs) {
-        GraphSet& gs = kv.second;
-        for (int i = 0; i < 2; ++i) {
-            if (gs.g[i]) (void)hipGraphExecDestroy(gs.g[i]);
-            for (auto& r : gs.ev[i]) {
-                if (r.a) (void)hipEventDestroy(r.a);
-                if (r.b) (void)hipEventDestroy(r.b);
-            }
-        }
-    }
+    for (auto& kv : e->graphs)
+        if (kv.second) (void)hipGraphExecDestroy(kv.second);
     e->graphs.clear();
 }
 
@@ -53,12 +45,11 @@ void engine_destroy(stag_engine* e) {
         if (e->ev[i]) (void)hipEventDestroy(e->ev[i]);
     }
     if (e->hstage) (void)hipHostFree(e->hstage);
-    if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
     ctx->used.fetch_sub(e->bytes);
     delete e;
 }
 
-int engine_create(stag_ctx* ctx, const stag_gauge* g, int prec, int N, bool own_b,
+int engine_create(stag_ctx* ctx, const stag_gauge* g, int prec, int N, bool serving,
                   stag_engine** out) {
     stag_engine* e = new stag_engine();
     e->ctx = ctx;
@@ -81,7 +72,10 @@ int engine_create(stag_ctx* ctx, const stag_gauge* g, int prec, int N, bool own_
         {(void**)&e->partials, N * nparts * sizeof(double)},
         {(void**)&e->partials1, N * nparts * sizeof(double)},
     };
-    if (own_b) reqs.push_back({&e->b64, N * e->rs64});
+    // the right-hand sides live in the engine: the fix-up kernels captured in
+    // the iteration graphs read them, so their address must not change
+    reqs.push_back({&e->b64, N * e->rs64});
+    e->serving = serving;
     if (prec == P64) {
         reqs.push_back({&e->d64, N * e->rs64});
         reqs.push_back({&e->Ad64, N * e->rs64});
@@ -117,11 +111,10 @@ int engine_create(stag_ctx* ctx, const stag_gauge* g, int prec, int N, bool own_
             return set_error(ctx, STAG_EDEVICE, "solver workspace: pinned buffer / event");
         }
     }
-    if (hipHostMalloc((void**)&e->hstage, state_bytes(N), hipHostMallocDefault) != hipSuccess ||
-        hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    if (hipHostMalloc((void**)&e->hstage, state_bytes(N), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         engine_destroy(e);
-        return set_error(ctx, STAG_EDEVICE, "solver workspace: pinned staging / capture stream");
+        return set_error(ctx, STAG_EDEVICE, "solver workspace: pinned staging");
     }
     // Every slot starts free, and the direction / y buffers must hold finite
     // values (beta = 0 multiplies them). hipMemset runs on the null stream,
@@ -148,7 +141,7 @@ int engine_acquire(stag_ctx* ctx, const stag_gauge* g, int prec, int N, stag_eng
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         for (auto* e : ctx->engines)
-            if (!e->in_use && e->gauge == g && e->prec == prec && e->N == N && !e->b64) {
+            if (!e->in_use && e->gauge == g && e->prec == prec && e->N == N && !e->serving) {
                 e->in_use = true;
                 *out = e;
                 return STAG_OK;
@@ -175,36 +168,21 @@ namespace {
 
 struct Ctx {
     stag_engine* e;
-    hipStream_t s;
-    const void* b;
-    size_t b_rs;
-    int nk;                          // kernel block size (>= highest busy slot + 1)
-    bool timed;
-    std::vector<Timing::Rec>* cap;  // non-null while capturing a timed graph
-    mutable size_t cap_next;        // next unused record of *cap
+    Issue is;   // a stream, or a graph under construction
+    int nk;     // kernel block size (>= highest busy slot + 1)
+    bool timed; // eager only: bracket each kernel with timing events
 };
 
-// Launch `fn` bracketed by timing events when the run is timed. Inside a
-// graph capture the events become external event-record nodes of the graph.
+// Launch `fn` bracketed by timing events when the run is timed.
 template <typename F>
 hipError_t timed_launch(const Ctx& c, int kind, F&& fn) {
     if (!c.timed) return fn();
-    if (c.cap) {
-        if (c.cap_next >= c.cap->size()) return hipErrorInvalidValue;
-        Timing::Rec& rec = (*c.cap)[c.cap_next];
-        c.cap_next += 1;
-        rec.kind = kind;
-        hipError_t err = hipEventRecordWithFlags(rec.a, c.s, hipEventRecordExternal);
-        if (err == hipSuccess) err = fn();
-        if (err == hipSuccess) err = hipEventRecordWithFlags(rec.b, c.s, hipEventRecordExternal);
-        return err;
-    }
     hipEvent_t a = nullptr;
-    hipError_t err = timing_begin(c.e->ctx, c.s, &a);
+    hipError_t err = timing_begin(c.e->ctx, c.is.stream, &a);
     if (err != hipSuccess) return err;
     err = fn();
     if (err != hipSuccess) return err;
-    return timing_end(c.e->ctx, c.s, kind, a);
+    return timing_end(c.e->ctx, c.is.stream, kind, a);
 }
 
 Reduce make_red(stag_engine* e, int kind, double* partials = nullptr) {
@@ -224,6 +202,7 @@ struct Opt {
     const Reduce* fin = nullptr;     // reduction finalised at kernel start
     bool finalize = true;            // finalise this kernel's reduction right after it
     double* partials = nullptr;      // where this kernel's partials go (null: e->partials)
+    const HopExtra* ex = nullptr;    // fp64 stages of a reliable update
 };
 
 // A hop stage. With Opt::finalize, a reduction it produces (XPAY_DOT,
@@ -242,11 +221,11 @@ hipError_t hop(const Ctx& c, int prec, int stage, int epi, const void* in, void*
     const int kk = prec == e->prec && run == F_ACTIVE ? (stage == 1 ? KK_HOP1 : KK_HOP2)
                                                        : (stage == 1 ? KK_HOP1_64 : KK_HOP2_64);
     hipError_t err = timed_launch(c, kk, [&]() {
-        return enqueue_hop(e->gauge, prec, S, c.nk, epi, t, in, rs, out, rs, p_out, x, rs, c.b,
-                           c.b_rs, nullptr, st, run, &red, c.s, lazy_r, rs, o.fin);
+        return enqueue_hop(e->gauge, prec, S, c.nk, epi, t, in, rs, out, rs, p_out, x, rs, e->b64,
+                           e->rs64, nullptr, st, run, &red, c.is, lazy_r, rs, o.fin, o.ex);
     });
     if (err != hipSuccess || !o.finalize || !(epi == EPI_XPAY_DOT || epi == EPI_RESID)) return err;
-    return timed_launch(c, KK_OTHER, [&]() { return launch_finalize(c.nk, red, run, c.s); });
+    return timed_launch(c, KK_OTHER, [&]() { return launch_finalize(c.nk, red, run, c.is); });
 }
 
 hipError_t vec(const Ctx& c, int prec, int op, std::initializer_list<std::pair<void*, size_t>> f,
@@ -266,15 +245,13 @@ hipError_t vec(const Ctx& c, int prec, int op, std::initializer_list<std::pair<v
     a.red = make_red(e, kind, o.partials);
     if (o.fin) a.fin = *o.fin;
     const int kk = op == OP_UPD_CG || op == OP_UPD_MIXED ? KK_UPDATE : KK_OTHER;
-    hipError_t err = timed_launch(c, kk, [&]() { return launch_vec(prec, c.nk, op, a, c.s); });
+    hipError_t err = timed_launch(c, kk, [&]() { return launch_vec(prec, c.nk, op, a, c.is); });
     if (err != hipSuccess || !o.finalize || !(op == OP_INIT_B || op == OP_UPD_CG || op == OP_UPD_MIXED))
         return err;
-    return timed_launch(c, KK_OTHER, [&]() { return launch_finalize(c.nk, a.red, run, c.s); });
+    return timed_launch(c, KK_OTHER, [&]() { return launch_finalize(c.nk, a.red, run, c.is); });
 }
 
-// Kernel launches of one K-iteration block.
 constexpr int kKernelsPerIteration = 3;
-inline size_t block_launches(int K) { return (size_t)K * kKernelsPerIteration + 1; }
 
 // K CG iterations (Fig.1; Sec.3.2 for a low-precision inner solve), three
 // kernels each:
@@ -331,42 +308,55 @@ hipError_t enqueue_iterations(const Ctx& c, int K) {
         }
         if (err) return err;
     }
-    return timed_launch(c, KK_OTHER, [&]() { return launch_finalize(c.nk, pend_r, F_ACTIVE, c.s); });
+    return timed_launch(c, KK_OTHER, [&]() { return launch_finalize(c.nk, pend_r, F_ACTIVE, c.is); });
 }
 
-hipError_t state_step(const Ctx& c, int kind, unsigned run) {
-    return timed_launch(c, KK_OTHER, [&]() { return launch_state(c.nk, kind, c.e->st, run, c.s); });
-}
-
-// fp64 true residual r64 = b - A x64 for the slots whose flags match `run`.
-hipError_t enqueue_true_residual(const Ctx& c, unsigned run) {
+// Plain CG (Fig.1): the iterated residual of the slots flagged F_CONV met
+// the tolerance; r = b - A x in fp64 and |r|^2, then (finalisation) finish,
+// or restart from the true residual with d = r.
+hipError_t enqueue_check(const Ctx& c) {
     stag_engine* e = c.e;
+    const unsigned run = F_CONV;
     hipError_t err;
     if ((err = hop(c, P64, 1, EPI_PLAIN, e->x64, e->t64, nullptr, FIN_STORE, run))) return err;
-    return hop(c, P64, 2, EPI_RESID, e->t64, e->r64, e->x64, FIN_TRUE, run);
+    return hop(c, P64, 2, EPI_RESID, e->t64, e->r64, e->x64, FIN_CG_CHECK, run);
 }
 
-// Plain CG: the iterated residual met the tolerance; check the true one and
-// either finish or restart from it (r = b - A x, direction d = r).
-hipError_t enqueue_check(const Ctx& c) {
-    hipError_t err;
-    if ((err = enqueue_true_residual(c, F_CONV))) return err;
-    return state_step(c, FIN_CG_CHECK, F_CONV);
-}
-
-// Mixed CG (Sec.3.2): reliable + group-wise update. x += y in fp64, y = 0,
-// r = b - A x in fp64, the low-precision residual restarts from it, and the
-// direction carries over (Eq.6) or restarts after a stall.
+// Mixed CG (Sec.3.2): reliable + group-wise update of the slots flagged
+// F_RU or F_STALL, three kernels: the fp64 stage 1 gathers x + y; stage 2
+// stores x += y and y = 0 at its own site, forms r = b - A x with |r|^2 and
+// stores the inner residual q(r); the finalisation then finishes the slot
+// or carries the direction over (Eq.6), restarting it after a stall.
 hipError_t enqueue_update(const Ctx& c) {
     stag_engine* e = c.e;
     const unsigned run = F_RU | F_STALL;
+    HopExtra x1;
+    x1.lazy_y = e->y32;
+    x1.lazy_y_rs = e->rs32;
+    HopExtra x2 = x1;
+    x2.aux = e->rs;
+    x2.aux_rs = e->rsP;
+    x2.aux_prec = e->prec;
+    Opt o1, o2;
+    o1.ex = &x1;
+    o2.ex = &x2;
     hipError_t err;
-    if ((err = vec(c, e->prec, OP_RU_BEGIN, {{e->x64, e->rs64}, {e->y32, e->rs32}}, FIN_STORE, run)))
+    if ((err = hop(c, P64, 1, EPI_PLAIN, e->x64, e->t64, nullptr, FIN_STORE, run, nullptr, o1)))
         return err;
-    if ((err = enqueue_true_residual(c, run))) return err;
-    if ((err = vec(c, e->prec, OP_RU_END, {{e->r64, e->rs64}, {e->rs, e->rsP}}, FIN_STORE, run)))
-        return err;
-    return state_step(c, FIN_RU_END, run);
+    return hop(c, P64, 2, EPI_RESID, e->t64, e->r64, e->x64, FIN_RU_END, run, nullptr, o2);
+}
+
+// One block: K iterations in segments of at most F, each segment followed by
+// the fix-up of the slots it flagged (predicated on the flags: a no-op for
+// the others), so a flagged slot waits at most F iterations.
+hipError_t enqueue_block(const Ctx& c, int K, int F) {
+    const bool mixed = c.e->prec != P64;
+    hipError_t err;
+    for (int done = 0; done < K; done += F) {
+        if ((err = enqueue_iterations(c, std::min(F, K - done)))) return err;
+        if ((err = mixed ? enqueue_update(c) : enqueue_check(c))) return err;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -402,16 +392,17 @@ void run_init(EngineRun& R, stag_engine* e, hipStream_t s, const void* b, size_t
     R.b = b;
     R.b_rs = b_rs;
     R.K = K;
+    // plain CG checks its true residual once per block (it converges once);
+    // mixed CG updates every ~tens of iterations, so a flagged slot should
+    // not idle for a whole block
+    R.F = e->prec == P64 ? K : std::min(K, 8);
     R.use_graph = use_graph;
     R.timed = e->ctx->timing.on;
-    if (R.timed && e->ctx->timing.no_graph_events) R.use_graph = false;
+    if (R.timed) R.use_graph = false;  // timing events bracket eager launches
     R.launched = R.polled = 0;
-    R.fix_after.assign(e->N, -1);
     R.start_after.assign(e->N, -1);
     R.last_poll = -1;
     R.busy_hi = 0;
-    R.block_graph[0] = R.block_graph[1] = nullptr;
-    R.block_inst[0] = R.block_inst[1] = 0;
 }
 
 int default_graph_k(uint32_t Vh) { return Vh >= 262144 ? 16 : (Vh >= 32768 ? 32 : 64); }
@@ -437,9 +428,9 @@ int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots) {
         RCK(hipMemcpyAsync(e->st + si.slot, &s, sizeof(RhsState), hipMemcpyHostToDevice, R.s));
         if (si.slot + 1 > R.busy_hi) R.busy_hi = si.slot + 1;
         // polls of blocks launched before this start show the slot's previous state
-        R.fix_after[si.slot] = R.start_after[si.slot] = R.launched - 1;
+        R.start_after[si.slot] = R.launched - 1;
     }
-    Ctx c{e, R.s, R.b, R.b_rs, pick_n(R.busy_hi), R.timed, nullptr, 0};
+    Ctx c{e, Issue{R.s}, pick_n(R.busy_hi), R.timed};
     void* b = const_cast<void*>(R.b);
     if (e->prec != P64) {
         RCK(vec(c, e->prec, OP_START, {{b, R.b_rs}, {e->d, e->rsP}, {e->rs, e->rsP}, {e->y32, e->rs32}},
@@ -452,98 +443,53 @@ int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots) {
     return STAG_OK;
 }
 
-static int get_graphs(EngineRun& R, int nk, GraphSet** out) {
+// The graph of one block of work (K iterations with their fix-ups) for
+// kernel block size nk, built node by node on first use and kept. Every
+// buffer it uses belongs to the engine, so it serves every later block.
+static int get_graph(EngineRun& R, int nk, hipGraphExec_t* out) {
     stag_engine* e = R.e;
-    const int ninst = R.timed ? 2 : 1;
-    const long long key = ((long long)R.K << 16) | ((long long)nk << 1) | (R.timed ? 1 : 0);
-    // the iteration kernels never read b, so one graph serves every b buffer
+    const long long key = ((long long)R.K << 16) | (long long)nk;
     auto it = e->graphs.find(key);
     if (it != e->graphs.end()) {
-        *out = &it->second;
+        *out = it->second;
         return STAG_OK;
     }
-    GraphSet gs;
-    gs.n = ninst;
-    bool ok = true;
-    hipError_t bad = hipSuccess;
-    // capture on the engine's idle stream (a graph does not depend on the
-    // stream it was captured on); replays go to the run's stream
-    hipStream_t cs = e->cap_stream;
-    for (int inst = 0; inst < ninst && ok; ++inst) {
-        Ctx cc{e, cs, R.b, R.b_rs, nk, R.timed, nullptr, 0};
-        if (R.timed) {
-            gs.ev[inst].resize(block_launches(R.K));
-            for (auto& r : gs.ev[inst]) {
-                r.a = r.b = nullptr;
-                if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) ok = false;
-            }
-            cc.cap = &gs.ev[inst];
-        }
-        if (!ok) break;
-        hipGraph_t graph = nullptr;
-        hipError_t berr = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
-        if (berr != hipSuccess) {
-            (void)hipGetLastError();
-            bad = berr;
-            ok = false;
-            break;
-        }
-        hipError_t cerr = enqueue_iterations(cc, R.K);
-        hipError_t eerr = hipStreamEndCapture(cs, &graph);
-        hipError_t ierr = hipErrorInvalidValue;
-        if (cerr == hipSuccess && eerr == hipSuccess && graph)
-            ierr = hipGraphInstantiate(&gs.g[inst], graph, nullptr, nullptr, 0);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (ierr != hipSuccess) {
-            (void)hipGetLastError();
-            gs.g[inst] = nullptr;
-            bad = cerr != hipSuccess ? cerr : eerr != hipSuccess ? eerr : ierr;
-            ok = false;
-        }
+    GraphBuild gb;
+    hipError_t err = hipGraphCreate(&gb.graph, 0);
+    if (err == hipSuccess) {
+        Issue is;
+        is.gb = &gb;
+        Ctx c{e, is, nk, false};
+        err = enqueue_block(c, R.K, R.F);
     }
-    if (!ok) {
-        for (int i = 0; i < 2; ++i) {
-            if (gs.g[i]) (void)hipGraphExecDestroy(gs.g[i]);
-            for (auto& r : gs.ev[i]) {
-                if (r.a) (void)hipEventDestroy(r.a);
-                if (r.b) (void)hipEventDestroy(r.b);
-            }
-        }
-        if (R.timed) {
-            // the runtime refused event nodes in a capture: time eagerly
-            e->ctx->timing.no_graph_events = true;
-            R.use_graph = false;
-            *out = nullptr;
-            return STAG_OK;
-        }
-        return set_error(e->ctx, STAG_EDEVICE, "solver: graph capture failed: %s",
-                         hipGetErrorString(bad));
+    hipGraphExec_t exec = nullptr;
+    if (err == hipSuccess) err = hipGraphInstantiate(&exec, gb.graph, nullptr, nullptr, 0);
+    if (gb.graph) (void)hipGraphDestroy(gb.graph);
+    if (err != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(e->ctx, STAG_EDEVICE, "solver: graph construction failed: %s",
+                         hipGetErrorString(err));
     }
-    auto res = e->graphs.emplace(key, std::move(gs));
-    *out = &res.first->second;
+    e->graphs.emplace(key, exec);
+    *out = exec;
     return STAG_OK;
 }
 
-// Enqueue K iterations for the busy slots, then the poll of the state.
+// Enqueue one block (K iterations with fix-ups) for the busy slots, then the
+// poll of the state.
 int run_enqueue_block(EngineRun& R) {
     stag_engine* e = R.e;
     const int nk = pick_n(R.busy_hi > 0 ? R.busy_hi : 1);
     const long long j = R.launched;
-    GraphSet* gs = nullptr;
-    if (R.use_graph) {
-        int rc = get_graphs(R, nk, &gs);
-        if (rc) return rc;
-    }
     const int buf = (int)(j % 2);
-    if (gs) {
-        const int inst = (int)(j % gs->n);
-        RCK(hipGraphLaunch(gs->g[inst], R.s));
-        R.block_graph[buf] = gs;
-        R.block_inst[buf] = inst;
+    if (R.use_graph) {
+        hipGraphExec_t exec = nullptr;
+        int rc = get_graph(R, nk, &exec);
+        if (rc) return rc;
+        RCK(hipGraphLaunch(exec, R.s));
     } else {
-        Ctx c{e, R.s, R.b, R.b_rs, nk, R.timed, nullptr, 0};
-        RCK(enqueue_iterations(c, R.K));
-        R.block_graph[buf] = nullptr;
+        Ctx c{e, Issue{R.s}, nk, R.timed};
+        RCK(enqueue_block(c, R.K, R.F));
     }
     RCK(hipMemcpyAsync(e->host[buf], e->st, state_bytes(e->N), hipMemcpyDeviceToHost, R.s));
     RCK(hipEventRecord(e->ev[buf], R.s));
@@ -553,9 +499,9 @@ int run_enqueue_block(EngineRun& R) {
 
 // Wait for (or, with blocking = false, test) the oldest outstanding poll.
 // On success *h points at the polled states (valid until the next block is
-// enqueued); fix-up work (true-residual checks, reliable updates) for
-// flagged slots is enqueued. Returns STAG_PENDING when not blocking and the
-// poll is not complete yet.
+// enqueued). Flagged slots need nothing from the host: every block ends its
+// segments with the predicated fix-ups. Returns STAG_PENDING when not
+// blocking and the poll is not complete yet.
 int run_process_poll(EngineRun& R, bool blocking, const RhsState** h) {
     stag_engine* e = R.e;
     if (R.polled >= R.launched) return set_error(e->ctx, STAG_EINVAL, "solver: no poll outstanding");
@@ -571,41 +517,10 @@ int run_process_poll(EngineRun& R, bool blocking, const RhsState** h) {
         }
         RCK(q);
     }
-    if (R.timed) {
-        timing_collect(e->ctx);
-        GraphSet* gs = R.block_graph[buf];
-        if (gs) {
-            Timing& T = e->ctx->timing;
-            std::lock_guard<std::mutex> lk(T.mu);
-            for (auto& r : gs->ev[R.block_inst[buf]]) {
-                float ms = 0.f;
-                if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
-                    T.count[r.kind] += 1;
-                    T.ms[r.kind] += ms;
-                }
-                (void)hipGetLastError();
-            }
-        }
-    }
+    if (R.timed) timing_collect(e->ctx);
     R.polled = j + 1;
     R.last_poll = j;
     const RhsState* st = e->host[buf];
-    const bool mixed = e->prec != P64;
-    bool need = false;
-    for (int r = 0; r < R.busy_hi; ++r) {
-        const unsigned f = st[r].flags;
-        if (flags_terminal(f) || j <= R.fix_after[r]) continue;
-        if ((!mixed && (f & F_CONV)) || (mixed && (f & (F_RU | F_STALL)))) {
-            need = true;
-            // the fix is enqueued after every block launched so far; the
-            // first poll that sees its effect is the next one enqueued
-            R.fix_after[r] = R.launched - 1;
-        }
-    }
-    if (need) {
-        Ctx c{e, R.s, R.b, R.b_rs, pick_n(R.busy_hi), R.timed, nullptr, 0};
-        RCK(mixed ? enqueue_update(c) : enqueue_check(c));
-    }
     *h = st;
     return STAG_OK;
 }
@@ -627,8 +542,9 @@ int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, siz
                  hipStream_t stream) {
     const auto t0 = std::chrono::steady_clock::now();
     const int K = p.graph_k > 0 ? p.graph_k : default_graph_k(e->Vh);
+    RCK(hipMemcpy2DAsync(e->b64, e->rs64, b64, b_rs, e->rs64, n, hipMemcpyDeviceToDevice, stream));
     EngineRun R;
-    run_init(R, e, stream, b64, b_rs, K, p.use_graph != 0);
+    run_init(R, e, stream, e->b64, e->rs64, K, p.use_graph != 0);
     std::vector<SlotInit> slots(n);
     for (int r = 0; r < n; ++r) slots[r] = SlotInit{r, mass[r], p};
     int rc = run_start_slots(R, slots);
@@ -710,10 +626,10 @@ int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps,
     if (err == hipSuccess && e->y32) err = hipMemsetAsync(e->y32, 0, bytes[2], s);
     if (err == hipSuccess) err = hipMemsetAsync(e->partials, 0, pbytes, s);
     if (err == hipSuccess) err = hipMemsetAsync(e->partials1, 0, pbytes, s);
-    std::vector<LaunchEvents> ev((size_t)reps, LaunchEvents{nullptr, nullptr});
+    std::vector<Issue> ev((size_t)reps, Issue{s});
     for (auto& v : ev) {
-        if (err == hipSuccess) err = hipEventCreate(&v.start);
-        if (err == hipSuccess) err = hipEventCreate(&v.stop);
+        if (err == hipSuccess) err = hipEventCreate(&v.ev_start);
+        if (err == hipSuccess) err = hipEventCreate(&v.ev_stop);
     }
     const bool mixed = prec != P64;
     Reduce pend_r = make_red(e, FIN_STORE, e->partials1);
@@ -724,7 +640,7 @@ int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps,
     pend_a.st = e->st;
     pend_a.st_out = e->st1;
     pend_a.out = sink;
-    auto one = [&](int which, const LaunchEvents* le) -> hipError_t {
+    auto one = [&](int which, const Issue& is) -> hipError_t {
         Reduce red = make_red(e, FIN_STORE);
         const size_t rs = mixed ? e->rsP : e->rs64;
         void* dd = mixed ? e->d : e->d64;
@@ -733,11 +649,10 @@ int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps,
         void* ad = mixed ? e->Ad : e->Ad64;
         if (which == 0)
             return enqueue_hop(g, prec, N > 1 ? 1 : t.S1, N, EPI_PLAIN, t, dd, rs, tt, rs, 1, nullptr,
-                               0, nullptr, 0, nullptr, e->st1, F_ACTIVE, nullptr, s, rr, rs, &pend_r,
-                               le);
+                               0, nullptr, 0, nullptr, e->st1, F_ACTIVE, nullptr, is, rr, rs, &pend_r);
         if (which == 1)
             return enqueue_hop(g, prec, N > 1 ? 1 : t.S2, N, EPI_XPAY_DOT, t, tt, rs, ad, rs, 0, dd,
-                               rs, nullptr, 0, nullptr, e->st, F_ACTIVE, &red, s, rr, rs, nullptr, le);
+                               rs, nullptr, 0, nullptr, e->st, F_ACTIVE, &red, is, rr, rs);
         VecArgs a{};
         if (mixed) {
             void* f[] = {e->y32, e->rs, e->d, e->Ad};
@@ -759,16 +674,16 @@ int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps,
         a.swizzle = t.swizzle;
         a.red = make_red(e, FIN_STORE, e->partials1);
         a.fin = pend_a;
-        return launch_vec(prec, N, mixed ? OP_UPD_MIXED : OP_UPD_CG, a, s, le);
+        return launch_vec(prec, N, mixed ? OP_UPD_MIXED : OP_UPD_CG, a, is);
     };
     for (int which = 0; which < 3 && err == hipSuccess; ++which) {
-        for (int i = 0; i < 3 && err == hipSuccess; ++i) err = one(which, nullptr);  // warm-up
-        for (int i = 0; i < reps && err == hipSuccess; ++i) err = one(which, &ev[(size_t)i]);
+        for (int i = 0; i < 3 && err == hipSuccess; ++i) err = one(which, Issue{s});  // warm-up
+        for (int i = 0; i < reps && err == hipSuccess; ++i) err = one(which, ev[(size_t)i]);
         if (err == hipSuccess) err = hipStreamSynchronize(s);
         double tot = 0.0;
         for (int i = 0; i < reps && err == hipSuccess; ++i) {
             float ms = 0.f;
-            err = hipEventElapsedTime(&ms, ev[(size_t)i].start, ev[(size_t)i].stop);
+            err = hipEventElapsedTime(&ms, ev[(size_t)i].ev_start, ev[(size_t)i].ev_stop);
             tot += ms;
         }
         us[which] = tot * 1e3 / reps;
@@ -776,8 +691,8 @@ int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps,
     if (sink) (void)hipFreeAsync(sink, s);
     (void)hipStreamSynchronize(s);
     for (auto& v : ev) {
-        if (v.start) (void)hipEventDestroy(v.start);
-        if (v.stop) (void)hipEventDestroy(v.stop);
+        if (v.ev_start) (void)hipEventDestroy(v.ev_start);
+        if (v.ev_stop) (void)hipEventDestroy(v.ev_stop);
     }
     // the state was overwritten: mark every slot free for the next solve
     (void)hipMemsetAsync(e->st, 0, sizeof(RhsState) * N, s);

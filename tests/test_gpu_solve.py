@@ -145,6 +145,37 @@ def test_graph_and_eager_bitwise(stag, ctx):
     assert np.array_equal(outs[0][1], outs[1][1]) and np.array_equal(outs[0][1], outs[2][1])
 
 
+@pytest.mark.parametrize("inner", ["f64", "f32", "f16s"])
+def test_consecutive_solves_new_rhs_buffers(stag, ctx, inner):
+    """One gauge, one solver workspace reused by solves whose right-hand
+    sides sit in different (freed and reallocated) buffers: each solve must
+    answer its own b (the fix-up kernels inside the cached graphs read b)."""
+    L, m, tol = (6, 6, 6, 6), 0.1, 1e-9
+    U = links(L, "haar", 71)
+    g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"))
+    p = stag.cg_params(tol=tol, inner=inner, graph_k=8)
+    xs = []
+    for seed in (72, 73, 74):
+        b = synth.gaussian_rhs(L, 2, seed)
+        fb = ctx.field(g, 0, "f64", 2).load(b)
+        fx = ctx.field(g, 0, "f64", 2)
+        rc, st = stag.stag_cg_solve(ctx, g, [m, m], fb, fx, p)
+        x = fx.store()
+        fb.destroy()
+        fx.destroy()
+        assert rc == 0, st
+        assert max(true_res(U, L, [m, m], b, x)) <= tol
+        xs.append(x)
+    # the last solve in a fresh context gives the same bits
+    with stag.Context(0) as c2:
+        g2 = c2.gauge(L, U, precisions=("f64", "f32", "f16s"))
+        b = synth.gaussian_rhs(L, 2, 74)
+        fb = c2.field(g2, 0, "f64", 2).load(b)
+        fx = c2.field(g2, 0, "f64", 2)
+        rc, st = stag.stag_cg_solve(c2, g2, [m, m], fb, fx, p)
+        assert rc == 0 and np.array_equal(fx.store(), xs[-1])
+
+
 def test_zero_rhs_and_nan(stag, ctx):
     L = (4, 4, 4, 4)
     U = links(L, "haar", 51)
