@@ -7,6 +7,8 @@
 // launches a kernel or appends it to a graph.
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "kern.h"
 #include "launch.h"
 
@@ -16,6 +18,28 @@ __device__ __forceinline__ char* slot(const VecArgs& a, int k, int r) {
     return (char*)a.f[k] + (size_t)r * a.rs[k];
 }
 
+// Own-site operands of a fused update: x (fp64 CG) or y (fp32, mixed CG),
+// then r (or rs), d and Ad in the iteration's precision.
+template <int P, int OP>
+struct UpdOps {
+    using T = typename Real<P>::T;
+    using A = typename std::conditional<OP == OP_UPD_CG, double, float>::type;
+    A ar[3], ai[3];
+    T sr[3], si[3], dr[3], di[3], qr[3], qi[3];
+};
+
+template <int P, int OP>
+__device__ __forceinline__ void load_upd(const VecArgs& a, int r, uint32_t s, UpdOps<P, OP>& u) {
+    if constexpr (OP == OP_UPD_CG) {
+        load_site<P64>(slot(a, 0, r), a.Vh, s, u.ar, u.ai);
+    } else {
+        load_site<P32>(slot(a, 0, r), a.Vh, s, u.ar, u.ai);
+    }
+    load_site<P>(slot(a, 1, r), a.Vh, s, u.sr, u.si);
+    load_site<P>(slot(a, 2, r), a.Vh, s, u.dr, u.di);
+    load_site<P>(slot(a, 3, r), a.Vh, s, u.qr, u.qi);
+}
+
 template <int P, int N, int OP>
 __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
     using T = typename Real<P>::T;
@@ -23,11 +47,31 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
     const uint32_t s = blk * kBlock + threadIdx.x;
     const uint32_t Vh = a.Vh;
     const bool valid = s < Vh;
-    // the state of every RHS, in LDS: finalised here from the previous
-    // reduction's partials when a.fin is set, else copied as it is
+    // Per-RHS state, finalised here from the previous reduction's partials
+    // when a.fin is set. One RHS: each wavefront keeps it in registers (no
+    // barrier) and an update requests its operands before alpha is summed.
+    // Several RHS: the block shares one copy in LDS.
+    constexpr bool UPD = OP == OP_UPD_CG || OP == OP_UPD_MIXED;
     __shared__ RhsState ls[N];
+    RhsState s1{};
     unsigned act = (1u << N) - 1u;
-    if (a.st) {
+    [[maybe_unused]] UpdOps<P, OP> u0;
+    if constexpr (N == 1) {
+        if (a.st) {
+            s1 = *a.st;
+            if (!(s1.flags & a.run_mask)) act = 0;
+        }
+        if constexpr (UPD) {
+            if (valid && act) load_upd<P, OP>(a, 0, s, u0);
+        }
+        if (a.st && a.fin.partials) {
+            // always: block 0 must pass the state on even when it is inactive
+            Reduce F = a.fin;
+            F.st = a.st;
+            finalize_wave1(F, a.run_mask, s1);
+            if (!(s1.flags & a.run_mask)) act = 0;
+        }
+    } else if (a.st) {
         if (a.fin.partials) {
             Reduce F = a.fin;
             F.st = a.st;
@@ -40,6 +84,13 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
         for (int r = 0; r < N; ++r)
             if (ls[r].flags & a.run_mask) act |= 1u << r;
     }
+    auto stv = [&](int r) -> const RhsState& {
+        if constexpr (N == 1) {
+            return s1;
+        } else {
+            return ls[r];
+        }
+    };
     double dv[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) dv[r] = 0.0;
@@ -76,46 +127,47 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
                 }
             } else if constexpr (OP == OP_UPD_CG) {
                 // x += alpha d; r -= alpha Ad; |r|^2   (all fp64)
-                const double al = ls[r].alpha;
-                double xr[3], xi[3], rr[3], ri[3], dr[3], di[3], qr[3], qi[3];
-                load_site<P64>(slot(a, 0, r), Vh, s, xr, xi);
-                load_site<P64>(slot(a, 1, r), Vh, s, rr, ri);
-                load_site<P64>(slot(a, 2, r), Vh, s, dr, di);
-                load_site<P64>(slot(a, 3, r), Vh, s, qr, qi);
+                const double al = stv(r).alpha;
+                UpdOps<P, OP> u;
+                if constexpr (N == 1) {
+                    u = u0;
+                } else {
+                    load_upd<P, OP>(a, r, s, u);
+                }
                 double acc = 0.0;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    xr[c] = fma(al, dr[c], xr[c]);
-                    xi[c] = fma(al, di[c], xi[c]);
-                    rr[c] = fma(-al, qr[c], rr[c]);
-                    ri[c] = fma(-al, qi[c], ri[c]);
-                    acc += rr[c] * rr[c] + ri[c] * ri[c];
+                    u.ar[c] = fma(al, u.dr[c], u.ar[c]);
+                    u.ai[c] = fma(al, u.di[c], u.ai[c]);
+                    u.sr[c] = fma(-al, u.qr[c], u.sr[c]);
+                    u.si[c] = fma(-al, u.qi[c], u.si[c]);
+                    acc += u.sr[c] * u.sr[c] + u.si[c] * u.si[c];
                 }
-                store_site<P64>(slot(a, 0, r), Vh, s, xr, xi);
-                store_site<P64>(slot(a, 1, r), Vh, s, rr, ri);
+                store_site<P64>(slot(a, 0, r), Vh, s, u.ar, u.ai);
+                store_site<P64>(slot(a, 1, r), Vh, s, u.sr, u.si);
                 dv[r] = acc;
             } else if constexpr (OP == OP_UPD_MIXED) {
                 // y += alpha d (fp32); rs = q(rs - alpha Ad); |rs|^2 of the stored rs
-                const float al = (float)ls[r].alpha;
-                float yr[3], yi[3];
-                T sr[3], si[3], dr[3], di[3], qr[3], qi[3];
-                load_site<P32>(slot(a, 0, r), Vh, s, yr, yi);
-                load_site<P>(slot(a, 1, r), Vh, s, sr, si);
-                load_site<P>(slot(a, 2, r), Vh, s, dr, di);
-                load_site<P>(slot(a, 3, r), Vh, s, qr, qi);
+                const float al = (float)stv(r).alpha;
+                UpdOps<P, OP> u;
+                if constexpr (N == 1) {
+                    u = u0;
+                } else {
+                    load_upd<P, OP>(a, r, s, u);
+                }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    yr[c] = fmaf(al, dr[c], yr[c]);
-                    yi[c] = fmaf(al, di[c], yi[c]);
-                    sr[c] = fmaf(-al, qr[c], sr[c]);
-                    si[c] = fmaf(-al, qi[c], si[c]);
+                    u.ar[c] = fmaf(al, u.dr[c], u.ar[c]);
+                    u.ai[c] = fmaf(al, u.di[c], u.ai[c]);
+                    u.sr[c] = fmaf(-al, u.qr[c], u.sr[c]);
+                    u.si[c] = fmaf(-al, u.qi[c], u.si[c]);
                 }
-                store_site<P32>(slot(a, 0, r), Vh, s, yr, yi);
-                store_site<P>(slot(a, 1, r), Vh, s, sr, si);
+                store_site<P32>(slot(a, 0, r), Vh, s, u.ar, u.ai);
+                store_site<P>(slot(a, 1, r), Vh, s, u.sr, u.si);
                 double acc = 0.0;
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    acc += (double)sr[c] * (double)sr[c] + (double)si[c] * (double)si[c];
+                    acc += (double)u.sr[c] * (double)u.sr[c] + (double)u.si[c] * (double)u.si[c];
                 dv[r] = acc;
             } else if constexpr (OP == OP_ZERO) {
                 T z[3] = {T(0), T(0), T(0)}, zi[3] = {T(0), T(0), T(0)};

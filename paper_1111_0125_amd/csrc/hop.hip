@@ -19,27 +19,47 @@
 
 namespace stag {
 
-// The operand at site n: the stored input, or, for a deferred direction
-// update, d_new = q(r + beta d) formed from the stored r and d.
+// What an operand is made of at one site: the stored input and, for a
+// deferred direction update, the stored residual.
 template <int P>
-__device__ __forceinline__ void load_operand(const HopArgs& a, const char* in_r, int r, uint32_t n,
-                                             double beta, typename Real<P>::T (&vr)[3],
-                                             typename Real<P>::T (&vi)[3]) {
+struct Raw {
+    typename Real<P>::T vr[3], vi[3], rr[3], ri[3];
+};
+
+// Load the raw operand of RHS r at site n (the residual only when `lazy`).
+template <int P>
+__device__ __forceinline__ void load_raw(const HopArgs& a, const char* in_r, int r, uint32_t n,
+                                         bool lazy, Raw<P>& w) {
+    load_site<P>(in_r, a.g.Vh, n, w.vr, w.vi);
+    if (lazy) load_site<P>((const char*)a.lazy_r + (size_t)r * a.lazy_r_rs, a.g.Vh, n, w.rr, w.ri);
+}
+
+// The operand from its raw parts: the stored input, or d_new = q(r + beta d)
+// for a deferred direction update; with `add_y` in the fp64 stages of a
+// reliable update (x gathered by stage 1, x at stage 2's own site), x + y.
+template <int P>
+__device__ __forceinline__ void combine(const HopArgs& a, const Raw<P>& w, int r, uint32_t n,
+                                        bool lazy, double beta, bool add_y,
+                                        typename Real<P>::T (&vr)[3],
+                                        typename Real<P>::T (&vi)[3]) {
     using T = typename Real<P>::T;
-    load_site<P>(in_r, a.g.Vh, n, vr, vi);
-    if (a.lazy_r) {
+    if (lazy) {
         const T be = (T)beta;
-        T rr[3], ri[3];
-        load_site<P>((const char*)a.lazy_r + (size_t)r * a.lazy_r_rs, a.g.Vh, n, rr, ri);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            vr[c] = fma(be, vr[c], rr[c]);
-            vi[c] = fma(be, vi[c], ri[c]);
+            vr[c] = fma(be, w.vr[c], w.rr[c]);
+            vi[c] = fma(be, w.vi[c], w.ri[c]);
         }
         round_site<P>(vr, vi);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            vr[c] = w.vr[c];
+            vi[c] = w.vi[c];
+        }
     }
     if constexpr (P == P64) {
-        if (a.lazy_y) {
+        if (add_y && a.lazy_y) {
             float yr[3], yi[3];
             load_site<P32>((const char*)a.lazy_y + (size_t)r * a.lazy_y_rs, a.g.Vh, n, yr, yi);
 #pragma unroll
@@ -51,6 +71,16 @@ __device__ __forceinline__ void load_operand(const HopArgs& a, const char* in_r,
     }
 }
 
+// The own-site operand of stage 2 (x, formed like a stage-1 operand).
+template <int P>
+__device__ __forceinline__ void load_operand(const HopArgs& a, const char* in_r, int r, uint32_t n,
+                                             bool lazy, double beta, typename Real<P>::T (&vr)[3],
+                                             typename Real<P>::T (&vi)[3]) {
+    Raw<P> w;
+    load_raw<P>(a, in_r, r, n, lazy, w);
+    combine<P>(a, w, r, n, lazy, beta, true, vr, vi);
+}
+
 template <int P, int S, int N, int EPI, bool NT>
 __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
     using T = typename Real<P>::T;
@@ -59,12 +89,43 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
     const uint32_t s = gt / S;
     const int j = (int)(gt % S);
     const uint32_t Vh = a.g.Vh;
+    const bool valid = s < Vh;
+    // stage 1 forms the deferred direction at the neighbours it gathers
+    const bool lazy_nb = EPI == EPI_PLAIN && a.lazy_r != nullptr;
 
-    // the state of every RHS, in LDS: finalised here from the previous
-    // reduction's partials when a.fin is set, else copied as it is
+    // Per-RHS state, finalised here from the previous reduction's partials
+    // when a.fin is set. One RHS: each wavefront keeps it in registers (no
+    // barrier), and the operands of the first hop pair are requested before
+    // the partials are summed, so the two memory latencies overlap. Several
+    // RHS: the block shares one copy in LDS.
     __shared__ RhsState ls[N];
+    RhsState s1{};
     unsigned act = (1u << N) - 1u;
-    if (a.st) {
+    int x = 0, y = 0, z = 0, t = 0;
+    if (valid) site_coords(a.g, s, a.p_out, x, y, z, t);
+    [[maybe_unused]] uint32_t nf0 = 0, nb0 = 0;
+    [[maybe_unused]] T lr0[18], li0[18];
+    [[maybe_unused]] Raw<P> wf0, wb0;
+    if constexpr (N == 1) {
+        if (a.st) {
+            s1 = *a.st;
+            if (!(s1.flags & a.run_mask)) act = 0;
+        }
+        if (valid && act) {
+            const int mu = j * (4 / S);
+            neighbours(a.g, s, x, y, z, t, mu, nf0, nb0);
+            load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, lr0, li0);
+            load_raw<P>(a, (const char*)a.in, 0, nf0, lazy_nb, wf0);
+            load_raw<P>(a, (const char*)a.in, 0, nb0, lazy_nb, wb0);
+        }
+        if (a.st && a.fin.partials) {
+            // always: block 0 must pass the state on even when it is inactive
+            Reduce F = a.fin;
+            F.st = a.st;
+            finalize_wave1(F, a.run_mask, s1);
+            if (!(s1.flags & a.run_mask)) act = 0;
+        }
+    } else if (a.st) {
         if (a.fin.partials) {
             Reduce F = a.fin;
             F.st = a.st;
@@ -77,6 +138,13 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
         for (int r = 0; r < N; ++r)
             if (ls[r].flags & a.run_mask) act |= 1u << r;
     }
+    auto stv = [&](int r) -> const RhsState& {
+        if constexpr (N == 1) {
+            return s1;
+        } else {
+            return ls[r];
+        }
+    };
 
     T ar[N][3], ai[N][3];
     [[maybe_unused]] T hr2[N][3], hi2[N][3];  // S = 1: sum of pairs 2 and 3 in progress
@@ -85,10 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) ar[r][c] = ai[r][c] = hr2[r][c] = hi2[r][c] = T(0);
 
-    const bool valid = s < Vh;
     if (valid && act) {
-        int x, y, z, t;
-        site_coords(a.g, s, a.p_out, x, y, z, t);
         // Each hop pair mu contributes p_mu = F_mu chi(x+mu) + B_mu chi(x-mu),
         // accumulated from zero; the pairs are combined as
         // (p0 + p1) + (p2 + p3), lane-locally for the pairs this lane owns
@@ -98,28 +163,38 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
         for (int k = 0; k < 4 / S; ++k) {
             const int mu = j * (4 / S) + k;
             uint32_t nf, nb;
-            neighbours(a.g, s, x, y, z, t, mu, nf, nb);
             T lr[18], li[18];
-            load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, lr, li);
+            if (N == 1 && k == 0) {
+                nf = nf0;
+                nb = nb0;
+#pragma unroll
+                for (int e = 0; e < 18; ++e) {
+                    lr[e] = lr0[e];
+                    li[e] = li0[e];
+                }
+            } else {
+                neighbours(a.g, s, x, y, z, t, mu, nf, nb);
+                load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, lr, li);
+            }
 #pragma unroll
             for (int r = 0; r < N; ++r) {
                 if (!((act >> r) & 1u)) continue;
                 const char* in_r = (const char*)a.in + (size_t)r * a.in_rs;
-                T vr[3], vi[3], pr[3] = {T(0), T(0), T(0)}, pi[3] = {T(0), T(0), T(0)};
-                // the deferred direction is the input of stage 1 only; stage 2
-                // gathers t as stored
-                if constexpr (EPI == EPI_PLAIN) {
-                    const double be = a.lazy_r ? ls[r].beta : 0.0;
-                    load_operand<P>(a, in_r, r, nf, be, vr, vi);
-                    matvec_acc(lr, li, 0, vr, vi, pr, pi);
-                    load_operand<P>(a, in_r, r, nb, be, vr, vi);
-                    matvec_acc(lr, li, 9, vr, vi, pr, pi);
+                const double be = lazy_nb ? stv(r).beta : 0.0;
+                Raw<P> wf, wb;
+                if (N == 1 && k == 0) {
+                    wf = wf0;
+                    wb = wb0;
                 } else {
-                    load_site<P>(in_r, Vh, nf, vr, vi);
-                    matvec_acc(lr, li, 0, vr, vi, pr, pi);
-                    load_site<P>(in_r, Vh, nb, vr, vi);
-                    matvec_acc(lr, li, 9, vr, vi, pr, pi);
+                    load_raw<P>(a, in_r, r, nf, lazy_nb, wf);
+                    load_raw<P>(a, in_r, r, nb, lazy_nb, wb);
                 }
+                T vr[3], vi[3], pr[3] = {T(0), T(0), T(0)}, pi[3] = {T(0), T(0), T(0)};
+                // stage 2 gathers t as stored
+                combine<P>(a, wf, r, nf, lazy_nb, be, EPI == EPI_PLAIN, vr, vi);
+                matvec_acc(lr, li, 0, vr, vi, pr, pi);
+                combine<P>(a, wb, r, nb, lazy_nb, be, EPI == EPI_PLAIN, vr, vi);
+                matvec_acc(lr, li, 9, vr, vi, pr, pi);
                 if constexpr (S == 1) {
                     // k = 0, 2 start a pair sum; k = 1, 3 complete it;
                     // k = 3 also adds the two pair sums
@@ -188,8 +263,8 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                 store_site<P>(out_r, Vh, s, ar[r], ai[r]);
             } else {
                 T xr[3], xi[3], hr[3], hi[3];
-                load_operand<P>(a, (const char*)a.x + (size_t)r * a.x_rs, r, s,
-                                a.lazy_r ? ls[r].beta : 0.0, xr, xi);
+                load_operand<P>(a, (const char*)a.x + (size_t)r * a.x_rs, r, s, a.lazy_r != nullptr,
+                                a.lazy_r ? stv(r).beta : 0.0, xr, xi);
                 if (a.lazy_r) store_site<P>((char*)a.x + (size_t)r * a.x_rs, Vh, s, xr, xi);
                 if constexpr (P == P64) {
                     if (a.lazy_y) {
@@ -199,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                         store_site<P32>((char*)a.lazy_y + (size_t)r * a.lazy_y_rs, Vh, s, z, zi);
                     }
                 }
-                const T m2 = (T)(a.st ? ls[r].m2 : a.m2[r]);
+                const T m2 = (T)(a.st ? stv(r).m2 : a.m2[r]);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     hr[c] = fma(m2, xr[c], -ar[r][c]);

@@ -480,4 +480,18 @@ __device__ __forceinline__ void finalize_block(const Reduce& R, unsigned run_mas
     }
 }
 
+// Single right-hand side, many-block consumer: every wavefront holds the
+// input state s (read by the caller), sums the partials and applies R.kind
+// in its own registers, bit-identically in every wave, so no barrier or LDS
+// is needed; thread 0 of block 0 writes the result to R.st_out (never to the
+// input: other waves may still be reading it).
+__device__ __forceinline__ void finalize_wave1(const Reduce& R, unsigned run_mask, RhsState& s) {
+    if (s.flags & run_mask) {
+        const double sum = wave_sum_partials(R.partials, R.nparts);
+        const bool t0 = blockIdx.x == 0 && threadIdx.x == 0;
+        finalize_one(R.kind, &s, sum, t0 && R.out ? R.out : nullptr);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *R.st_out = s;
+}
+
 }  // namespace stag
