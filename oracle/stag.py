@@ -386,8 +386,8 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=100,
     Inner iterations run on stored low-precision vectors (fp32 arithmetic,
     alpha and beta rounded to fp32 when applied); all inner products are
     accumulated in fp64 (Sec.3.2, last paragraph). The partial solution y is
-    fp32 (never fp16). Update trigger, applied both as reliable update and
-    as group-wise update ("we apply both"):
+    fp32 (never fp16). The update trigger starts both a reliable update and
+    a group-wise update at once (Sec.3.2 uses the two together):
 
     * |r_s| < delta * max|r_s| since the last update, or |r_s| within the
       requested tolerance: x += y in fp64, y = 0, r = b - A x in fp64, the
