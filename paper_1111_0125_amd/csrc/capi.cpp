@@ -80,15 +80,12 @@ HopTune get_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh) {
         auto it = ctx->tune.find(tune_key(prec, N, Vh));
         if (it != ctx->tune.end()) return it->second;
     }
-    // Heuristic default: enough lanes in flight to cover the 256 CUs with a
-    // few waves each; split sites across lanes on small lattices.
+    // Default (what the autotuner finds best on most lattices measured, from
+    // 16^3x32 to 32^3x64): one lane per site, non-temporal link loads,
+    // XCD-aware block order.
+    (void)Vh;
     HopTune t;
-    if (N == 1) {
-        const uint64_t target = 1u << 20;  // threads
-        int S = 1;
-        while (S < 4 && (uint64_t)Vh * S < target) S *= 2;
-        t.S1 = t.S2 = S;
-    }
+    t.S1 = t.S2 = 1;
     t.nt = 1;
     t.swizzle = 1;
     return t;
@@ -145,7 +142,6 @@ hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, con
         a.aux_rs = ex->aux_rs;
         a.aux_prec = ex->aux_prec;
     }
-    if (N > 1) S = 1;
     return launch_hop(prec, S, N, epi, t.nt != 0, a, is);
 }
 

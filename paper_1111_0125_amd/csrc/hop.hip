@@ -339,8 +339,17 @@ static hipError_t run_hop(const HopArgs& a, const Issue& is) {
                         hop_blocks(a.g.Vh, S), kBlock, args);
 }
 
+// Several RHS: non-temporal link loads, S in {1, 2, 4}.
+template <int P, int EPI, int N>
+static hipError_t run_block(int S, const HopArgs& a, const Issue& is) {
+    if (S == 1) return run_hop<P, 1, N, EPI, true>(a, is);
+    if (S == 2) return run_hop<P, 2, N, EPI, true>(a, is);
+    if (S == 4) return run_hop<P, 4, N, EPI, true>(a, is);
+    return hipErrorInvalidValue;
+}
+
 // Dispatch for this precision: N = 1 with S in {1, 2, 4} and both load
-// flavours; N > 1 with S = 1 and non-temporal link loads.
+// flavours; N > 1 with S in {1, 2, 4} and non-temporal link loads.
 template <int P, int EPI>
 static hipError_t dispatch_epi(int S, int N, bool nt, const HopArgs& a, const Issue& is) {
     if (N == 1) {
@@ -355,17 +364,15 @@ static hipError_t dispatch_epi(int S, int N, bool nt, const HopArgs& a, const Is
         }
         return hipErrorInvalidValue;
     }
-    if (S != 1) return hipErrorInvalidValue;
     switch (N) {
-        case 2: return run_hop<P, 1, 2, EPI, true>(a, is);
-        case 4: return run_hop<P, 1, 4, EPI, true>(a, is);
-        case 8: return run_hop<P, 1, 8, EPI, true>(a, is);
-        case 12: return run_hop<P, 1, 12, EPI, true>(a, is);
-        case 16: return run_hop<P, 1, 16, EPI, true>(a, is);
+        case 2: return run_block<P, EPI, 2>(S, a, is);
+        case 4: return run_block<P, EPI, 4>(S, a, is);
+        case 8: return run_block<P, EPI, 8>(S, a, is);
+        case 12: return run_block<P, EPI, 12>(S, a, is);
+        case 16: return run_block<P, EPI, 16>(S, a, is);
         default: return hipErrorInvalidValue;
     }
 }
-
 
 #define HOP_FN_NAME_(p) launch_hop_p##p
 #define HOP_FN_NAME(p) HOP_FN_NAME_(p)

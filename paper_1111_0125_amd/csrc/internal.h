@@ -187,6 +187,10 @@ void set_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh, const HopTune& t);
 // Engines (solver.cpp)
 int engine_acquire(stag_ctx* ctx, const stag_gauge* g, int prec, int N, stag_engine** out);
 void engine_release(stag_engine* e);
+// Whether the iteration kernels of e (nk right-hand sides per kernel)
+// finalise reductions at their start (small lattices) or leave it to a
+// one-block kernel (large ones).
+bool fuse_finalize(const stag_engine* e, int nk);
 // Average execution time (us) of the three iteration kernels of e under
 // tuning t (stage 1, stage 2, update), with the first nrhs slots active.
 int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps, double* us);

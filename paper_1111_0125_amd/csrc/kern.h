@@ -420,6 +420,7 @@ __device__ __forceinline__ double wave_sum_partials(const double* pp, int nparts
     const int lane = threadIdx.x & 63;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int i = lane;
+#pragma unroll 4
     for (; i + 192 < nparts; i += 256) {
         s0 += pp[i];
         s1 += pp[i + 64];

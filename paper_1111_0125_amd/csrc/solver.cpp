@@ -164,6 +164,19 @@ void engine_release(stag_engine* e) {
 
 // ------------------------------------------------------------------ enqueue helpers
 
+// Finalising a reduction at the start of its consumer costs every wave (one
+// RHS) or every block (several) one pass over all the chunk partials of the
+// RHS it serves. That pays on small lattices, where a separate one-block
+// kernel and its launch would be a large part of an iteration, and not on
+// large ones, where the passes would add up to a sizeable fraction of the
+// kernel's own traffic. Above this many partials per consumer the reduction
+// is finalised by a one-block kernel and consumers read the state.
+constexpr size_t kFuseMaxPartials = 2048;
+
+bool fuse_finalize(const stag_engine* e, int nk) {
+    return (size_t)num_chunks(e->Vh) * (size_t)nk <= kFuseMaxPartials;
+}
+
 namespace {
 
 struct Ctx {
@@ -212,8 +225,7 @@ hipError_t hop(const Ctx& c, int prec, int stage, int epi, const void* in, void*
                const Opt& o = Opt()) {
     stag_engine* e = c.e;
     const HopTune& t = prec == P64 && e->prec != P64 ? e->tune_64 : e->tune_lo;
-    int S = stage == 1 ? t.S1 : t.S2;
-    if (c.nk > 1) S = 1;
+    const int S = stage == 1 ? t.S1 : t.S2;
     const size_t rs = spinor_rhs_bytes(prec, e->Vh);
     Reduce red = make_red(e, kind, o.partials);
     RhsState* st = o.st ? o.st : e->st;
@@ -258,15 +270,17 @@ constexpr int kKernelsPerIteration = 3;
 //   stage 1  t = D_oe d, where d = r + beta d (the previous iteration's
 //            direction update, deferred) is formed at every neighbour;
 //   stage 2  d stored, Ad = m^2 d - D_eo t, chunk partials of <d, Ad>;
-//   update   alpha = |r|^2 / <d, Ad> finalised at kernel start, x (or y)
-//            += alpha d, r -= alpha Ad, chunk partials of |r|^2.
-// The |r|^2 of one update is finalised (beta, convergence and update
-// triggers) at the start of the next iteration's stage 1, and by a one-block
-// kernel after the last iteration, which leaves the state in e->st. A
-// many-block kernel that finalises reads one state buffer and its block 0
-// writes the other (update: st -> st1, stage 1: st1 -> st), and the two
-// reductions use separate partial buffers, so no kernel reads what it
-// writes.
+//   update   alpha = |r|^2 / <d, Ad>, x (or y) += alpha d, r -= alpha Ad,
+//            chunk partials of |r|^2.
+// Fused (small lattices): alpha is finalised at the start of the update, the
+// |r|^2 of one update (beta, convergence and update triggers) at the start
+// of the next iteration's stage 1, and by a one-block kernel after the last
+// iteration, which leaves the state in e->st. A many-block kernel that
+// finalises reads one state buffer and its block 0 writes the other (update:
+// st -> st1, stage 1: st1 -> st), and the two reductions use separate
+// partial buffers, so no kernel reads what it writes. Not fused (large
+// lattices): a one-block kernel finalises each reduction in place right
+// after the kernel that produced it.
 hipError_t enqueue_iterations(const Ctx& c, int K) {
     stag_engine* e = c.e;
     const bool mixed = e->prec != P64;
@@ -276,6 +290,7 @@ hipError_t enqueue_iterations(const Ctx& c, int K) {
     void* t = mixed ? e->t : e->t64;
     void* ad = mixed ? e->Ad : e->Ad64;
     void* r = mixed ? e->rs : e->r64;
+    const bool fuse = fuse_finalize(e, c.nk);
     Reduce pend_r = make_red(e, kind_r, e->partials1);
     pend_r.st = e->st1;
     pend_r.st_out = e->st;
@@ -285,18 +300,20 @@ hipError_t enqueue_iterations(const Ctx& c, int K) {
     hipError_t err;
     for (int k = 0; k < K; ++k) {
         Opt o1;
-        if (k > 0) {
+        if (fuse && k > 0) {
             o1.st = e->st1;
             o1.fin = &pend_r;
         }
         if ((err = hop(c, P, 1, EPI_PLAIN, d, t, nullptr, FIN_STORE, F_ACTIVE, r, o1))) return err;
         Opt o2;
-        o2.finalize = false;
+        o2.finalize = !fuse;
         if ((err = hop(c, P, 2, EPI_XPAY_DOT, t, ad, d, FIN_ALPHA, F_ACTIVE, r, o2))) return err;
         Opt ou;
-        ou.fin = &pend_a;
-        ou.finalize = false;
-        ou.partials = e->partials1;
+        if (fuse) {
+            ou.fin = &pend_a;
+            ou.finalize = false;
+            ou.partials = e->partials1;
+        }
         if (mixed) {
             err = vec(c, P, OP_UPD_MIXED,
                       {{e->y32, e->rs32}, {e->rs, e->rsP}, {e->d, e->rsP}, {e->Ad, e->rsP}},
@@ -308,6 +325,7 @@ hipError_t enqueue_iterations(const Ctx& c, int K) {
         }
         if (err) return err;
     }
+    if (!fuse) return hipSuccess;
     return timed_launch(c, KK_OTHER, [&]() { return launch_finalize(c.nk, pend_r, F_ACTIVE, c.is); });
 }
 
@@ -594,7 +612,8 @@ namespace stag {
 // Average execution time (microseconds, from events recorded at the start
 // and the end of each kernel) of the three iteration kernels of engine e
 // with tuning t, over `reps` launches each: stage 1 (finalising the
-// previous |r|^2), stage 2, update (finalising alpha). All of the first
+// previous |r|^2 where the solver fuses finalisations), stage 2, update
+// (finalising alpha where fused). All of the first
 // nrhs slots are active with alpha = beta = 0, so d = r and every vector
 // stays put, and the finalisations are FIN_STORE, so the state, and with it
 // the work, is the same on every launch. The state is cleared afterwards.
@@ -632,6 +651,7 @@ int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps,
         if (err == hipSuccess) err = hipEventCreate(&v.ev_stop);
     }
     const bool mixed = prec != P64;
+    const bool fuse = fuse_finalize(e, N);
     Reduce pend_r = make_red(e, FIN_STORE, e->partials1);
     pend_r.st = e->st1;
     pend_r.st_out = e->st;
@@ -648,10 +668,11 @@ int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps,
         void* tt = mixed ? e->t : e->t64;
         void* ad = mixed ? e->Ad : e->Ad64;
         if (which == 0)
-            return enqueue_hop(g, prec, N > 1 ? 1 : t.S1, N, EPI_PLAIN, t, dd, rs, tt, rs, 1, nullptr,
-                               0, nullptr, 0, nullptr, e->st1, F_ACTIVE, nullptr, is, rr, rs, &pend_r);
+            return enqueue_hop(g, prec, t.S1, N, EPI_PLAIN, t, dd, rs, tt, rs, 1, nullptr,
+                               0, nullptr, 0, nullptr, fuse ? e->st1 : e->st, F_ACTIVE, nullptr, is,
+                               rr, rs, fuse ? &pend_r : nullptr);
         if (which == 1)
-            return enqueue_hop(g, prec, N > 1 ? 1 : t.S2, N, EPI_XPAY_DOT, t, tt, rs, ad, rs, 0, dd,
+            return enqueue_hop(g, prec, t.S2, N, EPI_XPAY_DOT, t, tt, rs, ad, rs, 0, dd,
                                rs, nullptr, 0, nullptr, e->st, F_ACTIVE, &red, is, rr, rs);
         VecArgs a{};
         if (mixed) {
@@ -673,7 +694,7 @@ int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps,
         a.run_mask = F_ACTIVE;
         a.swizzle = t.swizzle;
         a.red = make_red(e, FIN_STORE, e->partials1);
-        a.fin = pend_a;
+        if (fuse) a.fin = pend_a;
         return launch_vec(prec, N, mixed ? OP_UPD_MIXED : OP_UPD_CG, a, is);
     };
     for (int which = 0; which < 3 && err == hipSuccess; ++which) {

@@ -159,21 +159,31 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, stag_tune_
     auto time_cfg = [&](const HopTune& tu, double* us) -> int {
         return time_iteration_kernels(e, tu, nrhs, reps, us);
     };
-    HopTune bestT;
-    double best1 = 1e30, best2 = 1e30, best3 = 1e30;
+    // The default shape is measured first and kept unless another is at
+    // least 2 % faster, so repeated tunings settle on the same shape.
+    constexpr double kGain = 0.98;
+    HopTune bestT = get_tune(ctx, prec, N, Vh);
+    bestT.S1 = bestT.S2 = 1;
+    bestT.nt = 1;
+    bestT.swizzle = 1;
+    double us0[3];
+    rc = time_cfg(bestT, us0);
+    double best1 = us0[0], best2 = us0[1], best3 = us0[2];
     const int Ss[] = {1, 2, 4};
     for (int nt = 0; nt <= 1 && rc == STAG_OK; ++nt)
         for (int sw = 0; sw <= 1 && rc == STAG_OK; ++sw)
             for (int S : Ss) {
-                if (N > 1 && S != 1) continue;
+                if (N > 1 && nt == 0) break;  // several RHS always load links non-temporally
                 HopTune tu;
                 tu.nt = nt;
                 tu.swizzle = sw;
                 tu.S1 = tu.S2 = S;
+                if (tu.nt == bestT.nt && tu.swizzle == bestT.swizzle && S == bestT.S1 && S == bestT.S2)
+                    continue;
                 double us[3];
                 if ((rc = time_cfg(tu, us))) break;
                 // one (nt, swizzle) pair serves all kernels; S is per stage
-                if (us[0] + us[1] + us[2] < best1 + best2 + best3) {
+                if (us[0] + us[1] + us[2] < kGain * (best1 + best2 + best3)) {
                     best1 = us[0];
                     best2 = us[1];
                     best3 = us[2];
@@ -182,16 +192,16 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, stag_tune_
             }
     // refine S per stage with the chosen (nt, swizzle)
     for (int S : Ss) {
-        if (rc != STAG_OK || (N > 1 && S != 1)) break;
+        if (rc != STAG_OK) break;
         HopTune tu = bestT;
         tu.S1 = tu.S2 = S;
         double us[3];
         if ((rc = time_cfg(tu, us))) break;
-        if (us[0] < best1) {
+        if (us[0] < kGain * best1) {
             best1 = us[0];
             bestT.S1 = S;
         }
-        if (us[1] < best2) {
+        if (us[1] < kGain * best2) {
             best2 = us[1];
             bestT.S2 = S;
         }
