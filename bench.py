@@ -103,6 +103,43 @@ def a_apply_bandwidth(stag, torch, costs, synth, reps=50):
     return out
 
 
+def c3_solves(stag, torch, synth, costs):
+    """32^3x64 Haar, m = 0.005, 1e-10: mixed CG with fp16+scale and with
+    fp32 inner iterations, and plain fp64 CG; time-to-tolerance each."""
+    name = "c3_32x32x32x64"
+    cfg = synth.CONFIGS[name]
+    L, m, tol = cfg["L"], cfg["mass"], cfg["tol"]
+    log("generating", name)
+    U = synth.config_links(name)
+    b = synth.config_rhs(name)
+    out = {"lattice": list(L), "mass": m, "tol": tol}
+    with stag.Context(0) as ctx:
+        g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"))
+        del U
+        fb = ctx.field(g, 0, "f64", 1).load(b)
+        fx = ctx.field(g, 0, "f64", 1)
+        for inner in ("f16s", "f32", "f64"):
+            stag.stag_tune(ctx, g, inner, 1)
+            p = stag.cg_params(tol=tol, inner=inner)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st = stag.stag_cg_solve(ctx, g, [m], fb, fx, p)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            s0 = st[0]
+            out[inner] = {"time_to_tol_s": round(dt, 4), "status": rc, "iters": s0["iters"],
+                          "reliable_updates": s0["reliable_updates"], "restarts": s0["restarts"],
+                          "true_rel_res": s0["true_rel_res"],
+                          "us_per_iteration": round(dt * 1e6 / max(s0["iters"], 1), 2)}
+            log("c3", inner, out[inner])
+    if out["f64"]["status"] == 0:
+        for inner in ("f16s", "f32"):
+            if out[inner]["status"] == 0:
+                out[f"speedup_{inner}_vs_f64"] = round(out["f64"]["time_to_tol_s"] /
+                                                       out[inner]["time_to_tol_s"], 3)
+    return out
+
+
 def batched_c4(stag, torch, synth):
     """24^3 x 48, exp(i 0.5 H) links, m = 0.01, 12 right-hand sides to 1e-8:
     one block solve (links loaded once per site for all 12) against one
@@ -340,6 +377,7 @@ def main():
 
     if not args.no_extras:
         result["a_apply_32x32x32x64"] = a_apply_bandwidth(stag, torch, costs, synth)
+        result["c3_32x32x32x64_solves"] = c3_solves(stag, torch, synth, costs)
         result["batched_24x24x24x48_12rhs"] = batched_c4(stag, torch, synth)
         result["serving"] = serving(stag, synth, n_requests=args.serve_requests,
                                     full=args.serve_full)

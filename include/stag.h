@@ -170,7 +170,12 @@ typedef struct stag_cg_params {
                           without halving the true residual; <= 0: 20 */
     int graph_k;       /* iterations per host poll (replayed as one HIP graph when
                           use_graph); <= 0: automatic */
-    int use_graph;     /* 1: capture the K-iteration block as a hipGraph */
+    int use_graph;     /* 1: replay each K-iteration block as one hipGraph */
+    int use_x0;        /* 1: x holds the initial guess on entry; 0: start from x = 0 */
+    int escalate;      /* F16S inner, gauge with an F32 copy: when the fp16-storage inner
+                          iteration stalls at its precision floor (ESTALL, here after at most
+                          3 stall updates without progress), continue from the current x
+                          with F32 inner iterations (no stall restarts); default 1 */
 } stag_cg_params;
 
 typedef struct stag_cg_stats {
@@ -181,20 +186,27 @@ typedef struct stag_cg_stats {
     double true_rel_res;   /* |b - A x| / |b| in fp64 at the end */
     double iter_rel_res;   /* iterated residual norm / |b| at the end */
     double seconds;        /* wall time of the whole call */
+    int inner_final;       /* inner precision of the last iterations (STAG_F16S solves
+                              that escalated end in STAG_F32) */
 } stag_cg_stats;
 
-/* Fill *p with the defaults (tol 1e-8, plain fp64 CG). */
+/* Fill *p with the defaults (tol 1e-8, plain fp64 CG, x from 0, escalation on). */
 void stag_cg_params_default(stag_cg_params* p);
 
 /* stag_cg_solve: solve A_j x_j = b_j (Sec.2 Eq.1, Fig.1; mixed: Sec.3.2)
  * for every right-hand side j of the even F64 field `b`, writing the even F64
- * field `x` (same nrhs; x starts from 0). mass: host array [b->nrhs]. All
+ * field `x` (same nrhs; x starts from 0, or from its contents with use_x0).
+ * mass: host array [b->nrhs]. All
  * right-hand sides of one call are iterated together, each with its own
  * scalars, sharing every link load. Success requires the fp64 true
  * residual |b - A x| <= tol |b| for each; b_j = 0 gives x_j = 0. Returns
  * after all solves ended (the host waits on `stream`); per-RHS outcomes are
  * in stats[j] (array of b->nrhs, may be NULL). The return value is STAG_OK
  * when every right-hand side converged, else the first failing status.
+ * With an F16S inner precision whose solve stalls (ESTALL) and `escalate`
+ * set, the call continues all right-hand sides from the current x with F32
+ * inner iterations (those already converged stop at once); stats add up both
+ * passes and report inner_final = STAG_F32.
  * Errors: EINVAL (arguments, non-finite b), ENOMEM, EDEVICE; ENOCONV,
  * EBREAKDOWN, ESTALL as solve outcomes (x holds the last iterate).
  */

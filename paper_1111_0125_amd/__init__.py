@@ -73,6 +73,8 @@ class CgParams(ctypes.Structure):
         ("max_stall", ctypes.c_int),
         ("graph_k", ctypes.c_int),
         ("use_graph", ctypes.c_int),
+        ("use_x0", ctypes.c_int),
+        ("escalate", ctypes.c_int),
     ]
 
 
@@ -85,6 +87,7 @@ class CgStats(ctypes.Structure):
         ("true_rel_res", ctypes.c_double),
         ("iter_rel_res", ctypes.c_double),
         ("seconds", ctypes.c_double),
+        ("inner_final", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -284,7 +287,7 @@ def stag_apply_A(ctx: Context, gauge: Gauge, mass, fin: Field, fout: Field, stre
 
 
 def cg_params(tol=1e-8, inner="f64", max_iter=0, delta=0.1, stall_iters=100, max_stall=20,
-              graph_k=0, use_graph=True) -> CgParams:
+              graph_k=0, use_graph=True, use_x0=False, escalate=True) -> CgParams:
     p = CgParams()
     lib.stag_cg_params_default(ctypes.byref(p))
     p.tol = tol
@@ -295,6 +298,8 @@ def cg_params(tol=1e-8, inner="f64", max_iter=0, delta=0.1, stall_iters=100, max
     p.max_stall = max_stall
     p.graph_k = graph_k
     p.use_graph = 1 if use_graph else 0
+    p.use_x0 = 1 if use_x0 else 0
+    p.escalate = 1 if escalate else 0
     return p
 
 

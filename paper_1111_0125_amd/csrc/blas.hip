@@ -100,11 +100,11 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
         for (int r = 0; r < N; ++r) {
             if (!((act >> r) & 1u)) continue;
             if constexpr (OP == OP_INIT_B) {
-                // r64 = b, x64 = 0, |b|^2
+                // r64 = b, x64 = 0 (kept when the slot starts from x0), |b|^2
                 double br[3], bi[3], z[3] = {0.0, 0.0, 0.0}, zi[3] = {0.0, 0.0, 0.0};
                 load_site<P64>(slot(a, 0, r), Vh, s, br, bi);
                 store_site<P64>(slot(a, 1, r), Vh, s, br, bi);
-                store_site<P64>(slot(a, 2, r), Vh, s, z, zi);
+                if (!a.st || !(stv(r).flags & F_X0)) store_site<P64>(slot(a, 2, r), Vh, s, z, zi);
                 double acc = 0.0;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) acc += br[c] * br[c] + bi[c] * bi[c];

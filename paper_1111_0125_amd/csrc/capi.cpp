@@ -1,7 +1,10 @@
 // C ABI entry points of libstag: contexts, gauges, fields, the Dirac
 // operator, A, and the CG solve. Argument validation happens here, before
 // any device work; the solver engine is in solver.cpp.
+#include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <limits>
 #include <cstdio>
 #include <cstring>
 
@@ -583,7 +586,13 @@ void stag_cg_params_default(stag_cg_params* p) {
     p->max_stall = 20;
     p->graph_k = 0;
     p->use_graph = 1;
+    p->use_x0 = 0;
+    p->escalate = 1;
 }
+
+// Stall restarts without a halving of the true residual after which an
+// escalating fp16 pass hands over to fp32.
+constexpr int kEscalateStalls = 3;
 
 int stag_cg_solve(stag_ctx* ctx, const stag_gauge* g, const double* mass, const stag_field* b,
                   stag_field* x, const stag_cg_params* params, stag_cg_stats* stats,
@@ -609,12 +618,54 @@ int stag_cg_solve(stag_ctx* ctx, const stag_gauge* g, const double* mass, const 
         if (!(mass[r] > 0.0) || !std::isfinite(mass[r]))
             return set_error(ctx, STAG_EINVAL, "stag_cg_solve: mass[%d] must be finite and > 0", r);
     DeviceGuard dg(ctx->device);
+    const int n = b->nrhs;
+    hipStream_t s = pick_stream(ctx, stream);
+    const auto t0 = std::chrono::steady_clock::now();
+    const bool can_escalate = p.inner_prec == STAG_F16S && p.escalate && (g->mask & STAG_MASK_F32);
+    // with somewhere to go, an fp16 pass gives up after a few stall restarts
+    // without progress instead of the full max_stall
+    stag_cg_params p1 = p;
+    if (can_escalate) p1.max_stall = std::min(p.max_stall > 0 ? p.max_stall : 20, kEscalateStalls);
+    std::vector<stag_cg_stats> st1(n);
     stag_engine* e = nullptr;
-    int rc = engine_acquire(ctx, g, p.inner_prec, pick_n(b->nrhs), &e);
+    int rc = engine_acquire(ctx, g, p.inner_prec, pick_n(n), &e);
     if (rc) return rc;
-    rc = engine_solve(e, b->nrhs, mass, b->data, b->rs, x->data, x->rs, p, stats,
-                      pick_stream(ctx, stream));
+    rc = engine_solve(e, n, mass, b->data, b->rs, x->data, x->rs, p1, st1.data(), s);
     engine_release(e);
+    bool stalled = false;
+    for (const auto& t : st1) stalled |= t.status == STAG_ESTALL;
+    if (stalled && can_escalate) {
+        // fp16 storage has hit its precision floor: continue from the current
+        // x with fp32 inner iterations (converged RHS stop at their start).
+        // fp32 needs no stall restarts (they would throw away the Krylov
+        // space while the slow modes left over by the fp16 pass converge).
+        stag_cg_params p2 = p;
+        p2.inner_prec = STAG_F32;
+        p2.use_x0 = 1;
+        p2.stall_iters = std::numeric_limits<int>::max();
+        std::vector<stag_cg_stats> st2(n);
+        rc = engine_acquire(ctx, g, STAG_F32, pick_n(n), &e);
+        if (rc) return rc;
+        rc = engine_solve(e, n, mass, b->data, b->rs, x->data, x->rs, p2, st2.data(), s);
+        engine_release(e);
+        if (rc == STAG_EINVAL || rc == STAG_ENOMEM || rc == STAG_EDEVICE) return rc;
+        const double secs =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int r = 0; r < n; ++r) {
+            stag_cg_stats& a = st1[r];
+            const stag_cg_stats& c = st2[r];
+            a.iters += c.iters;
+            a.reliable_updates += c.reliable_updates;
+            a.restarts += c.restarts;
+            a.status = c.status;
+            a.true_rel_res = c.true_rel_res;
+            a.iter_rel_res = c.iter_rel_res;
+            a.seconds = secs;
+            a.inner_final = STAG_F32;
+        }
+    }
+    if (stats)
+        for (int r = 0; r < n; ++r) stats[r] = st1[r];
     return rc;
 }
 

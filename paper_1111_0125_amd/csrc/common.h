@@ -139,7 +139,8 @@ enum StateFlag : unsigned {
     F_MAXIT = 64u,       // iteration cap reached
     F_ESTALL = 128u,     // repeated stall restarts without progress
     F_BADINPUT = 256u,   // |b|^2 not finite
-    F_NEW = 512u,        // slot being started (from x = 0)
+    F_NEW = 512u,        // slot being started
+    F_X0 = 1024u,        // slot being started from an initial guess x0
 };
 
 struct RhsState {
@@ -174,10 +175,12 @@ enum FinKind : int {
     FIN_CG = 2,        // |r|^2 -> beta, convergence / cap (plain CG)
     FIN_MIXED = 3,     // |r|^2 -> beta, update / stall triggers (mixed CG)
     FIN_TRUE = 4,      // rr_true = sum
-    FIN_INIT = 5,      // bb = sum; start state of a solve from x = 0
+    FIN_INIT = 5,      // bb = sum; start state of a solve (from x = 0, or pending x0)
     FIN_RU_END = 6,    // rr_true = sum, then the state after a reliable / group-wise
                        // update (mixed CG)
     FIN_CG_CHECK = 7,  // rr_true = sum, then accept or restart (plain CG)
+    FIN_X0 = 8,        // |b - A x0|^2 = sum: residual state of a start from x0
+    FIN_ACTIVATE = 9,  // a started slot begins iterating
 };
 
 // A reduction: the producing kernel writes one fp64 partial per 64-site

@@ -146,6 +146,7 @@ struct SlotInit {
     int slot;
     double mass;
     stag_cg_params params;
+    const void* x0 = nullptr;  // initial guess (fp64 internal layout, one RHS) or null: x = 0
 };
 
 void run_init(EngineRun& R, stag_engine* e, hipStream_t s, const void* b, size_t b_rs, int K,
@@ -153,7 +154,7 @@ void run_init(EngineRun& R, stag_engine* e, hipStream_t s, const void* b, size_t
 int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots);
 int run_enqueue_block(EngineRun& R);
 int run_process_poll(EngineRun& R, bool blocking, const RhsState** h);
-void fill_stats(const RhsState& s, double secs, stag_cg_stats* out);
+void fill_stats(const RhsState& s, double secs, int inner_prec, stag_cg_stats* out);
 bool flags_terminal(unsigned f);
 int status_of_flags(unsigned f);
 int default_graph_k(uint32_t Vh);

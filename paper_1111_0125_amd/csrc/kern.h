@@ -281,7 +281,10 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
         case FIN_TRUE:
             s.rr_true = sum;
             break;
-        case FIN_INIT:
+        case FIN_INIT: {
+            // the slot stays F_NEW (with F_X0 when it starts from x0) until
+            // its first direction is set; b = 0 finishes it at once
+            const unsigned x0 = s.flags & F_X0;
             s.bb = sum;
             s.rr_stop = s.tol2 * sum;
             s.rr = s.rr_old = s.rr_true = s.best_true = sum;
@@ -290,11 +293,27 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
             s.beta = 0.0;  // first direction d = r
             if (!isfinite(sum)) {
                 s.flags = F_BADINPUT;
-            } else if (sum == 0.0 || sum <= s.rr_stop) {
+            } else if (sum == 0.0 || (!x0 && sum <= s.rr_stop)) {
                 s.flags = F_DONE;
             } else {
-                s.flags = F_ACTIVE;
+                s.flags = F_NEW | x0;
             }
+            break;
+        }
+        case FIN_X0:
+            // r = b - A x0 replaces r = b
+            s.rr = s.rr_old = s.rr_true = s.best_true = sum;
+            s.rmax = s.rmin = sqrt(sum);
+            if (!isfinite(sum)) {
+                s.flags = F_BADINPUT;
+            } else if (sum <= s.rr_stop) {
+                s.flags = F_DONE;
+            } else {
+                s.flags = F_NEW;
+            }
+            break;
+        case FIN_ACTIVATE:
+            s.flags = F_ACTIVE;
             break;
         case FIN_RU_END: {
             const double rt = sum;

@@ -203,7 +203,7 @@ static void harvest(Serve* S, Batch* b, const RhsState* h) {
         if (!flags_terminal(h[s].flags)) continue;
         const int r = b->slot_rhs[s];
         const double secs = std::chrono::duration<double>(Clock::now() - t->t_submit).count();
-        fill_stats(h[s], secs, &t->stats[r]);
+        fill_stats(h[s], secs, b->prec, &t->stats[r]);
         // x64 (colour-major fp64) -> canonical complex128 [Vh][3] of the result
         hipError_t err = launch_export(P64, (char*)b->e->x64 + (size_t)s * b->e->rs64, b->e->rs64,
                                        (char*)t->x_dev + (size_t)r * Vh * 48, (uint32_t)Vh, 1,

@@ -425,13 +425,16 @@ void run_init(EngineRun& R, stag_engine* e, hipStream_t s, const void* b, size_t
 
 int default_graph_k(uint32_t Vh) { return Vh >= 262144 ? 16 : (Vh >= 32768 ? 32 : 64); }
 
-// Start the given slots from x = 0: per-slot initial state, then the first
-// direction d = r = b and |b|^2 (the finalisation turns F_NEW into
-// F_ACTIVE, F_DONE for b = 0, or F_BADINPUT).
+// Start the given slots, from x = 0 or from an initial guess x0: per-slot
+// initial state, r = b and |b|^2 (FIN_INIT), for x0 slots r = b - A x0 in
+// fp64 and its norm (FIN_X0), then the first direction d = r (rounded to the
+// inner precision, y = 0) and the switch to F_ACTIVE. b = 0 finishes a slot
+// at once (FIN_INIT: F_DONE), a non-finite b with F_BADINPUT.
 int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots) {
     stag_engine* e = R.e;
     if (slots.empty()) return STAG_OK;
     const uint64_t n_unknowns = 3ull * e->Vh;
+    bool any_x0 = false;
     for (const SlotInit& si : slots) {
         RhsState& s = e->hstage[si.slot];
         std::memset(&s, 0, sizeof(s));
@@ -442,22 +445,35 @@ int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots) {
         s.stall_iters = p.stall_iters > 0 ? p.stall_iters : 100;
         s.max_stall = p.max_stall > 0 ? p.max_stall : 20;
         s.max_iter = p.max_iter > 0 ? p.max_iter : (int)std::min<uint64_t>(10 * n_unknowns, 1000000);
-        s.flags = F_NEW;
+        s.flags = F_NEW | (si.x0 ? F_X0 : 0u);
         RCK(hipMemcpyAsync(e->st + si.slot, &s, sizeof(RhsState), hipMemcpyHostToDevice, R.s));
+        if (si.x0) {
+            RCK(hipMemcpyAsync((char*)e->x64 + (size_t)si.slot * e->rs64, si.x0, e->rs64,
+                               hipMemcpyDeviceToDevice, R.s));
+            any_x0 = true;
+        }
         if (si.slot + 1 > R.busy_hi) R.busy_hi = si.slot + 1;
         // polls of blocks launched before this start show the slot's previous state
         R.start_after[si.slot] = R.launched - 1;
     }
     Ctx c{e, Issue{R.s}, pick_n(R.busy_hi), R.timed};
     void* b = const_cast<void*>(R.b);
+    RCK(vec(c, P64, OP_INIT_B, {{b, R.b_rs}, {e->r64, e->rs64}, {e->x64, e->rs64}}, FIN_INIT, F_NEW));
+    if (any_x0) {
+        RCK(hop(c, P64, 1, EPI_PLAIN, e->x64, e->t64, nullptr, FIN_STORE, F_X0));
+        RCK(hop(c, P64, 2, EPI_RESID, e->t64, e->r64, e->x64, FIN_X0, F_X0));
+    }
     if (e->prec != P64) {
-        RCK(vec(c, e->prec, OP_START, {{b, R.b_rs}, {e->d, e->rsP}, {e->rs, e->rsP}, {e->y32, e->rs32}},
-                FIN_STORE, F_NEW));
+        RCK(vec(c, e->prec, OP_START,
+                {{e->r64, e->rs64}, {e->d, e->rsP}, {e->rs, e->rsP}, {e->y32, e->rs32}}, FIN_STORE,
+                F_NEW));
     } else {
-        RCK(vec(c, P64, OP_START, {{b, R.b_rs}, {e->d64, e->rs64}, {nullptr, 0}, {nullptr, 0}},
+        RCK(vec(c, P64, OP_START, {{e->r64, e->rs64}, {e->d64, e->rs64}, {nullptr, 0}, {nullptr, 0}},
                 FIN_STORE, F_NEW));
     }
-    RCK(vec(c, P64, OP_INIT_B, {{b, R.b_rs}, {e->r64, e->rs64}, {e->x64, e->rs64}}, FIN_INIT, F_NEW));
+    Reduce act = make_red(e, FIN_ACTIVATE);
+    act.nparts = 0;  // a state transition: nothing to sum
+    RCK(timed_launch(c, KK_OTHER, [&]() { return launch_finalize(c.nk, act, F_NEW, c.is); }));
     return STAG_OK;
 }
 
@@ -543,7 +559,7 @@ int run_process_poll(EngineRun& R, bool blocking, const RhsState** h) {
     return STAG_OK;
 }
 
-void fill_stats(const RhsState& s, double secs, stag_cg_stats* out) {
+void fill_stats(const RhsState& s, double secs, int inner_prec, stag_cg_stats* out) {
     out->iters = s.iters;
     out->reliable_updates = s.updates;
     out->restarts = s.restarts;
@@ -551,6 +567,7 @@ void fill_stats(const RhsState& s, double secs, stag_cg_stats* out) {
     out->true_rel_res = s.bb > 0 ? std::sqrt(s.rr_true / s.bb) : 0.0;
     out->iter_rel_res = s.bb > 0 ? std::sqrt(s.rr / s.bb) : 0.0;
     out->seconds = secs;
+    out->inner_final = inner_prec;
 }
 
 // ------------------------------------------------------------------ one-shot solve
@@ -564,7 +581,10 @@ int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, siz
     EngineRun R;
     run_init(R, e, stream, e->b64, e->rs64, K, p.use_graph != 0);
     std::vector<SlotInit> slots(n);
-    for (int r = 0; r < n; ++r) slots[r] = SlotInit{r, mass[r], p};
+    for (int r = 0; r < n; ++r) {
+        slots[r] = SlotInit{r, mass[r], p};
+        if (p.use_x0) slots[r].x0 = (const char*)x_out + (size_t)r * x_rs;
+    }
     int rc = run_start_slots(R, slots);
     if (rc) return rc;
     const long long max_blocks = (2ll * (p.max_iter > 0 ? p.max_iter : 1000000)) / K + 4096;
@@ -588,6 +608,9 @@ int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, siz
     }
     RCK(hipStreamSynchronize(stream));
     RCK(hipMemcpy2DAsync(x_out, x_rs, e->x64, e->rs64, e->rs64, n, hipMemcpyDeviceToDevice, stream));
+    for (int r = 0; r < n; ++r)  // b = 0 (finished at its start): x = 0 whatever x0 was
+        if (fin[r].bb == 0.0 && fin[r].flags == F_DONE)
+            RCK(hipMemsetAsync((char*)x_out + (size_t)r * x_rs, 0, e->rs64, stream));
     RCK(hipStreamSynchronize(stream));
     if (R.timed) timing_collect(e->ctx);
     const double secs =
@@ -595,7 +618,7 @@ int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, siz
     rc = STAG_OK;
     for (int r = 0; r < n; ++r) {
         stag_cg_stats s;
-        fill_stats(fin[r], secs, &s);
+        fill_stats(fin[r], secs, e->prec, &s);
         if (stats) stats[r] = s;
         if (rc == STAG_OK && s.status != STAG_OK) rc = s.status;
     }

@@ -34,7 +34,7 @@ def true_res(U, L, masses, b, x):
 
 
 def solve(stag, ctx, L, U, b, masses, tol, inner="f64", precisions=None, **kw):
-    precisions = precisions or ("f64",) if inner == "f64" else ("f64", inner)
+    precisions = precisions or (("f64",) if inner == "f64" else ("f64", inner))
     g = ctx.gauge(L, U, precisions=precisions)
     fb = ctx.field(g, 0, "f64", b.shape[0]).load(b)
     fx = ctx.field(g, 0, "f64", b.shape[0])
@@ -174,6 +174,54 @@ def test_consecutive_solves_new_rhs_buffers(stag, ctx, inner):
         fx = c2.field(g2, 0, "f64", 2)
         rc, st = stag.stag_cg_solve(c2, g2, [m, m], fb, fx, p)
         assert rc == 0 and np.array_equal(fx.store(), xs[-1])
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32", "f16s"])
+def test_initial_guess(stag, ctx, inner):
+    """use_x0: the exact solution needs no iteration, a perturbed one converges
+    to the same tolerance, and b = 0 gives x = 0 whatever x0 was."""
+    L, m, tol = (6, 6, 6, 6), 0.1, 1e-10
+    U = links(L, "haar", 81)
+    b = synth.gaussian_rhs(L, 2, 82)
+    b[1] = 0.0
+    g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"))
+    fb = ctx.field(g, 0, "f64", 2).load(b)
+    fx = ctx.field(g, 0, "f64", 2)
+    rc, st = stag.stag_cg_solve(ctx, g, [m, m], fb, fx, stag.cg_params(tol=tol, inner=inner))
+    assert rc == 0
+    x = fx.store()
+    assert not np.any(x[1])
+    # restart from the converged answer: nothing to do
+    rc, st = stag.stag_cg_solve(ctx, g, [m, m], fb, fx, stag.cg_params(tol=tol, inner=inner, use_x0=True))
+    assert rc == 0 and st[0]["iters"] == 0 and np.array_equal(fx.store()[0], x[0])
+    # from a perturbed guess; the b = 0 slot returns x = 0
+    x0 = x + 1e-3 * synth.gaussian_rhs(L, 2, 83)
+    fx.load(x0)
+    rc, st = stag.stag_cg_solve(ctx, g, [m, m], fb, fx, stag.cg_params(tol=tol, inner=inner, use_x0=True))
+    xr = fx.store()
+    assert rc == 0 and 0 < st[0]["iters"]
+    assert true_res(U, L, [m], b[:1], xr[:1])[0] <= tol
+    assert not np.any(xr[1])
+    g.destroy()
+
+
+def test_f16s_escalates_to_f32(stag, ctx):
+    """An fp16-storage inner solve that stalls (forced here with a tiny stall
+    window) ends in ESTALL without escalation, and with it continues in fp32
+    from the current x to the requested true residual."""
+    L, m, tol = (8, 8, 8, 8), 0.01, 1e-10
+    U = links(L, "haar", 91)
+    b = synth.gaussian_rhs(L, 1, 92)
+    rc, st, x = solve(stag, ctx, L, U, b, [m], tol, inner="f16s", precisions=("f64", "f32", "f16s"),
+                      stall_iters=3, max_stall=1, escalate=False)
+    log("no escalation", rc, st[0])
+    assert rc == stag.STAG_ESTALL and st[0]["inner_final"] == stag.PREC["f16s"]
+    rc, st, x = solve(stag, ctx, L, U, b, [m], tol, inner="f16s", precisions=("f64", "f32", "f16s"),
+                      stall_iters=3, max_stall=1)
+    log("escalated", rc, st[0])
+    assert rc == 0 and st[0]["inner_final"] == stag.PREC["f32"]
+    assert true_res(U, L, [m], b, x)[0] <= tol
+    assert abs(st[0]["true_rel_res"] - true_res(U, L, [m], b, x)[0]) <= 1e-12
 
 
 def test_zero_rhs_and_nan(stag, ctx):
