@@ -365,6 +365,16 @@ def main():
                              "true_rel_res": st64["true_rel_res"],
                              "solves_per_s": round(1 / s64, 3)}
         result["speedup_mixed_vs_fp64"] = round(s64 / sec, 3)
+        # the plain iterative refinement of Fig.2 (direction restarted at each
+        # update) on the same system, against the Eq.6 carry-over above
+        prs = stag.cg_params(tol=tol, inner=inner, mixed_variant="restart")
+        stag.stag_cg_solve(ctx, g, [mass], fb, fx, prs)
+        srs, strs = timed_solves(stag, torch, ctx, g, mass, fb, fx, prs, 2)
+        result["fig2_restart_variant"] = {"time_to_1e-8_ms": round(srs * 1e3, 3),
+                                          "iters": strs["iters"],
+                                          "updates": strs["reliable_updates"],
+                                          "true_rel_res": strs["true_rel_res"],
+                                          "iters_vs_eq6_carry": round(strs["iters"] / max(iters, 1), 3)}
         p16 = stag.cg_params(tol=tol, inner="f16s")
         stag.stag_cg_solve(ctx, g, [mass], fb, fx, p16)
         s16, st16 = timed_solves(stag, torch, ctx, g, mass, fb, fx, p16, 2)

@@ -176,7 +176,17 @@ typedef struct stag_cg_params {
                           iteration stalls at its precision floor (ESTALL, here after at most
                           3 stall updates without progress), continue from the current x
                           with F32 inner iterations (no stall restarts); default 1 */
+    int mixed_variant; /* mixed: what an update does with the search direction.
+                          STAG_MIXED_CARRY (default): keep it, d = r + beta d with
+                          beta = |r_true|^2 / |r_prev|^2 (Sec.3.2, Eq.6); the inner cycle
+                          ends when |r| < delta max|r| since the update.
+                          STAG_MIXED_RESTART: restart it, d = r, every update (the plain
+                          iterative refinement of Fig.2); the cycle ends when
+                          |r| < delta |r at the cycle start|. */
 } stag_cg_params;
+
+#define STAG_MIXED_CARRY 0
+#define STAG_MIXED_RESTART 1
 
 typedef struct stag_cg_stats {
     int iters;             /* CG iterations (inner iterations for mixed) */

@@ -37,6 +37,7 @@ STAG_ENOTFOUND = -8
 
 F64, F32, F16S = 0, 1, 2
 PREC = {"f64": F64, "f32": F32, "f16s": F16S}
+MIXED_CARRY, MIXED_RESTART = 0, 1
 MAX_RHS = 16
 
 STATUS_NAME = {
@@ -75,6 +76,7 @@ class CgParams(ctypes.Structure):
         ("use_graph", ctypes.c_int),
         ("use_x0", ctypes.c_int),
         ("escalate", ctypes.c_int),
+        ("mixed_variant", ctypes.c_int),
     ]
 
 
@@ -287,7 +289,8 @@ def stag_apply_A(ctx: Context, gauge: Gauge, mass, fin: Field, fout: Field, stre
 
 
 def cg_params(tol=1e-8, inner="f64", max_iter=0, delta=0.1, stall_iters=100, max_stall=20,
-              graph_k=0, use_graph=True, use_x0=False, escalate=True) -> CgParams:
+              graph_k=0, use_graph=True, use_x0=False, escalate=True,
+              mixed_variant="carry") -> CgParams:
     p = CgParams()
     lib.stag_cg_params_default(ctypes.byref(p))
     p.tol = tol
@@ -300,6 +303,7 @@ def cg_params(tol=1e-8, inner="f64", max_iter=0, delta=0.1, stall_iters=100, max
     p.use_graph = 1 if use_graph else 0
     p.use_x0 = 1 if use_x0 else 0
     p.escalate = 1 if escalate else 0
+    p.mixed_variant = {"carry": MIXED_CARRY, "restart": MIXED_RESTART}[mixed_variant]
     return p
 
 

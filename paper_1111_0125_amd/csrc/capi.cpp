@@ -588,6 +588,7 @@ void stag_cg_params_default(stag_cg_params* p) {
     p->use_graph = 1;
     p->use_x0 = 0;
     p->escalate = 1;
+    p->mixed_variant = STAG_MIXED_CARRY;
 }
 
 // Stall restarts without a halving of the true residual after which an
@@ -611,6 +612,8 @@ int stag_cg_solve(stag_ctx* ctx, const stag_gauge* g, const double* mass, const 
         return set_error(ctx, STAG_EINVAL, "stag_cg_solve: tol must be in (0, 1)");
     if (p.inner_prec < 0 || p.inner_prec > 2)
         return set_error(ctx, STAG_EINVAL, "stag_cg_solve: inner precision %d", p.inner_prec);
+    if (p.mixed_variant != STAG_MIXED_CARRY && p.mixed_variant != STAG_MIXED_RESTART)
+        return set_error(ctx, STAG_EINVAL, "stag_cg_solve: mixed_variant %d", p.mixed_variant);
     if (!(g->mask & STAG_MASK_F64) || !(g->mask & (1 << p.inner_prec)))
         return set_error(ctx, STAG_EINVAL,
                          "stag_cg_solve: gauge needs the F64 copy and the inner-precision copy");

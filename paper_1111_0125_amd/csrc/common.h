@@ -156,6 +156,7 @@ struct RhsState {
     double delta;     // update threshold (fraction of the running maximum)
     double tol2;      // tol^2
     double m2;        // mass^2
+    double rstart;    // |r| when the current inner cycle started (last update)
     int since;        // iterations since the last new residual minimum
     int stall_iters;
     int stall_count;
@@ -165,7 +166,15 @@ struct RhsState {
     int updates;
     int restarts;
     unsigned flags;
-    int pad;
+    int variant;      // mixed CG: MIXED_CARRY (Sec.3.2, Eq.6) or MIXED_RESTART (Fig.2)
+};
+
+// Mixed CG variants: what an update does with the search direction.
+enum MixedVariant : int {
+    MIXED_CARRY = 0,    // keep it, d = r + beta d with beta from Eq.6; the inner
+                        // cycle ends when |r| < delta * max|r| since the update
+    MIXED_RESTART = 1,  // restart it, d = r (iterative refinement of Fig.2); the
+                        // cycle ends when |r| < delta * |r at the cycle start|
 };
 
 // Finalisation applied to a reduced sum (by the one-block finalize kernel).

@@ -269,7 +269,8 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
             }
             if (!isfinite(sum)) {
                 s.flags = F_BREAKDOWN;
-            } else if (rn < s.delta * s.rmax || sum <= s.rr_stop) {
+            } else if (rn < s.delta * (s.variant == MIXED_RESTART ? s.rstart : s.rmax) ||
+                       sum <= s.rr_stop) {
                 s.flags = F_RU;
             } else if (s.since >= s.stall_iters) {
                 s.flags = F_STALL;
@@ -288,7 +289,7 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
             s.bb = sum;
             s.rr_stop = s.tol2 * sum;
             s.rr = s.rr_old = s.rr_true = s.best_true = sum;
-            s.rmax = s.rmin = sqrt(sum);
+            s.rmax = s.rmin = s.rstart = sqrt(sum);
             s.since = 0;
             s.beta = 0.0;  // first direction d = r
             if (!isfinite(sum)) {
@@ -303,7 +304,7 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
         case FIN_X0:
             // r = b - A x0 replaces r = b
             s.rr = s.rr_old = s.rr_true = s.best_true = sum;
-            s.rmax = s.rmin = sqrt(sum);
+            s.rmax = s.rmin = s.rstart = sqrt(sum);
             if (!isfinite(sum)) {
                 s.flags = F_BADINPUT;
             } else if (sum <= s.rr_stop) {
@@ -335,8 +336,10 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
                 break;
             }
             // Eq.6: the next direction is r + beta d with beta = |r_true|^2 / |r_prev|^2;
-            // a stall restarts the direction from r (beta = 0)
-            s.beta = stall ? 0.0 : rt / s.rr_old;
+            // a stall, and every update of the Fig.2 variant, restarts it from r
+            const bool restart = stall || s.variant == MIXED_RESTART;
+            s.beta = restart ? 0.0 : rt / s.rr_old;
+            if (restart && !stall) s.restarts += 1;
             if (stall) {
                 s.restarts += 1;
                 if (rt < 0.25 * s.best_true) {
@@ -352,7 +355,7 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
                 break;
             }
             s.rr = rt;
-            s.rmax = s.rmin = sqrt(rt);
+            s.rmax = s.rmin = s.rstart = sqrt(rt);
             s.since = 0;
             s.flags = F_ACTIVE;
             break;

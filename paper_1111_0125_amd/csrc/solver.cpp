@@ -446,6 +446,7 @@ int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots) {
         s.max_stall = p.max_stall > 0 ? p.max_stall : 20;
         s.max_iter = p.max_iter > 0 ? p.max_iter : (int)std::min<uint64_t>(10 * n_unknowns, 1000000);
         s.flags = F_NEW | (si.x0 ? F_X0 : 0u);
+        s.variant = p.mixed_variant == MIXED_RESTART ? MIXED_RESTART : MIXED_CARRY;
         RCK(hipMemcpyAsync(e->st + si.slot, &s, sizeof(RhsState), hipMemcpyHostToDevice, R.s));
         if (si.x0) {
             RCK(hipMemcpyAsync((char*)e->x64 + (size_t)si.slot * e->rs64, si.x0, e->rs64,

@@ -113,6 +113,26 @@ def test_mixed_true_residual_and_counts(stag, ctx, inner):
     assert abs(st[0]["reliable_updates"] - est["updates"]) <= 2 + (0 if inner == "f32" else 4)
 
 
+def test_fig2_restart_variant_matches_refinement_oracle(stag, ctx):
+    """The Fig.2 variant (the direction restarts at every update, the inner
+    cycle ends at a delta reduction from its start) against the oracle's
+    iterative refinement: same true residual bar, iteration and outer-step
+    counts close to the oracle's; and it needs more iterations than the
+    Eq.6 carry-over on the same system (the point of Sec.3.2)."""
+    L, m, tol = (6, 6, 6, 6), 0.03, 1e-8
+    U = links(L, "haar", 81)
+    b = synth.gaussian_rhs(L, 1, 82)
+    rc, st, x = solve(stag, ctx, L, U, b, [m], tol, inner="f32", mixed_variant="restart")
+    log("restart", st)
+    assert rc == 0 and true_res(U, L, [m], b, x)[0] <= tol
+    _, est = ostag.refinement_cg(U, L, m, b[0], tol, prec="f32", eps_in=0.1)
+    log("oracle refinement", est)
+    assert abs(st[0]["iters"] - est["iters"]) <= 0.05 * est["iters"] + 10
+    assert abs(st[0]["reliable_updates"] - est["outer"]) <= 2
+    rc2, st2, _ = solve(stag, ctx, L, U, b, [m], tol, inner="f32")
+    assert rc2 == 0 and st2[0]["iters"] < st[0]["iters"]
+
+
 def test_batched_equals_single(stag, ctx):
     """Each right-hand side of a block solve equals its own single solve."""
     L, tol = (8, 8, 8, 8), 1e-8
