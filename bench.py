@@ -18,6 +18,7 @@ lattice, and the fp64 CPU oracle timed on this host as a baseline.
 from __future__ import annotations
 
 import argparse
+import functools
 import json
 import math
 import os
@@ -40,13 +41,21 @@ def log(*a):
 KERNEL_NAMES = ("hop_stage1", "hop_stage2", "update")
 
 
-def kernel_bytes(which, inner, vh, costs):
+def kernel_bytes(which, inner, vh, costs, r12):
     """Algorithmic bytes of one launch of a CG-iteration kernel (as the solver runs it)."""
+    r12 = r12 and inner != "f16s"
     if which == 0:
-        return vh * costs.hop_bytes_per_site(inner, 1, lazy=True)
+        return vh * costs.hop_bytes_per_site(inner, 1, lazy=True, r12=r12)
     if which == 1:
-        return vh * costs.hop_bytes_per_site(inner, 2, lazy=True)
+        return vh * costs.hop_bytes_per_site(inner, 2, lazy=True, r12=r12)
     return vh * costs.update_bytes_per_site(inner, inner != "f64")
+
+
+@functools.lru_cache(maxsize=1)
+def c3_inputs(synth):
+    name = "c3_32x32x32x64"
+    log("generating", name, "links ...")
+    return synth.config_links(name), synth.config_rhs(name)
 
 
 def timed_solves(stag, torch, ctx, g, mass, fb, fx, params, k):
@@ -64,42 +73,43 @@ def timed_solves(stag, torch, ctx, g, mass, fb, fx, params, k):
 
 def a_apply_bandwidth(stag, torch, costs, synth, reps=50):
     """GB/s of A = both hop stages on the 32^3 x 64 lattice, per precision,
-    timed with torch events on the stream the library launches on."""
+    full and 12-parameter links, timed with torch events on the stream the
+    library launches on."""
     name = "c3_32x32x32x64"
     cfg = synth.CONFIGS[name]
     L = cfg["L"]
-    log("generating", name, "links ...")
-    U = synth.config_links(name)
+    U, _ = c3_inputs(synth)
     v = synth.gaussian_rhs(L, 1, cfg["rhs_seed"])
     out = {}
-    with stag.Context(0) as ctx:
-        g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"))
-        del U
-        vh = g.vh
-        stream = torch.cuda.current_stream()
-        for prec in ("f64", "f32", "f16s"):
-            cfgt, _ = stag.stag_tune(ctx, g, prec, 1)
-            fi = ctx.field(g, 0, prec, 1).load(v)
-            fo = ctx.field(g, 0, prec, 1)
-            for _ in range(5):
-                stag.stag_apply_A(ctx, g, [cfg["mass"]], fi, fo, stream=stream)
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(reps):
-                stag.stag_apply_A(ctx, g, [cfg["mass"]], fi, fo, stream=stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            byts = vh * costs.a_bytes_per_site(prec)
-            gbs = byts / (ms * 1e-3) / 1e9
-            out[prec] = {"us_per_A": round(ms * 1e3, 2), "GB/s": round(gbs, 1),
-                         "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
-                         "GFLOP/s": round(vh * costs.a_flops_per_site() / (ms * 1e-3) / 1e9, 1),
-                         "bytes_per_A": byts, "tune": cfgt}
-            log("A-apply 32^3x64", prec, out[prec])
-            fi.destroy()
-            fo.destroy()
+    for r12 in (False, True):
+        with stag.Context(0) as ctx:
+            g = ctx.gauge(L, U, precisions=("f64", "f32") if r12 else ("f64", "f32", "f16s"), r12=r12)
+            vh = g.vh
+            stream = torch.cuda.current_stream()
+            for prec in (("f64", "f32") if r12 else ("f64", "f32", "f16s")):
+                cfgt, _ = stag.stag_tune(ctx, g, prec, 1)
+                fi = ctx.field(g, 0, prec, 1).load(v)
+                fo = ctx.field(g, 0, prec, 1)
+                for _ in range(5):
+                    stag.stag_apply_A(ctx, g, [cfg["mass"]], fi, fo, stream=stream)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    stag.stag_apply_A(ctx, g, [cfg["mass"]], fi, fo, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                byts = vh * costs.a_bytes_per_site(prec, r12=r12)
+                gbs = byts / (ms * 1e-3) / 1e9
+                key = prec + ("_r12" if r12 else "")
+                out[key] = {"us_per_A": round(ms * 1e3, 2), "GB/s": round(gbs, 1),
+                            "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
+                            "GFLOP/s": round(vh * costs.a_flops_per_site() / (ms * 1e-3) / 1e9, 1),
+                            "bytes_per_A": byts, "tune": cfgt}
+                log("A-apply 32^3x64", key, out[key])
+                fi.destroy()
+                fo.destroy()
     return out
 
 
@@ -109,13 +119,10 @@ def c3_solves(stag, torch, synth, costs):
     name = "c3_32x32x32x64"
     cfg = synth.CONFIGS[name]
     L, m, tol = cfg["L"], cfg["mass"], cfg["tol"]
-    log("generating", name)
-    U = synth.config_links(name)
-    b = synth.config_rhs(name)
-    out = {"lattice": list(L), "mass": m, "tol": tol}
+    U, b = c3_inputs(synth)
+    out = {"lattice": list(L), "mass": m, "tol": tol, "links": "12-parameter f64/f32, full f16s"}
     with stag.Context(0) as ctx:
-        g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"))
-        del U
+        g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"), r12=True)
         fb = ctx.field(g, 0, "f64", 1).load(b)
         fx = ctx.field(g, 0, "f64", 1)
         for inner in ("f16s", "f32", "f64"):
@@ -129,7 +136,7 @@ def c3_solves(stag, torch, synth, costs):
             s0 = st[0]
             out[inner] = {"time_to_tol_s": round(dt, 4), "status": rc, "iters": s0["iters"],
                           "reliable_updates": s0["reliable_updates"], "restarts": s0["restarts"],
-                          "true_rel_res": s0["true_rel_res"],
+                          "true_rel_res": s0["true_rel_res"], "inner_final": s0["inner_final"],
                           "us_per_iteration": round(dt * 1e6 / max(s0["iters"], 1), 2)}
             log("c3", inner, out[inner])
     if out["f64"]["status"] == 0:
@@ -151,7 +158,7 @@ def batched_c4(stag, torch, synth):
     U = synth.config_links(name)
     b = synth.config_rhs(name)
     with stag.Context(0) as ctx:
-        g = ctx.gauge(L, U, precisions=("f64", "f32"))
+        g = ctx.gauge(L, U, precisions=("f64", "f32"), r12=True)
         stag.stag_tune(ctx, g, "f32", n)
         stag.stag_tune(ctx, g, "f32", 1)
         fb = ctx.field(g, 0, "f64", n).load(b)
@@ -196,7 +203,7 @@ def serving(stag, synth, n_requests=40, rate=None, full=False, seed=2011):
     reqs = synth.request_stream(seed, n_requests, rate, sizes, masses, tols, max_nrhs=8)
     lat, nrhs_done = [], 0
     with stag.Context(0) as ctx:
-        gauges = [ctx.gauge(L, U, precisions=("f64", "f32")) for L, U in zip(sizes, links)]
+        gauges = [ctx.gauge(L, U, precisions=("f64", "f32"), r12=True) for L, U in zip(sizes, links)]
         del links
         pending = {}
         t0 = time.perf_counter()
@@ -270,6 +277,8 @@ def main():
     ap.add_argument("--serve-full", action="store_true",
                     help="serving stream over all four lattice sizes (long)")
     ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--full-links", action="store_true",
+                    help="store the gauge copies in full (18 reals per link) instead of 12 parameters")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -291,7 +300,8 @@ def main():
     b = synth.config_rhs(WORKLOAD)
     torch.cuda.init()
     ctx = stag.Context(0)
-    g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"))
+    r12 = not args.full_links
+    g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"), r12=r12)
     vh = g.vh
     tunes = {p: stag.stag_tune(ctx, g, p, 1)[0] for p in ("f64", "f32", "f16s")}
     log("tuned", tunes)
@@ -313,14 +323,17 @@ def main():
     us = stag.stag_time_kernels(ctx, g, inner, 1, reps=200)
     kinds = {}
     for k, name in enumerate(KERNEL_NAMES):
-        byts = kernel_bytes(k, inner, vh, costs)
+        byts = kernel_bytes(k, inner, vh, costs, r12)
         kinds[name] = {"avg_us": round(us[k], 3), "bytes_per_launch": byts,
                        "GB/s": round(byts / (us[k] * 1e-6) / 1e9, 1)}
     dom = max(kinds, key=lambda k: kinds[k]["avg_us"])
     d = kinds[dom]
     roofline = {"bound": "hbm", "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(d["GB/s"] / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"{dom} ({inner}, 16^3x32)", "avg_us": d["avg_us"],
+                "kernel": (f"{dom} ({inner}, 16^3x32, {'12-parameter' if r12 and inner != 'f16s' else 'full'}"
+                           f" links, S1={tunes[inner]['S1']} S2={tunes[inner]['S2']} "
+                           f"nt={tunes[inner]['nt']} swizzle={tunes[inner]['swizzle']})"),
+                "avg_us": d["avg_us"],
                 "bytes_per_launch": d["bytes_per_launch"]}
     iters = last["iters"]
     per_iter_us = sec * 1e6 / max(iters, 1)
@@ -344,13 +357,15 @@ def main():
                          f"m={mass}, 1 complex Gaussian RHS (seed {cfg['rhs_seed']}), "
                          f"true residual {tol:g}, {inner}-inner CG + fp64 reliable updates"),
             "lattice": list(L), "mass": mass, "tol": tol, "inner": inner, "nrhs": 1,
+            "links": "12-parameter f64/f32 (third row rebuilt), full f16s" if r12 else "full",
         },
         "roofline": roofline,
         "solve": {"iters": iters, "reliable_updates": last["reliable_updates"],
                   "true_rel_res": last["true_rel_res"], "time_to_1e-8_ms": round(sec * 1e3, 3),
                   "us_per_iteration": round(per_iter_us, 3),
                   "kernel_us_per_iteration": round(sum(us), 3),
-                  "bytes_per_iteration": costs.cg_iteration_bytes_per_site(inner, True) * vh},
+                  "bytes_per_iteration": costs.cg_iteration_bytes_per_site(
+                      inner, True, r12=r12 and inner != "f16s") * vh},
         "kernels": kinds,
         "tune": tunes,
     }

@@ -38,6 +38,7 @@ STAG_ENOTFOUND = -8
 F64, F32, F16S = 0, 1, 2
 PREC = {"f64": F64, "f32": F32, "f16s": F16S}
 MIXED_CARRY, MIXED_RESTART = 0, 1
+GAUGE_R12 = 1 << 4
 MAX_RHS = 16
 
 STATUS_NAME = {
@@ -214,28 +215,29 @@ class Context:
         except Exception:
             pass
 
-    def gauge(self, L, U, precisions=("f64", "f32")) -> "Gauge":
-        return Gauge(self, L, U, precisions)
+    def gauge(self, L, U, precisions=("f64", "f32"), r12=False) -> "Gauge":
+        return Gauge(self, L, U, precisions, r12)
 
     def field(self, gauge, parity=0, prec="f64", nrhs=1) -> "Field":
         return Field(self, gauge, parity, prec, nrhs)
 
 
 class Gauge:
-    """A resident gauge field (stag_gauge_create)."""
+    """A resident gauge field (stag_gauge_create); r12: 12-parameter F64 / F32
+    copies (SU(3) links only)."""
 
-    def __init__(self, ctx: Context, L, U, precisions=("f64", "f32")):
+    def __init__(self, ctx: Context, L, U, precisions=("f64", "f32"), r12=False):
         L = tuple(int(v) for v in L)
         Lx, Ly, Lz, Lt = L
         U = _check_c128(U, (Lt, Lz, Ly, Lx, 4, 3, 3), "links")
-        mask = 0
+        mask = GAUGE_R12 if r12 else 0
         for p in precisions:
             mask |= 1 << PREC[p]
         h = ctypes.c_void_p()
         ptr, dev = _ptr(U)
         Lc = (ctypes.c_int * 4)(*L)
         ctx.check(lib.stag_gauge_create(ctx.h, Lc, ptr, dev, mask, ctypes.byref(h)))
-        self.ctx, self.h, self.L, self.mask = ctx, h, L, mask
+        self.ctx, self.h, self.L, self.mask, self.r12 = ctx, h, L, mask, bool(r12)
         self.vh = Lx * Ly * Lz * Lt // 2
 
     def destroy(self):

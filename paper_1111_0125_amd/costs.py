@@ -11,12 +11,14 @@ Eq.5); the flop convention is the paper's, the byte convention is the
 compulsory one.
 
 Bytes per stored link matrix / colour vector:
-  f64  144 / 48
-  f32   72 / 24
+  f64  144 / 48   (12-parameter storage: 96 per link)
+  f32   72 / 24   (12-parameter storage: 48 per link)
   f16s  36 (+ one 4-byte scale per site shared by its 8 links) / 16
 """
 
 LINK_BYTES = {"f64": 144, "f32": 72, "f16s": 36}
+# 12-parameter storage (two rows per SU(3) link), f64 and f32 copies only
+LINK_BYTES_R12 = {"f64": 96, "f32": 48, "f16s": 36}
 SPINOR_BYTES = {"f64": 48, "f32": 24, "f16s": 16}
 SITE_SCALE_BYTES = {"f64": 0, "f32": 0, "f16s": 4}
 
@@ -25,7 +27,8 @@ FLOPS_PER_SITE_XPAY = 12        # m^2 x - t over 3 complex numbers
 FLOPS_PER_SITE_DOT = 12         # Re<x, h> over 3 complex numbers
 
 
-def hop_bytes_per_site(prec: str, stage: int, nrhs: int = 1, lazy: bool = False) -> int:
+def hop_bytes_per_site(prec: str, stage: int, nrhs: int = 1, lazy: bool = False,
+                       r12: bool = False) -> int:
     """Compulsory bytes per output site of one hop launch.
 
     stage 1 (D_oe, plain output): 8 links + nrhs x (read input + write output)
@@ -34,7 +37,7 @@ def hop_bytes_per_site(prec: str, stage: int, nrhs: int = 1, lazy: bool = False)
     formed in the kernel): stage 1 also reads r; stage 2 also reads r and
     writes the new d.
     """
-    links = 8 * LINK_BYTES[prec] + SITE_SCALE_BYTES[prec]
+    links = 8 * (LINK_BYTES_R12 if r12 else LINK_BYTES)[prec] + SITE_SCALE_BYTES[prec]
     if stage == 1:
         nvec = 3 if lazy else 2
     else:
@@ -42,9 +45,9 @@ def hop_bytes_per_site(prec: str, stage: int, nrhs: int = 1, lazy: bool = False)
     return links + nrhs * nvec * SPINOR_BYTES[prec]
 
 
-def a_bytes_per_site(prec: str, nrhs: int = 1) -> int:
+def a_bytes_per_site(prec: str, nrhs: int = 1, r12: bool = False) -> int:
     """One application of A = both stages, per even site."""
-    return hop_bytes_per_site(prec, 1, nrhs) + hop_bytes_per_site(prec, 2, nrhs)
+    return hop_bytes_per_site(prec, 1, nrhs, r12=r12) + hop_bytes_per_site(prec, 2, nrhs, r12=r12)
 
 
 def a_flops_per_site(nrhs: int = 1) -> int:
@@ -59,9 +62,10 @@ def update_bytes_per_site(prec: str, mixed: bool) -> int:
     return 2 * SPINOR_BYTES["f32"] + 4 * SPINOR_BYTES[prec]
 
 
-def cg_iteration_bytes_per_site(prec: str, mixed: bool, nrhs: int = 1) -> int:
+def cg_iteration_bytes_per_site(prec: str, mixed: bool, nrhs: int = 1, r12: bool = False) -> int:
     """One CG iteration as run (three kernels: lazy stage 1, lazy stage 2, update)."""
-    return (hop_bytes_per_site(prec, 1, nrhs, lazy=True) + hop_bytes_per_site(prec, 2, nrhs, lazy=True)
+    return (hop_bytes_per_site(prec, 1, nrhs, lazy=True, r12=r12)
+            + hop_bytes_per_site(prec, 2, nrhs, lazy=True, r12=r12)
             + nrhs * update_bytes_per_site(prec, mixed))
 
 

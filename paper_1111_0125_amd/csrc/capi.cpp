@@ -118,6 +118,7 @@ hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, con
     a.lazy_r_rs = lazy_r_rs;
     a.gauge = g->G[prec][p_out];
     a.gscale = prec == P16S ? g->gscale[p_out] : nullptr;
+    a.r12 = g->r12 && prec != P16S;
     a.in = in;
     a.in_rs = in_rs;
     a.out = out;
@@ -265,6 +266,8 @@ int stag_gauge_create(stag_ctx* ctx, const int L[4], const double* U, int U_on_d
     }
     if (V / 2 >= (1ull << 31))
         return set_error(ctx, STAG_EINVAL, "stag_gauge_create: lattice too large");
+    const bool r12 = (prec_mask & STAG_GAUGE_R12) != 0;
+    prec_mask &= ~STAG_GAUGE_R12;
     if (prec_mask <= 0 || prec_mask > 7)
         return set_error(ctx, STAG_EINVAL, "stag_gauge_create: bad precision mask %d", prec_mask);
     DeviceGuard dg(ctx->device);
@@ -273,6 +276,7 @@ int stag_gauge_create(stag_ctx* ctx, const int L[4], const double* U, int U_on_d
     for (int i = 0; i < 4; ++i) g->L[i] = L[i];
     g->g = make_geom(L);
     g->mask = prec_mask;
+    g->r12 = r12;
     const size_t Vh = g->g.Vh;
     const size_t ubytes = (size_t)V * 4 * 9 * 16;
     void* Ud = nullptr;
@@ -280,7 +284,7 @@ int stag_gauge_create(stag_ctx* ctx, const int L[4], const double* U, int U_on_d
     auto cleanup = [&]() {
         for (int p = 0; p < 3; ++p)
             for (int q = 0; q < 2; ++q)
-                if (g->G[p][q]) dev_free(ctx, g->G[p][q], gauge_parity_bytes(p, Vh) - (p == P16S ? Vh * 4 : 0));
+                if (g->G[p][q]) dev_free(ctx, g->G[p][q], link_bytes(p, Vh, r12));
         for (int q = 0; q < 2; ++q)
             if (g->gscale[q]) dev_free(ctx, g->gscale[q], Vh * 4);
         delete g;
@@ -302,14 +306,37 @@ int stag_gauge_create(stag_ctx* ctx, const int L[4], const double* U, int U_on_d
         }
     }
     const void* Usrc = U_on_device ? (const void*)U : Ud;
+    if (r12) {
+        // the third row is rebuilt from the first two: only valid for SU(3)
+        int* bad = nullptr;
+        int hbad = 0;
+        hipError_t e = hipMalloc((void**)&bad, sizeof(int));
+        if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int), ctx->stream);
+        if (e == hipSuccess) e = launch_su3_check(Usrc, (uint64_t)V * 4, 1e-10, bad, ctx->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (bad) (void)hipFree(bad);
+        if (e != hipSuccess || hbad) {
+            (void)hipGetLastError();
+            if (Ud) (void)hipFree(Ud);
+            cleanup();
+            return e != hipSuccess
+                       ? set_error(ctx, STAG_EDEVICE, "stag_gauge_create: SU(3) check: %s",
+                                   hipGetErrorString(e))
+                       : set_error(ctx, STAG_EINVAL,
+                                   "stag_gauge_create: STAG_GAUGE_R12 needs SU(3) links "
+                                   "(|U U^+ - 1| or |det U - 1| above 1e-10)");
+        }
+    }
     for (int p = 0; p < 3 && rc == STAG_OK; ++p) {
         if (!(prec_mask & (1 << p))) continue;
-        const size_t gb = gauge_parity_bytes(p, Vh) - (p == P16S ? Vh * 4 : 0);
+        const size_t gb = link_bytes(p, Vh, r12);
         for (int q = 0; q < 2 && rc == STAG_OK; ++q) {
             rc = dev_alloc(ctx, gb, &g->G[p][q]);
             if (rc == STAG_OK && p == P16S) rc = dev_alloc(ctx, Vh * 4, (void**)&g->gscale[q]);
             if (rc == STAG_OK) {
-                hipError_t e = launch_gauge_pack(p, Usrc, g->G[p][q], g->gscale[q], g->g, q, ctx->stream);
+                hipError_t e =
+                    launch_gauge_pack(p, Usrc, g->G[p][q], g->gscale[q], g->g, q, r12, ctx->stream);
                 if (e != hipSuccess) {
                     (void)hipGetLastError();
                     rc = set_error(ctx, STAG_EDEVICE, "gauge pack: %s", hipGetErrorString(e));
@@ -364,7 +391,7 @@ int stag_gauge_destroy(stag_gauge* g) {
     const size_t Vh = g->g.Vh;
     for (int p = 0; p < 3; ++p)
         for (int q = 0; q < 2; ++q)
-            if (g->G[p][q]) dev_free(ctx, g->G[p][q], gauge_parity_bytes(p, Vh) - (p == P16S ? Vh * 4 : 0));
+            if (g->G[p][q]) dev_free(ctx, g->G[p][q], link_bytes(p, Vh, g->r12));
     for (int q = 0; q < 2; ++q)
         if (g->gscale[q]) dev_free(ctx, g->gscale[q], Vh * 4);
     delete g;

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
         if (valid && act) {
             const int mu = j * (4 / S);
             neighbours(a.g, s, x, y, z, t, mu, nf0, nb0);
-            load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, lr0, li0);
+            load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, a.r12, eta_sign(mu, x, y, z), lr0, li0);
             load_raw<P>(a, (const char*)a.in, 0, nf0, lazy_nb, wf0);
             load_raw<P>(a, (const char*)a.in, 0, nb0, lazy_nb, wb0);
         }
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                 }
             } else {
                 neighbours(a.g, s, x, y, z, t, mu, nf, nb);
-                load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, lr, li);
+                load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, a.r12, eta_sign(mu, x, y, z), lr, li);
             }
 #pragma unroll
             for (int r = 0; r < N; ++r) {

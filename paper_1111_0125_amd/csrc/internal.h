@@ -77,6 +77,7 @@ struct stag_gauge {
     int mask = 0;
     void* G[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
     float* gscale[2] = {nullptr, nullptr};  // P16S
+    bool r12 = false;                       // P64 / P32 copies in 12-parameter form
     size_t bytes = 0;
 };
 

@@ -154,12 +154,75 @@ __device__ __forceinline__ void round_site(typename Real<P>::T (&re)[3], typenam
 
 // ------------------------------------------------------------------ gauge access
 
+// Third row of an SU(3) matrix whose first two rows are entries o..o+5 of
+// (lr, li): the conjugated cross product of rows 0 and 1, written to o+6..o+8.
+template <typename T>
+__device__ __forceinline__ void third_row(T (&lr)[18], T (&li)[18], int o) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+        // a_k1 b_k2 - a_k2 b_k1
+        const T pr = fma(lr[o + k1], lr[o + 3 + k2], -(li[o + k1] * li[o + 3 + k2]));
+        const T pi = fma(lr[o + k1], li[o + 3 + k2], li[o + k1] * lr[o + 3 + k2]);
+        const T qr = fma(lr[o + k2], lr[o + 3 + k1], -(li[o + k2] * li[o + 3 + k1]));
+        const T qi = fma(lr[o + k2], li[o + 3 + k1], li[o + k2] * lr[o + 3 + k1]);
+        lr[o + 6 + k] = pr - qr;
+        li[o + 6 + k] = qi - pi;
+    }
+}
+
 // Load the 18 complex entries of hop pair mu (forward link then backward
-// link, each row-major) of output site s.
+// link, each row-major) of output site s. With r12 the links are stored as
+// two rows without phases: the third rows are rebuilt and the forward link
+// is multiplied by eta, the backward one by -eta (eta = eta_mu(x) = +-1).
 template <int P, bool NT>
 __device__ __forceinline__ void load_pair(const void* G, const float* gscale, uint32_t Vh,
-                                          uint32_t s, int mu, typename Real<P>::T (&lr)[18],
+                                          uint32_t s, int mu, int r12, int eta,
+                                          typename Real<P>::T (&lr)[18],
                                           typename Real<P>::T (&li)[18]) {
+    using T = typename Real<P>::T;
+    if constexpr (P != P16S) {
+        if (r12) {
+            if constexpr (P == P64) {
+                const d2v* g = (const d2v*)G + (size_t)(12 * mu) * Vh + s;
+#pragma unroll
+                for (int e = 0; e < 6; ++e) {
+                    const d2v f = ldg<NT>(g + (size_t)e * Vh);
+                    const d2v b = ldg<NT>(g + (size_t)(6 + e) * Vh);
+                    lr[e] = f.x;
+                    li[e] = f.y;
+                    lr[9 + e] = b.x;
+                    li[9 + e] = b.y;
+                }
+            } else {
+                const f4v* g = (const f4v*)G + (size_t)(6 * mu) * Vh + s;
+#pragma unroll
+                for (int w = 0; w < 3; ++w) {
+                    const f4v f = ldg<NT>(g + (size_t)w * Vh);
+                    const f4v b = ldg<NT>(g + (size_t)(3 + w) * Vh);
+                    lr[2 * w] = f.x;
+                    li[2 * w] = f.y;
+                    lr[2 * w + 1] = f.z;
+                    li[2 * w + 1] = f.w;
+                    lr[9 + 2 * w] = b.x;
+                    li[9 + 2 * w] = b.y;
+                    lr[9 + 2 * w + 1] = b.z;
+                    li[9 + 2 * w + 1] = b.w;
+                }
+            }
+            third_row(lr, li, 0);
+            third_row(lr, li, 9);
+            const T sf = (T)eta, sb = -(T)eta;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) {
+                lr[e] *= sf;
+                li[e] *= sf;
+                lr[9 + e] *= sb;
+                li[9 + e] *= sb;
+            }
+            return;
+        }
+    }
     if constexpr (P == P64) {
         const d2v* g = (const d2v*)G + (size_t)(18 * mu) * Vh + s;
 #pragma unroll
@@ -190,6 +253,12 @@ __device__ __forceinline__ void load_pair(const void* G, const float* gscale, ui
             li[2 * w + 1] = h2f_hi(v.y) * sc;
         }
     }
+}
+
+// eta_mu(x) = (-1)^(x_0 + ... + x_{mu-1}) of the site with coordinates x, y, z.
+__device__ __forceinline__ int eta_sign(int mu, int x, int y, int z) {
+    const int s = (mu > 0 ? x : 0) + (mu > 1 ? y : 0) + (mu > 2 ? z : 0);
+    return (s & 1) ? -1 : 1;
 }
 
 // acc += L v for the 3x3 complex matrix starting at entry `o` of (lr, li).

@@ -48,6 +48,7 @@ struct HopArgs {
     unsigned run_mask;     // process RHS r iff st[r].flags & run_mask
     int p_out;
     int swizzle;
+    int r12;               // links in 12-parameter form (P64 / P32)
     Geom g;
     Reduce red;            // XPAY_DOT / RESID: where the chunk partials go
     // Reduction finalised at kernel start (fin.partials null: none): every
@@ -108,8 +109,12 @@ hipError_t launch_vec(int prec, int N, int op, const VecArgs& a, const Issue& is
 hipError_t launch_finalize(int N, const Reduce& R, unsigned run_mask, const Issue& is);
 
 // Layout conversion kernels (canonical complex128 <-> internal storage).
+// r12: 12-parameter layout (P64 / P32 only; P16S is always full).
 hipError_t launch_gauge_pack(int prec, const void* U_dev, void* G, float* gscale, const Geom& g,
-                             int p_out, hipStream_t stream);
+                             int p_out, bool r12, hipStream_t stream);
+// Sets *bad_dev = 1 when a link is not SU(3) within tol (bad_dev zeroed by the caller).
+hipError_t launch_su3_check(const void* U_dev, uint64_t nlinks, double tol, int* bad_dev,
+                            hipStream_t stream);
 hipError_t launch_import(int prec, const void* src_dev, void* dst, size_t dst_rs, uint32_t Vh,
                          int nrhs, hipStream_t stream);
 hipError_t launch_export(int prec, const void* src, size_t src_rs, void* dst_dev, uint32_t Vh,

@@ -96,8 +96,131 @@ __global__ __launch_bounds__(kBlock) void k_gauge_pack(const d2v* __restrict__ U
     }
 }
 
+// 12-parameter packing (P64 / P32): the first two rows of U_mu(x) and of
+// U_mu(x - mu)^dagger per hop pair, without phases (layout in common.h).
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_gauge_pack12(const d2v* __restrict__ U, void* G, Geom g,
+                                                         int p_out) {
+    const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= g.Vh) return;
+    int c[4];
+    site_coords(g, s, p_out, c[0], c[1], c[2], c[3]);
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];
+    auto lex_of = [&](const int* q) -> size_t {
+        return (size_t)q[0] + (size_t)Lx * ((size_t)q[1] + (size_t)Ly * ((size_t)q[2] + (size_t)Lz * q[3]));
+    };
+    double lr[48], li[48];
+    const size_t lex = lex_of(c);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        int b[4] = {c[0], c[1], c[2], c[3]};
+        b[mu] = (b[mu] == 0) ? g.L[mu] - 1 : b[mu] - 1;
+        const d2v* uf = U + (lex * 4 + mu) * 9;
+        const d2v* ub = U + (lex_of(b) * 4 + mu) * 9;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const d2v f = uf[i * 3 + k];
+                lr[12 * mu + 3 * i + k] = f.x;
+                li[12 * mu + 3 * i + k] = f.y;
+                // U^dagger: entry (i, k) = conj(U[k][i])
+                const d2v v = ub[k * 3 + i];
+                lr[12 * mu + 6 + 3 * i + k] = v.x;
+                li[12 * mu + 6 + 3 * i + k] = -v.y;
+            }
+    }
+    const size_t Vh = g.Vh;
+    if constexpr (P == P64) {
+        d2v* o = (d2v*)G;
+#pragma unroll
+        for (int e = 0; e < 48; ++e) {
+            d2v v;
+            v.x = lr[e];
+            v.y = li[e];
+            o[(size_t)e * Vh + s] = v;
+        }
+    } else {
+        f4v* o = (f4v*)G;
+#pragma unroll
+        for (int w = 0; w < 24; ++w) {
+            f4v v;
+            v.x = (float)lr[2 * w];
+            v.y = (float)li[2 * w];
+            v.z = (float)lr[2 * w + 1];
+            v.w = (float)li[2 * w + 1];
+            o[(size_t)w * Vh + s] = v;
+        }
+    }
+}
+
+// Flag (bad = 1) every link with max |U U^+ - 1| or |det U - 1| above tol.
+// All writers store the same value, so the race is benign.
+__global__ __launch_bounds__(kBlock) void k_su3_check(const d2v* __restrict__ U, uint64_t nlinks,
+                                                      double tol, int* bad) {
+    const uint64_t l = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (l >= nlinks) return;
+    double ur[9], ui[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        const d2v v = U[l * 9 + e];
+        ur[e] = v.x;
+        ui[e] = v.y;
+    }
+    double err = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            // (U U^+)_ik = sum_j U_ij conj(U_kj)
+            double re = 0.0, im = 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                re += ur[3 * i + j] * ur[3 * k + j] + ui[3 * i + j] * ui[3 * k + j];
+                im += ui[3 * i + j] * ur[3 * k + j] - ur[3 * i + j] * ui[3 * k + j];
+            }
+            if (i == k) re -= 1.0;
+            err = fmax(err, fmax(fabs(re), fabs(im)));
+        }
+    // det U = row0 . (row1 x row2)
+    auto cm = [](double ar, double ai, double br, double bi, double& cr, double& ci) {
+        cr = ar * br - ai * bi;
+        ci = ar * bi + ai * br;
+    };
+    double dr = 0.0, di = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+        double pr, pi, qr, qi;
+        cm(ur[3 + k1], ui[3 + k1], ur[6 + k2], ui[6 + k2], pr, pi);
+        cm(ur[3 + k2], ui[3 + k2], ur[6 + k1], ui[6 + k1], qr, qi);
+        double tr, ti;
+        cm(ur[k], ui[k], pr - qr, pi - qi, tr, ti);
+        dr += tr;
+        di += ti;
+    }
+    err = fmax(err, fmax(fabs(dr - 1.0), fabs(di)));
+    if (!(err <= tol)) *bad = 1;
+}
+
+hipError_t launch_su3_check(const void* U_dev, uint64_t nlinks, double tol, int* bad_dev,
+                            hipStream_t st) {
+    const uint64_t nb = (nlinks + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_su3_check, dim3((uint32_t)nb), dim3(kBlock), 0, st, (const d2v*)U_dev, nlinks,
+                       tol, bad_dev);
+    return hipGetLastError();
+}
+
 hipError_t launch_gauge_pack(int prec, const void* U_dev, void* G, float* gscale, const Geom& g,
-                             int p_out, hipStream_t st) {
+                             int p_out, bool r12, hipStream_t st) {
+    if (r12 && prec != P16S) {
+        const dim3 grid((g.Vh + kBlock - 1) / kBlock), block(kBlock);
+        const d2v* U = (const d2v*)U_dev;
+        if (prec == P64)
+            hipLaunchKernelGGL((k_gauge_pack12<P64>), grid, block, 0, st, U, G, g, p_out);
+        else
+            hipLaunchKernelGGL((k_gauge_pack12<P32>), grid, block, 0, st, U, G, g, p_out);
+        return hipGetLastError();
+    }
     const dim3 grid((g.Vh + kBlock - 1) / kBlock), block(kBlock);
     const d2v* U = (const d2v*)U_dev;
     switch (prec) {

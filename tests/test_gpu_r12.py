@@ -1,0 +1,95 @@
+"""12-parameter link storage (two rows per SU(3) link, the third rebuilt in
+the kernels, the phases applied from the coordinates) against the CPU
+oracle's fp64 operator, which never compresses anything."""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import stag as ostag
+from tests.gpu_common import links, log, oracle_apply_A, oracle_dslash, rel_max
+
+pytestmark = pytest.mark.gpu
+
+LATTICES = [(2, 2, 2, 2), (4, 4, 4, 4), (4, 6, 4, 8), (2, 4, 6, 8), (16, 16, 16, 8)]
+TOL = {"f64": 1e-12, "f32": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def stag():
+    import paper_1111_0125_amd as s
+    return s
+
+
+@pytest.fixture(scope="module")
+def ctx(stag):
+    c = stag.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("L", LATTICES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_r12_dslash_and_A(stag, ctx, L, prec):
+    U = links(L, "haar", 13)
+    g = ctx.gauge(L, U, precisions=(prec,), r12=True)
+    for p_in in (0, 1):
+        v = synth.gaussian_rhs(L, 2, 14 + p_in)
+        fi = ctx.field(g, p_in, prec, 2).load(v)
+        fo = ctx.field(g, 1 - p_in, prec, 2)
+        stag.stag_dslash(ctx, g, fi, fo)
+        err = rel_max(fo.store(), oracle_dslash(U, v, L, p_in))
+        log("dslash r12", L, prec, p_in, err)
+        assert err <= TOL[prec]
+    v = synth.gaussian_rhs(L, 3, 16)
+    masses = [0.1, 0.05, 0.3]
+    fi = ctx.field(g, 0, prec, 3).load(v)
+    fo = ctx.field(g, 0, prec, 3)
+    stag.stag_apply_A(ctx, g, masses, fi, fo)
+    err = rel_max(fo.store(), oracle_apply_A(U, v, L, masses))
+    log("A r12", L, prec, err)
+    assert err <= TOL[prec]
+    g.destroy()
+
+
+def test_r12_rejects_non_su3(stag, ctx):
+    L = (4, 4, 4, 4)
+    U = links(L, "haar", 17).copy()
+    U[1, 2, 3, 0, 2] *= np.exp(0.3j)  # unitary, det != 1
+    with pytest.raises(stag.StagError):
+        ctx.gauge(L, U, precisions=("f64",), r12=True)
+    U = links(L, "haar", 17).copy()
+    U[0, 0, 0, 1, 3, 0, 0] += 1e-6  # not unitary
+    with pytest.raises(stag.StagError):
+        ctx.gauge(L, U, precisions=("f32",), r12=True)
+    # the same links are fine in full storage
+    ctx.gauge(L, U, precisions=("f32",)).destroy()
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32", "f16s"])
+def test_r12_solves_and_block_equals_single(stag, ctx, inner):
+    """Solves on 12-parameter links reach the fp64 true residual (measured with
+    the oracle's full A); a block of right-hand sides gives each one's bits."""
+    L, tol = (8, 8, 8, 8), 1e-9
+    U = links(L, "exp", 18, 0.3)
+    b = synth.gaussian_rhs(L, 3, 19)
+    masses = [0.05, 0.1, 0.2]
+    g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"), r12=True)
+    fb = ctx.field(g, 0, "f64", 3).load(b)
+    fx = ctx.field(g, 0, "f64", 3)
+    rc, st = stag.stag_cg_solve(ctx, g, masses, fb, fx, stag.cg_params(tol=tol, inner=inner))
+    log("r12 solve", inner, rc, st[0])
+    assert rc == 0
+    x = fx.store()
+    Ax = oracle_apply_A(U, x, L, masses)
+    for r in range(3):
+        res = math.sqrt(ostag.norm2(b[r] - Ax[r]) / ostag.norm2(b[r]))
+        assert res <= tol
+    f1 = ctx.field(g, 0, "f64", 1).load(b[1:2])
+    x1 = ctx.field(g, 0, "f64", 1)
+    rc1, st1 = stag.stag_cg_solve(ctx, g, masses[1:2], f1, x1, stag.cg_params(tol=tol, inner=inner))
+    assert rc1 == 0 and st1[0]["iters"] == st[1]["iters"]
+    assert np.array_equal(x1.store()[0], x[1])
+    g.destroy()
