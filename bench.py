@@ -51,6 +51,47 @@ def kernel_bytes(which, inner, vh, costs, r12):
     return vh * costs.update_bytes_per_site(inner, inner != "f64")
 
 
+COPY_FLOATS = 64 << 20  # calibration copy: 256 MiB each way
+TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "c2_16x16x16x32_iteration_kernels_hbm_traffic.md")
+
+
+def csrc_digest():
+    """sha256 over the kernel and library sources (names and contents)."""
+    import hashlib
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1111_0125_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def kernel_names(tune, inner):
+    """Symbol names of the three iteration kernels for a tuned shape (one RHS)."""
+    p = {"f64": 0, "f32": 1, "f16s": 2}[inner]
+    nt = "true" if tune["nt"] else "false"
+    op = 2 if inner == "f64" else 3
+    return [f"void stag::k_hop<{p}, {tune['S1']}, 1, 0, {nt}>(stag::HopArgs)",
+            f"void stag::k_hop<{p}, {tune['S2']}, 1, 2, {nt}>(stag::HopArgs)",
+            f"void stag::k_vec<{p}, 1, {op}>(stag::VecArgs)"]
+
+
+def measured_traffic(kernel, links):
+    """HBM bytes per launch of `kernel` from the committed counter summary, when
+    it was taken on these sources with these links; else None."""
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            txt = f.read()
+        blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("csrc_sha256") != csrc_digest() or blob.get("links") != links:
+        return None
+    k = blob.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
 @functools.lru_cache(maxsize=1)
 def c3_inputs(synth):
     name = "c3_32x32x32x64"
@@ -277,6 +318,9 @@ def main():
     ap.add_argument("--serve-full", action="store_true",
                     help="serving stream over all four lattice sizes (long)")
     ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only tune and launch the iteration kernels (as timed for the roofline), "
+                         "then a 256 MiB copy kernel: the program that hardware-counter runs profile")
     ap.add_argument("--full-links", action="store_true",
                     help="store the gauge copies in full (18 reals per link) instead of 12 parameters")
     args = ap.parse_args()
@@ -305,9 +349,22 @@ def main():
     vh = g.vh
     tunes = {p: stag.stag_tune(ctx, g, p, 1)[0] for p in ("f64", "f32", "f16s")}
     log("tuned", tunes)
+    inner = args.inner
+    if args.kernels_only:
+        us = stag.stag_time_kernels(ctx, g, inner, 1, reps=20)
+        n = COPY_FLOATS
+        xs = torch.ones(n, device="cuda")
+        ys = torch.empty_like(xs)
+        for _ in range(3):
+            torch.mul(xs, 2.0, out=ys)  # reads and writes n * 4 bytes
+        torch.cuda.synchronize()
+        print(json.dumps({"kernels_only": True, "tune": tunes[inner], "us": us,
+                          "kernel_names": kernel_names(tunes[inner], inner),
+                          "copy_bytes_read": n * 4, "copy_bytes_written": n * 4,
+                          "csrc_sha256": csrc_digest()}), flush=True)
+        return
     fb = ctx.field(g, 0, "f64", 1).load(b)
     fx = ctx.field(g, 0, "f64", 1)
-    inner = args.inner
     params = stag.cg_params(tol=tol, inner=inner)
 
     for _ in range(args.warmup):
@@ -328,8 +385,11 @@ def main():
                        "GB/s": round(byts / (us[k] * 1e-6) / 1e9, 1)}
     dom = max(kinds, key=lambda k: kinds[k]["avg_us"])
     d = kinds[dom]
+    dom_name = kernel_names(tunes[inner], inner)[KERNEL_NAMES.index(dom)]
+    traffic = measured_traffic(dom_name, "r12" if r12 else "full")
     roofline = {"bound": "hbm", "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(d["GB/s"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(d["GB/s"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel_symbol": dom_name,
                 "kernel": (f"{dom} ({inner}, 16^3x32, {'12-parameter' if r12 and inner != 'f16s' else 'full'}"
                            f" links, S1={tunes[inner]['S1']} S2={tunes[inner]['S2']} "
                            f"nt={tunes[inner]['nt']} swizzle={tunes[inner]['swizzle']})"),

@@ -160,8 +160,8 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, stag_tune_
         return time_iteration_kernels(e, tu, nrhs, reps, us);
     };
     // The default shape is measured first and kept unless another is at
-    // least 2 % faster, so repeated tunings settle on the same shape.
-    constexpr double kGain = 0.98;
+    // least 5 % faster, so repeated tunings settle on the same shape.
+    constexpr double kGain = 0.95;
     HopTune bestT = get_tune(ctx, prec, N, Vh);
     bestT.S1 = bestT.S2 = 1;
     bestT.nt = 1;
