@@ -230,24 +230,34 @@ def batched_c4(stag, torch, synth):
 
 def serving(stag, synth, n_requests=40, rate=None, full=False, seed=2011):
     """A Poisson stream of solve requests over resident gauge fields,
-    continuously batched per gauge; solves/s and submit-to-finish latency."""
+    continuously batched per gauge; solves/s and submit-to-finish latency.
+    Default: a light stream over 8^4 and 16^3x32 with smooth links. full:
+    the four resident Haar fields 8^4, 16^3x32, 24^3x48, 32^3x64 (gauge
+    seeds 15-18), masses {0.005, 0.01, 0.05, 0.1} (long: 32^3x64 at
+    m = 0.005 takes seconds per solve)."""
     import numpy as np
-    sizes = [(8, 8, 8, 8), (16, 16, 16, 32)]
     if full:
-        sizes += [(24, 24, 24, 48), (32, 32, 32, 64)]
-    masses = [0.01, 0.02, 0.05, 0.1]
+        sizes = [(8, 8, 8, 8), (16, 16, 16, 32), (24, 24, 24, 48), (32, 32, 32, 64)]
+        masses = [0.005, 0.01, 0.05, 0.1]
+        log("serving: generating", sizes)
+        links = [synth.haar_links(L, 15 + i) for i, L in enumerate(sizes)]
+    else:
+        sizes = [(8, 8, 8, 8), (16, 16, 16, 32)]
+        masses = [0.01, 0.02, 0.05, 0.1]
+        log("serving: generating", sizes)
+        # the same smooth-link recipe as the 16^3 x 32 workload (exp(i 0.3 H))
+        links = [synth.exp_ih_links(L, 15 + i, 0.3) for i, L in enumerate(sizes)]
     tols = [1e-6, 1e-8, 1e-10]
-    log("serving: generating", sizes)
-    # the same smooth-link recipe as the 16^3 x 32 workload (exp(i 0.3 H))
-    links = [synth.exp_ih_links(L, 15 + i, 0.3) for i, L in enumerate(sizes)]
-    rate = rate or (50.0 if not full else 5.0)
+    rate = rate or (50.0 if not full else 2.0)
     reqs = synth.request_stream(seed, n_requests, rate, sizes, masses, tols, max_nrhs=8)
     lat, nrhs_done = [], 0
+    lat_by = {i: [] for i in range(len(sizes))}
     with stag.Context(0) as ctx:
         gauges = [ctx.gauge(L, U, precisions=("f64", "f32"), r12=True) for L, U in zip(sizes, links)]
         del links
         pending = {}
         t0 = time.perf_counter()
+        t_log = t0
         i = 0
         while i < len(reqs) or pending:
             now = time.perf_counter() - t0
@@ -256,18 +266,22 @@ def serving(stag, synth, n_requests=40, rate=None, full=False, seed=2011):
                 L = sizes[q["lattice"]]
                 b = synth.gaussian_rhs(L, q["nrhs"], q["rhs_seed"])
                 tid = stag.stag_solver_submit(ctx, gauges[q["lattice"]], q["mass"], b, q["tol"], "f32")
-                pending[tid] = (q["nrhs"], gauges[q["lattice"]].vh)
+                pending[tid] = (q["nrhs"], gauges[q["lattice"]].vh, q["lattice"])
                 i += 1
             for tid in list(pending):
-                nr, vh = pending[tid]
+                nr, vh, li = pending[tid]
                 r = stag.stag_solver_poll(ctx, tid, nr, vh, want_x=False)
                 if r is not None:
                     rc, _, st, latency = r
                     if rc != 0:
                         raise RuntimeError(f"serving request failed: {rc} {st}")
                     lat.append(latency)
+                    lat_by[li].append(latency)
                     nrhs_done += nr
                     del pending[tid]
+            if time.perf_counter() - t_log > 15.0:
+                t_log = time.perf_counter()
+                log(f"serving: {len(lat)} of {len(reqs)} requests done, {len(pending)} pending")
             time.sleep(0.0005)
         wall = time.perf_counter() - t0
     lat = np.array(lat)
@@ -277,6 +291,10 @@ def serving(stag, synth, n_requests=40, rate=None, full=False, seed=2011):
            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
            "arrival_rate_per_s": rate,
            "lattices": ["x".join(map(str, L)) for L in sizes],
+           "links": "Haar" if full else "exp(i 0.3 H)",
+           "p50_p99_by_lattice_s": {"x".join(map(str, sizes[i])): [
+               round(float(np.percentile(v, 50)), 4), round(float(np.percentile(v, 99)), 4)]
+               for i, v in lat_by.items() if v},
            "masses": masses, "tols": tols, "inner": "f32"}
     log("serving", out)
     return out

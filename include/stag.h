@@ -174,7 +174,8 @@ typedef struct stag_cg_params {
     int inner_prec;    /* STAG_F64: plain CG (Fig.1); STAG_F32 / STAG_F16S: mixed (Sec.3.2) */
     double delta;      /* mixed: update when |r| < delta * max|r| since the last update; <= 0: 0.1 */
     int stall_iters;   /* mixed: forced update + direction restart after this many
-                          iterations without a new residual minimum; <= 0: 100 */
+                          iterations without a new residual minimum; <= 0: 100 with
+                          STAG_F16S, never with STAG_F32 (fp32 needs no safeguard) */
     int max_stall;     /* mixed: ESTALL after this many consecutive stall updates
                           without halving the true residual; <= 0: 20 */
     int graph_k;       /* iterations per host poll (replayed as one HIP graph when

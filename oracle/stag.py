@@ -379,7 +379,7 @@ def refinement_cg(U, L, m, b, tol, prec="f32", eps_in=0.1, max_iter=None):
 # Sec.3.2 corrected mixed-precision CG
 # --------------------------------------------------------------------------
 
-def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=100,
+def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
              max_iter=None, max_stall=20, carry_direction=True):
     """Corrected mixed-precision CG of Sec.3.2, emulated on the CPU.
 
@@ -395,14 +395,17 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=100,
       the direction is carried over as d = r + beta d (Eq.6) with
       beta = |r_true|^2 / |r_s,prev|^2;
     * no new residual minimum for ``stall_iters`` iterations (a safeguard the
-      paper does not need with fp32 storage): the same update, but the
-      direction restarts from d = r. ``max_stall`` consecutive stall updates
-      without halving the true residual norm end the solve ("stall").
+      paper does not need with fp32 storage; by default 100 with fp16+scale
+      storage and off with fp32): the same update, but the direction
+      restarts from d = r. ``max_stall`` consecutive stall updates without
+      halving the true residual norm end the solve ("stall").
 
     Convergence is declared only on the fp64 true residual.
     ``carry_direction=False`` restarts d = r at every update (ablation).
     Returns (x, stats).
     """
+    if stall_iters is None:
+        stall_iters = 100 if prec == "f16s" else math.inf
     A64 = lambda v: apply_A(U, v, L, m)
     Alow = LowOperator(U, L, m, prec)
     q = quantiser(prec)

@@ -290,7 +290,7 @@ def stag_apply_A(ctx: Context, gauge: Gauge, mass, fin: Field, fout: Field, stre
     return ctx.check(lib.stag_apply_A(ctx.h, gauge.h, mp, fin.h, fout.h, _stream(stream)))
 
 
-def cg_params(tol=1e-8, inner="f64", max_iter=0, delta=0.1, stall_iters=100, max_stall=20,
+def cg_params(tol=1e-8, inner="f64", max_iter=0, delta=0.1, stall_iters=0, max_stall=20,
               graph_k=0, use_graph=True, use_x0=False, escalate=True,
               mixed_variant="carry") -> CgParams:
     p = CgParams()

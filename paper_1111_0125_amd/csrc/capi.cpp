@@ -609,7 +609,7 @@ void stag_cg_params_default(stag_cg_params* p) {
     p->max_iter = 0;
     p->inner_prec = STAG_F64;
     p->delta = 0.1;
-    p->stall_iters = 100;
+    p->stall_iters = 0;
     p->max_stall = 20;
     p->graph_k = 0;
     p->use_graph = 1;

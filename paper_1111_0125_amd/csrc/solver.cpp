@@ -19,6 +19,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <limits>
 
 #include "internal.h"
 
@@ -442,7 +443,9 @@ int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots) {
         s.tol2 = p.tol * p.tol;
         s.m2 = si.mass * si.mass;
         s.delta = p.delta > 0 ? p.delta : 0.1;
-        s.stall_iters = p.stall_iters > 0 ? p.stall_iters : 100;
+        // the stall safeguard is for fp16 storage; fp32 runs without it
+        s.stall_iters = p.stall_iters > 0 ? p.stall_iters
+                                          : (e->prec == P16S ? 100 : std::numeric_limits<int>::max());
         s.max_stall = p.max_stall > 0 ? p.max_stall : 20;
         s.max_iter = p.max_iter > 0 ? p.max_iter : (int)std::min<uint64_t>(10 * n_unknowns, 1000000);
         s.flags = F_NEW | (si.x0 ? F_X0 : 0u);
