@@ -56,12 +56,15 @@ TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "prof
                                "c2_16x16x16x32_iteration_kernels_hbm_traffic.md")
 
 
+KERNEL_SOURCES = ("common.h", "launch.h", "kern.h", "hop.hip", "blas.hip", "layout.hip")
+
+
 def csrc_digest():
-    """sha256 over the kernel and library sources (names and contents)."""
+    """sha256 over the device-code sources (names and contents) of the kernels."""
     import hashlib
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1111_0125_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(d, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
@@ -86,7 +89,7 @@ def measured_traffic(kernel, links):
         blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
         return None
-    if blob.get("csrc_sha256") != csrc_digest() or blob.get("links") != links:
+    if blob.get("kernel_src_sha256") != csrc_digest() or blob.get("links") != links:
         return None
     k = blob.get("kernels", {}).get(kernel)
     return None if k is None else k.get("hbm_bytes_per_launch")
@@ -379,7 +382,7 @@ def main():
         print(json.dumps({"kernels_only": True, "tune": tunes[inner], "us": us,
                           "kernel_names": kernel_names(tunes[inner], inner),
                           "copy_bytes_read": n * 4, "copy_bytes_written": n * 4,
-                          "csrc_sha256": csrc_digest()}), flush=True)
+                          "kernel_src_sha256": csrc_digest()}), flush=True)
         return
     fb = ctx.field(g, 0, "f64", 1).load(b)
     fx = ctx.field(g, 0, "f64", 1)
