@@ -301,7 +301,8 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* gauge, int prec, int nrhs, stag_t
 #define STAG_K_HOP1_64 2  /* fp64 D_oe of a true-residual recompute */
 #define STAG_K_HOP2_64 3  /* fp64 D_eo + residual + norm of a recompute */
 #define STAG_K_UPDATE 4   /* fused x/y and r update with |r|^2 */
-#define STAG_K_XPAY 5     /* direction update d = r + beta d */
+#define STAG_K_XPAY 5     /* reserved: the direction update d = r + beta d is fused
+                             into the hop stages and has no kernel of its own */
 #define STAG_K_OTHER 6
 int stag_timing_enable(stag_ctx* ctx, int on);
 /* stag_time_kernels: average execution time in microseconds of the three

@@ -169,9 +169,6 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
                 for (int c = 0; c < 3; ++c)
                     acc += (double)u.sr[c] * (double)u.sr[c] + (double)u.si[c] * (double)u.si[c];
                 dv[r] = acc;
-            } else if constexpr (OP == OP_ZERO) {
-                T z[3] = {T(0), T(0), T(0)}, zi[3] = {T(0), T(0), T(0)};
-                store_site<P>(slot(a, 0, r), Vh, s, z, zi);
             }
         }
     }
@@ -192,7 +189,6 @@ template <int P, int N>
 static hipError_t run_vec_n(int op, const VecArgs& a, const Issue& is) {
     switch (op) {
         case OP_START: return issue_vec<P, N, OP_START>(a, is);
-        case OP_ZERO: return issue_vec<P, N, OP_ZERO>(a, is);
         default: break;
     }
     if constexpr (P == P64) {

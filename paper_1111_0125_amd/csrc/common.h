@@ -195,7 +195,6 @@ enum FinKind : int {
     FIN_ALPHA = 1,     // pAp -> alpha (or breakdown)
     FIN_CG = 2,        // |r|^2 -> beta, convergence / cap (plain CG)
     FIN_MIXED = 3,     // |r|^2 -> beta, update / stall triggers (mixed CG)
-    FIN_TRUE = 4,      // rr_true = sum
     FIN_INIT = 5,      // bb = sum; start state of a solve (from x = 0, or pending x0)
     FIN_RU_END = 6,    // rr_true = sum, then the state after a reliable / group-wise
                        // update (mixed CG)

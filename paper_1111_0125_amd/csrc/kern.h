@@ -348,9 +348,6 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
             }
             break;
         }
-        case FIN_TRUE:
-            s.rr_true = sum;
-            break;
         case FIN_INIT: {
             // the slot stays F_NEW (with F_X0 when it starts from x0) until
             // its first direction is set; b = 0 finishes it at once

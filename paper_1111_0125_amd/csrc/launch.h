@@ -64,7 +64,6 @@ enum VecOp : int {
     OP_START = 1,      // d = q(r64); if rs: rs = q(r64); if y: y = 0
     OP_UPD_CG = 2,     // x += a d, r -= a Ad, |r|^2 -> FIN_CG           (fp64)
     OP_UPD_MIXED = 3,  // y += a d, rs = q(rs - a Ad), |rs|^2 -> FIN_MIXED
-    OP_ZERO = 8,       // f0 = 0
 };
 
 struct VecArgs {

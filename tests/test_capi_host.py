@@ -61,3 +61,79 @@ def test_create_without_gpu_fails_cleanly():
     rc = s.lib.stag_create(0, 0, ctypes.byref(h))
     assert rc in (s.STAG_EDEVICE, s.STAG_EINVAL)
     assert s.lib.stag_last_error(None)
+
+
+ABI_PROBE = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "stag.h"
+#define F(T, m) printf("%s.%s %zu %zu\n", #T, #m, offsetof(T, m), sizeof(((T*)0)->m))
+int main(void) {
+    printf("stag_cg_params %zu\n", sizeof(stag_cg_params));
+    printf("stag_cg_stats %zu\n", sizeof(stag_cg_stats));
+    printf("stag_tune_cfg %zu\n", sizeof(stag_tune_cfg));
+    F(stag_cg_params, tol); F(stag_cg_params, max_iter); F(stag_cg_params, inner_prec);
+    F(stag_cg_params, delta); F(stag_cg_params, stall_iters); F(stag_cg_params, max_stall);
+    F(stag_cg_params, graph_k); F(stag_cg_params, use_graph); F(stag_cg_params, use_x0);
+    F(stag_cg_params, escalate); F(stag_cg_params, mixed_variant);
+    F(stag_cg_stats, iters); F(stag_cg_stats, reliable_updates); F(stag_cg_stats, restarts);
+    F(stag_cg_stats, status); F(stag_cg_stats, true_rel_res); F(stag_cg_stats, iter_rel_res);
+    F(stag_cg_stats, seconds); F(stag_cg_stats, inner_final);
+    F(stag_tune_cfg, S1); F(stag_tune_cfg, S2); F(stag_tune_cfg, nt); F(stag_tune_cfg, swizzle);
+    printf("STAG_GAUGE_R12 %d STAG_MIXED_CARRY %d STAG_MIXED_RESTART %d\n", STAG_GAUGE_R12,
+           STAG_MIXED_CARRY, STAG_MIXED_RESTART);
+    return 0;
+}
+"""
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of the C structs have the header's layout (sizes
+    and field offsets, from a C program compiled against stag.h)."""
+    import shutil
+    import subprocess
+
+    import paper_1111_0125_amd as s
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "probe.c"
+    src.write_text(ABI_PROBE)
+    exe = tmp_path / "probe"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    sizes, fields, consts = {}, {}, {}
+    for line in out:
+        parts = line.split()
+        if len(parts) == 2:
+            sizes[parts[0]] = int(parts[1])
+        elif len(parts) == 3:
+            fields[parts[0]] = (int(parts[1]), int(parts[2]))
+        elif line.startswith("STAG_GAUGE_R12"):
+            it = iter(parts)
+            consts = {k: int(v) for k, v in zip(it, it)}
+    mirrors = {"stag_cg_params": s.CgParams, "stag_cg_stats": s.CgStats, "stag_tune_cfg": s.TuneCfg}
+    for cname, py in mirrors.items():
+        assert ctypes.sizeof(py) == sizes[cname], cname
+        names = [f for f, _ in py._fields_]
+        cnames = [k.split(".", 1)[1] for k in fields if k.startswith(cname + ".")]
+        assert names == cnames, (cname, names, cnames)
+        for f, _ in py._fields_:
+            off, size = fields[f"{cname}.{f}"]
+            assert getattr(py, f).offset == off and getattr(py, f).size == size, (cname, f)
+    assert consts == {"STAG_GAUGE_R12": s.GAUGE_R12, "STAG_MIXED_CARRY": s.MIXED_CARRY,
+                      "STAG_MIXED_RESTART": s.MIXED_RESTART}
+
+
+def test_param_defaults():
+    import paper_1111_0125_amd as s
+    p = s.CgParams()
+    s.lib.stag_cg_params_default(ctypes.byref(p))
+    assert (p.tol, p.max_iter, p.inner_prec, p.delta) == (1e-8, 0, s.F64, 0.1)
+    assert (p.stall_iters, p.max_stall, p.graph_k, p.use_graph) == (0, 20, 0, 1)
+    assert (p.use_x0, p.escalate, p.mixed_variant) == (0, 1, s.MIXED_CARRY)
+    q = s.cg_params()
+    assert (q.stall_iters, q.use_x0, q.escalate, q.mixed_variant) == (0, 0, 1, s.MIXED_CARRY)
+    r = s.cg_params(inner="f16s", use_x0=True, mixed_variant="restart", escalate=False)
+    assert (r.inner_prec, r.use_x0, r.mixed_variant, r.escalate) == (s.F16S, 1, s.MIXED_RESTART, 0)
