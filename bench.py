@@ -471,6 +471,19 @@ def main():
                                           "updates": strs["reliable_updates"],
                                           "true_rel_res": strs["true_rel_res"],
                                           "iters_vs_eq6_carry": round(strs["iters"] / max(iters, 1), 3)}
+        # the two update methods of Sec.3.2 alone (capped at 4x the iterations
+        # of the scheme that applies both)
+        abl = {}
+        for var in ("reliable", "groupwise"):
+            pv = stag.cg_params(tol=tol, inner=inner, mixed_variant=var, max_iter=4 * iters)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, stv = stag.stag_cg_solve(ctx, g, [mass], fb, fx, pv)
+            torch.cuda.synchronize()
+            abl[var] = {"status": rc, "iters": stv[0]["iters"], "updates": stv[0]["reliable_updates"],
+                        "true_rel_res": stv[0]["true_rel_res"],
+                        "ms": round((time.perf_counter() - t0) * 1e3, 3)}
+        result["update_ablations"] = abl
         p16 = stag.cg_params(tol=tol, inner="f16s")
         stag.stag_cg_solve(ctx, g, [mass], fb, fx, p16)
         s16, st16 = timed_solves(stag, torch, ctx, g, mass, fb, fx, p16, 2)

@@ -192,11 +192,19 @@ typedef struct stag_cg_params {
                           ends when |r| < delta max|r| since the update.
                           STAG_MIXED_RESTART: restart it, d = r, every update (the plain
                           iterative refinement of Fig.2); the cycle ends when
-                          |r| < delta |r at the cycle start|. */
+                          |r| < delta |r at the cycle start|.
+                          Ablations of the two update methods that Sec.3.2 applies
+                          together: STAG_MIXED_RELIABLE recomputes r = b - A (x + y) in
+                          fp64 but never folds y into x (the solution stays in fp32);
+                          STAG_MIXED_GROUPWISE folds y into x but never recomputes r and
+                          checks the true residual once, when the iterated one has met
+                          tol (ENOCONV if the true one misses it). */
 } stag_cg_params;
 
 #define STAG_MIXED_CARRY 0
 #define STAG_MIXED_RESTART 1
+#define STAG_MIXED_RELIABLE 2
+#define STAG_MIXED_GROUPWISE 3
 
 typedef struct stag_cg_stats {
     int iters;             /* CG iterations (inner iterations for mixed) */

@@ -380,7 +380,7 @@ def refinement_cg(U, L, m, b, tol, prec="f32", eps_in=0.1, max_iter=None):
 # --------------------------------------------------------------------------
 
 def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
-             max_iter=None, max_stall=20, carry_direction=True):
+             max_iter=None, max_stall=20, carry_direction=True, update="both"):
     """Corrected mixed-precision CG of Sec.3.2, emulated on the CPU.
 
     Inner iterations run on stored low-precision vectors (fp32 arithmetic,
@@ -402,8 +402,16 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
 
     Convergence is declared only on the fp64 true residual.
     ``carry_direction=False`` restarts d = r at every update (ablation).
+    ``update`` selects the ablations of Sec.3.2's two update methods:
+    "reliable" only recomputes r = b - A (x + y) in fp64 at a trigger and
+    never folds y into x (the solution stays in fp32); "groupwise" only
+    folds y into x and never recomputes r, the direction continuing with
+    the iterated beta; when its iterated residual meets the tolerance the
+    true residual is computed once and decides ("inaccurate" if it misses).
     Returns (x, stats).
     """
+    if update not in ("both", "reliable", "groupwise"):
+        raise ValueError(update)
     if stall_iters is None:
         stall_iters = 100 if prec == "f16s" else math.inf
     A64 = lambda v: apply_A(U, v, L, m)
@@ -453,10 +461,29 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
             since += 1
         upd = rn < delta * rmax or rr <= stop
         stall = (not upd) and since >= stall_iters
-        if upd or stall:
+        if (upd or stall) and update == "groupwise":
+            # fold the correction into x; the iterated residual carries on
             x = x + y.astype(np.complex128)
             y[:] = 0
-            r64 = b - A64(x)
+            stats["updates"] += 1
+            if rr <= stop:
+                true_rr = norm2(b - A64(x))
+                if true_rr > stop:
+                    stats["status"] = "inaccurate"
+                break
+            rmax = rmin = rn
+            since = 0
+            if stall:
+                stats["restarts"] += 1
+                d = rs.copy()
+                continue
+        elif upd or stall:
+            if update == "both":
+                x = x + y.astype(np.complex128)
+                y[:] = 0
+                r64 = b - A64(x)
+            else:  # reliable only: y stays, r from x + y
+                r64 = b - A64(x + y.astype(np.complex128))
             rr = norm2(r64)
             true_rr = rr
             stats["updates"] += 1
@@ -483,7 +510,13 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
                 continue
         beta = rr / rr_old
         d = q((rs + np.float32(beta) * d).astype(np.complex64))
-    if stats["status"] == "ok" and true_rr > stop:
+    if update == "reliable":
+        # the solution is x + y; x is never updated by this variant
+        x = x + y.astype(np.complex128)
+        true_rr = norm2(b - A64(x))
+        if stats["status"] == "ok" and true_rr > stop:
+            stats["status"] = "noconv"
+    elif stats["status"] == "ok" and true_rr > stop:
         # ran out of iterations: fold in the pending correction
         x = x + y.astype(np.complex128)
         true_rr = norm2(b - A64(x))

@@ -37,7 +37,7 @@ STAG_ENOTFOUND = -8
 
 F64, F32, F16S = 0, 1, 2
 PREC = {"f64": F64, "f32": F32, "f16s": F16S}
-MIXED_CARRY, MIXED_RESTART = 0, 1
+MIXED_CARRY, MIXED_RESTART, MIXED_RELIABLE, MIXED_GROUPWISE = 0, 1, 2, 3
 GAUGE_R12 = 1 << 4
 MAX_RHS = 16
 
@@ -305,7 +305,8 @@ def cg_params(tol=1e-8, inner="f64", max_iter=0, delta=0.1, stall_iters=0, max_s
     p.use_graph = 1 if use_graph else 0
     p.use_x0 = 1 if use_x0 else 0
     p.escalate = 1 if escalate else 0
-    p.mixed_variant = {"carry": MIXED_CARRY, "restart": MIXED_RESTART}[mixed_variant]
+    p.mixed_variant = {"carry": MIXED_CARRY, "restart": MIXED_RESTART, "reliable": MIXED_RELIABLE,
+                       "groupwise": MIXED_GROUPWISE}[mixed_variant]
     return p
 
 

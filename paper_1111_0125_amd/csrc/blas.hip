@@ -169,6 +169,19 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
                 for (int c = 0; c < 3; ++c)
                     acc += (double)u.sr[c] * (double)u.sr[c] + (double)u.si[c] * (double)u.si[c];
                 dv[r] = acc;
+            } else if constexpr (OP == OP_FOLD) {
+                // x64 += y, y = 0
+                double xr[3], xi[3];
+                float yr[3], yi[3], z[3] = {0.f, 0.f, 0.f}, zi[3] = {0.f, 0.f, 0.f};
+                load_site<P64>(slot(a, 0, r), Vh, s, xr, xi);
+                load_site<P32>(slot(a, 1, r), Vh, s, yr, yi);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xr[c] = xr[c] + (double)yr[c];
+                    xi[c] = xi[c] + (double)yi[c];
+                }
+                store_site<P64>(slot(a, 0, r), Vh, s, xr, xi);
+                store_site<P32>(slot(a, 1, r), Vh, s, z, zi);
             }
         }
     }
@@ -199,6 +212,7 @@ static hipError_t run_vec_n(int op, const VecArgs& a, const Issue& is) {
         }
     } else {
         if (op == OP_UPD_MIXED) return issue_vec<P, N, OP_UPD_MIXED>(a, is);
+        if (op == OP_FOLD) return issue_vec<P, N, OP_FOLD>(a, is);
     }
     return hipErrorInvalidValue;
 }

@@ -145,6 +145,7 @@ hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, con
         a.aux = ex->aux;
         a.aux_rs = ex->aux_rs;
         a.aux_prec = ex->aux_prec;
+        a.keep_y = ex->keep_y;
     }
     return launch_hop(prec, S, N, epi, t.nt != 0, a, is);
 }
@@ -639,7 +640,7 @@ int stag_cg_solve(stag_ctx* ctx, const stag_gauge* g, const double* mass, const 
         return set_error(ctx, STAG_EINVAL, "stag_cg_solve: tol must be in (0, 1)");
     if (p.inner_prec < 0 || p.inner_prec > 2)
         return set_error(ctx, STAG_EINVAL, "stag_cg_solve: inner precision %d", p.inner_prec);
-    if (p.mixed_variant != STAG_MIXED_CARRY && p.mixed_variant != STAG_MIXED_RESTART)
+    if (p.mixed_variant < STAG_MIXED_CARRY || p.mixed_variant > STAG_MIXED_GROUPWISE)
         return set_error(ctx, STAG_EINVAL, "stag_cg_solve: mixed_variant %d", p.mixed_variant);
     if (!(g->mask & STAG_MASK_F64) || !(g->mask & (1 << p.inner_prec)))
         return set_error(ctx, STAG_EINVAL,

@@ -267,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                                 a.lazy_r ? stv(r).beta : 0.0, xr, xi);
                 if (a.lazy_r) store_site<P>((char*)a.x + (size_t)r * a.x_rs, Vh, s, xr, xi);
                 if constexpr (P == P64) {
-                    if (a.lazy_y) {
+                    if (a.lazy_y && !a.keep_y) {
                         // x += y in fp64, y = 0 (the group-wise update of Sec.3.2)
                         store_site<P>((char*)a.x + (size_t)r * a.x_rs, Vh, s, xr, xi);
                         float z[3] = {0.f, 0.f, 0.f}, zi[3] = {0.f, 0.f, 0.f};

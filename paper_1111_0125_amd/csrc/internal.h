@@ -134,6 +134,7 @@ struct EngineRun {
     size_t b_rs = 0;
     int K = 16;
     int F = 8;                // iterations between the predicated fix-ups
+    int variant = 0;          // mixed CG variant (MixedVariant), the same for every slot
     bool use_graph = true;
     bool timed = false;
     long long launched = 0;   // blocks enqueued (block j polls into buffer j % 2)
@@ -217,6 +218,7 @@ struct HopExtra {
     void* aux = nullptr;
     size_t aux_rs = 0;
     int aux_prec = P32;
+    int keep_y = 0;
 };
 
 hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, const HopTune& t,

@@ -382,6 +382,31 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
         case FIN_ACTIVATE:
             s.flags = F_ACTIVE;
             break;
+        case FIN_TRUE:
+            s.rr_true = sum;
+            break;
+        case FIN_GW: {
+            // y has been folded into x; the iterated residual carries on (its
+            // beta stays), after a stall from d = r
+            const bool stall = (s.flags & F_STALL) != 0;
+            s.updates += 1;
+            if (s.rr <= s.rr_stop || (s.flags & F_MAXIT)) {
+                s.flags = F_CHECK | (s.flags & F_MAXIT);
+                break;
+            }
+            if (stall) {
+                s.beta = 0.0;
+                s.restarts += 1;
+            }
+            s.rmax = s.rmin = s.rstart = sqrt(s.rr);
+            s.since = 0;
+            s.flags = F_ACTIVE;
+            break;
+        }
+        case FIN_GW_CHECK:
+            s.rr_true = sum;
+            s.flags = sum <= s.rr_stop ? F_DONE : ((s.flags & F_MAXIT) ? F_MAXIT : F_INACC);
+            break;
         case FIN_RU_END: {
             const double rt = sum;
             s.rr_true = rt;

@@ -43,6 +43,7 @@ struct HopArgs {
     void* aux;
     size_t aux_rs;
     int aux_prec;
+    int keep_y;            // with lazy_y: use x + y but store neither (reliable-update-only ablation)
     double m2[16];         // mass^2 per right-hand side (used when st is null)
     RhsState* st;          // null: every RHS is processed
     unsigned run_mask;     // process RHS r iff st[r].flags & run_mask
@@ -64,6 +65,7 @@ enum VecOp : int {
     OP_START = 1,      // d = q(r64); if rs: rs = q(r64); if y: y = 0
     OP_UPD_CG = 2,     // x += a d, r -= a Ad, |r|^2 -> FIN_CG           (fp64)
     OP_UPD_MIXED = 3,  // y += a d, rs = q(rs - a Ad), |rs|^2 -> FIN_MIXED
+    OP_FOLD = 4,       // x64 += y, y = 0 (f0 = x64, f1 = y)
 };
 
 struct VecArgs {

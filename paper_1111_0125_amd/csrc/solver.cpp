@@ -182,9 +182,10 @@ namespace {
 
 struct Ctx {
     stag_engine* e;
-    Issue is;   // a stream, or a graph under construction
-    int nk;     // kernel block size (>= highest busy slot + 1)
-    bool timed; // eager only: bracket each kernel with timing events
+    Issue is;     // a stream, or a graph under construction
+    int nk;       // kernel block size (>= highest busy slot + 1)
+    bool timed;   // eager only: bracket each kernel with timing events
+    int variant;  // mixed CG variant of the run (MixedVariant)
 };
 
 // Launch `fn` bracketed by timing events when the run is timed.
@@ -346,9 +347,23 @@ hipError_t enqueue_check(const Ctx& c) {
 // stores x += y and y = 0 at its own site, forms r = b - A x with |r|^2 and
 // stores the inner residual q(r); the finalisation then finishes the slot
 // or carries the direction over (Eq.6), restarting it after a stall.
+// Ablations: the reliable update alone keeps y (r = b - A (x + y)); the
+// group-wise update alone folds y into x, leaves r as iterated and checks
+// the true residual only once the iterated one has met the tolerance.
 hipError_t enqueue_update(const Ctx& c) {
     stag_engine* e = c.e;
     const unsigned run = F_RU | F_STALL;
+    hipError_t err;
+    if (c.variant == MIXED_GROUPWISE) {
+        if ((err = vec(c, e->prec, OP_FOLD, {{e->x64, e->rs64}, {e->y32, e->rs32}}, FIN_STORE, run)))
+            return err;
+        Reduce gw = make_red(e, FIN_GW);
+        gw.nparts = 0;  // a state transition: nothing to sum
+        if ((err = timed_launch(c, KK_OTHER, [&]() { return launch_finalize(c.nk, gw, run, c.is); })))
+            return err;
+        if ((err = hop(c, P64, 1, EPI_PLAIN, e->x64, e->t64, nullptr, FIN_STORE, F_CHECK))) return err;
+        return hop(c, P64, 2, EPI_RESID, e->t64, e->r64, e->x64, FIN_GW_CHECK, F_CHECK);
+    }
     HopExtra x1;
     x1.lazy_y = e->y32;
     x1.lazy_y_rs = e->rs32;
@@ -356,10 +371,10 @@ hipError_t enqueue_update(const Ctx& c) {
     x2.aux = e->rs;
     x2.aux_rs = e->rsP;
     x2.aux_prec = e->prec;
+    x2.keep_y = c.variant == MIXED_RELIABLE ? 1 : 0;
     Opt o1, o2;
     o1.ex = &x1;
     o2.ex = &x2;
-    hipError_t err;
     if ((err = hop(c, P64, 1, EPI_PLAIN, e->x64, e->t64, nullptr, FIN_STORE, run, nullptr, o1)))
         return err;
     return hop(c, P64, 2, EPI_RESID, e->t64, e->r64, e->x64, FIN_RU_END, run, nullptr, o2);
@@ -389,8 +404,8 @@ int status_of_flags(unsigned f) {
 }
 
 bool flags_terminal(unsigned f) {
-    return (f & (F_DONE | F_BADINPUT | F_BREAKDOWN | F_ESTALL)) ||
-           ((f & F_MAXIT) && !(f & (F_CONV | F_RU)));
+    return (f & (F_DONE | F_BADINPUT | F_BREAKDOWN | F_ESTALL | F_INACC)) ||
+           ((f & F_MAXIT) && !(f & (F_CONV | F_RU | F_CHECK)));
 }
 
 #define RCK(call)                                                                              \
@@ -449,7 +464,7 @@ int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots) {
         s.max_stall = p.max_stall > 0 ? p.max_stall : 20;
         s.max_iter = p.max_iter > 0 ? p.max_iter : (int)std::min<uint64_t>(10 * n_unknowns, 1000000);
         s.flags = F_NEW | (si.x0 ? F_X0 : 0u);
-        s.variant = p.mixed_variant == MIXED_RESTART ? MIXED_RESTART : MIXED_CARRY;
+        s.variant = p.mixed_variant;
         RCK(hipMemcpyAsync(e->st + si.slot, &s, sizeof(RhsState), hipMemcpyHostToDevice, R.s));
         if (si.x0) {
             RCK(hipMemcpyAsync((char*)e->x64 + (size_t)si.slot * e->rs64, si.x0, e->rs64,
@@ -460,7 +475,7 @@ int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots) {
         // polls of blocks launched before this start show the slot's previous state
         R.start_after[si.slot] = R.launched - 1;
     }
-    Ctx c{e, Issue{R.s}, pick_n(R.busy_hi), R.timed};
+    Ctx c{e, Issue{R.s}, pick_n(R.busy_hi), R.timed, R.variant};
     void* b = const_cast<void*>(R.b);
     RCK(vec(c, P64, OP_INIT_B, {{b, R.b_rs}, {e->r64, e->rs64}, {e->x64, e->rs64}}, FIN_INIT, F_NEW));
     if (any_x0) {
@@ -486,7 +501,7 @@ int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots) {
 // buffer it uses belongs to the engine, so it serves every later block.
 static int get_graph(EngineRun& R, int nk, hipGraphExec_t* out) {
     stag_engine* e = R.e;
-    const long long key = ((long long)R.K << 16) | (long long)nk;
+    const long long key = ((long long)R.K << 16) | ((long long)R.variant << 8) | (long long)nk;
     auto it = e->graphs.find(key);
     if (it != e->graphs.end()) {
         *out = it->second;
@@ -497,7 +512,7 @@ static int get_graph(EngineRun& R, int nk, hipGraphExec_t* out) {
     if (err == hipSuccess) {
         Issue is;
         is.gb = &gb;
-        Ctx c{e, is, nk, false};
+        Ctx c{e, is, nk, false, R.variant};
         err = enqueue_block(c, R.K, R.F);
     }
     hipGraphExec_t exec = nullptr;
@@ -526,7 +541,7 @@ int run_enqueue_block(EngineRun& R) {
         if (rc) return rc;
         RCK(hipGraphLaunch(exec, R.s));
     } else {
-        Ctx c{e, Issue{R.s}, nk, R.timed};
+        Ctx c{e, Issue{R.s}, nk, R.timed, R.variant};
         RCK(enqueue_block(c, R.K, R.F));
     }
     RCK(hipMemcpyAsync(e->host[buf], e->st, state_bytes(e->N), hipMemcpyDeviceToHost, R.s));
@@ -584,6 +599,7 @@ int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, siz
     RCK(hipMemcpy2DAsync(e->b64, e->rs64, b64, b_rs, e->rs64, n, hipMemcpyDeviceToDevice, stream));
     EngineRun R;
     run_init(R, e, stream, e->b64, e->rs64, K, p.use_graph != 0);
+    R.variant = e->prec != P64 ? p.mixed_variant : MIXED_CARRY;
     std::vector<SlotInit> slots(n);
     for (int r = 0; r < n; ++r) {
         slots[r] = SlotInit{r, mass[r], p};
@@ -609,6 +625,16 @@ int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, siz
             std::copy(h, h + n, fin.begin());
             break;
         }
+    }
+    if (R.variant == MIXED_RELIABLE) {
+        // the reliable-update-only ablation never folds y into x: the
+        // solution is x + y; report its true residual
+        Ctx c{e, Issue{stream}, pick_n(n), R.timed, R.variant};
+        const unsigned any = ~0u;
+        RCK(vec(c, e->prec, OP_FOLD, {{e->x64, e->rs64}, {e->y32, e->rs32}}, FIN_STORE, any));
+        RCK(hop(c, P64, 1, EPI_PLAIN, e->x64, e->t64, nullptr, FIN_STORE, any));
+        RCK(hop(c, P64, 2, EPI_RESID, e->t64, e->r64, e->x64, FIN_TRUE, any));
+        RCK(hipMemcpyAsync(fin.data(), e->st, sizeof(RhsState) * n, hipMemcpyDeviceToHost, stream));
     }
     RCK(hipStreamSynchronize(stream));
     RCK(hipMemcpy2DAsync(x_out, x_rs, e->x64, e->rs64, e->rs64, n, hipMemcpyDeviceToDevice, stream));

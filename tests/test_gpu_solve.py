@@ -133,6 +133,36 @@ def test_fig2_restart_variant_matches_refinement_oracle(stag, ctx):
     assert rc2 == 0 and st2[0]["iters"] < st[0]["iters"]
 
 
+@pytest.mark.parametrize("variant", ["carry", "reliable", "groupwise"])
+def test_update_ablations_match_oracle(stag, ctx, variant):
+    """The Sec.3.2 scheme and its two one-sided ablations on a system where
+    fp32 alone cannot reach the tolerance (4^4 Haar, m = 0.1, 1e-10): the
+    GPU reproduces the oracle's outcome, iteration count and residual level."""
+    L, m, tol = (4, 4, 4, 4), 0.1, 1e-10
+    U = links(L, "haar", 11)
+    b = synth.gaussian_rhs(L, 1, 111)
+    rc, st, x = solve(stag, ctx, L, U, b, [m], tol, inner="f32", mixed_variant=variant)
+    log(variant, rc, st[0])
+    upd = {"carry": "both"}.get(variant, variant)
+    _, est = ostag.mixed_cg(U, L, m, b[0], tol, prec="f32", update=upd)
+    log("oracle", est)
+    res = true_res(U, L, [m], b, x)[0]
+    assert abs(st[0]["true_rel_res"] - res) <= 1e-3 * res + 1e-14
+    if variant == "carry":
+        assert rc == 0 and res <= tol
+        assert abs(st[0]["iters"] - est["iters"]) <= 0.05 * est["iters"] + 5
+    elif variant == "reliable":
+        # stalls at fp32's level and runs to the iteration cap, like the oracle
+        assert rc == stag.STAG_ENOCONV and est["status"] == "noconv"
+        assert st[0]["iters"] == est["iters"]
+        assert res > 1e3 * tol and 0.1 < res / est["true_rel_res"] < 10
+    else:
+        # the iterated residual meets tol, the true one does not
+        assert rc == stag.STAG_ENOCONV and est["status"] == "inaccurate"
+        assert abs(st[0]["iters"] - est["iters"]) <= 0.05 * est["iters"] + 5
+        assert res > 10 * tol and 0.1 < res / est["true_rel_res"] < 10
+
+
 def test_batched_equals_single(stag, ctx):
     """Each right-hand side of a block solve equals its own single solve."""
     L, tol = (8, 8, 8, 8), 1e-8

@@ -301,6 +301,47 @@ def test_refinement_fig2_converges(mixed_case):
 
 # ---------------------------------------------------------------- paper numbers
 
+def test_update_ablations_agree_when_well_conditioned():
+    """Both one-sided update variants of Sec.3.2 are still correct solvers on a
+    well-conditioned system far from fp32's limit: all three agree with the
+    dense solve and take the same iterations."""
+    L, m, tol = (4, 4, 4, 4), 1.0, 1e-5
+    U = synth.haar_links(L, 11)
+    b = synth.gaussian_rhs(L, 1, 111)[0]
+    A = dense.dense_A_even(U, L, m)
+    xd = np.linalg.solve(A, b.ravel()).reshape(-1, 3)
+    ev = np.linalg.eigvalsh(A)
+    iters = set()
+    for upd in ("both", "reliable", "groupwise"):
+        x, st = stag.mixed_cg(U, L, m, b, tol, prec="f32", update=upd)
+        assert st["status"] == "ok", (upd, st)
+        res = math.sqrt(stag.norm2(b - stag.apply_A(U, x, L, m)) / stag.norm2(b))
+        assert res <= tol
+        assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= (ev.max() / ev.min()) * tol
+        iters.add(st["iters"])
+    assert len(iters) == 1
+
+
+def test_both_updates_are_needed():
+    """Sec.3.2 applies the reliable and the group-wise update together: near a
+    tolerance fp32 cannot hold, the reliable update alone keeps the solution
+    in fp32 and stalls far above it, and the group-wise update alone lets the
+    iterated residual drift from the true one, which then misses it."""
+    L, m, tol = (4, 4, 4, 4), 0.1, 1e-10
+    U = synth.haar_links(L, 11)
+    b = synth.gaussian_rhs(L, 1, 111)[0]
+    _, both = stag.mixed_cg(U, L, m, b, tol, prec="f32")
+    assert both["status"] == "ok" and both["true_rel_res"] <= tol
+    x, rel = stag.mixed_cg(U, L, m, b, tol, prec="f32", update="reliable")
+    assert rel["status"] == "noconv" and rel["true_rel_res"] > 1e3 * tol
+    # the reported residual is that of the returned x = x + y
+    res = math.sqrt(stag.norm2(b - stag.apply_A(U, x, L, m)) / stag.norm2(b))
+    assert abs(res - rel["true_rel_res"]) <= 1e-12
+    x, gw = stag.mixed_cg(U, L, m, b, tol, prec="f32", update="groupwise")
+    assert gw["status"] == "inaccurate" and gw["true_rel_res"] > 10 * tol
+    assert abs(gw["iters"] - both["iters"]) <= 0.05 * both["iters"]
+
+
 def test_paper_cost_model_golden():
     g = json.load(open(os.path.join(GOLDEN, "paper_cost_model.json")))
     reals = 8 * 18 + 8 * 6 + 6
