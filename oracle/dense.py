@@ -11,6 +11,10 @@ TEST INFRASTRUCTURE (see the package docstring).
   and for constant diagonal links, from Fourier analysis: with the staggered
   phases the cross terms of D^2 cancel and -D^2 acts as
   sum_mu 4 sin^2(p_mu + theta_mu) on a colour component with twist theta.
+  With ``naik=(c1, c3)`` the links are c1 times those and the long links
+  c3 times their cube (the improved operator); a three-hop also anticommutes
+  with the other directions' phases, and -D^2 acts as
+  sum_mu 4 (c1 sin q_mu + c3 sin 3 q_mu)^2 with q = p + theta.
 * ``fft_solve``: the exact solution of A x = b for such fields.
 """
 
@@ -31,25 +35,30 @@ def _eta(mu, c):
     return -1.0 if sum(c[:mu]) % 2 else 1.0
 
 
-def dense_D(U, L):
-    """Full 3V x 3V Dirac matrix (rows/cols ordered lex * 3 + colour)."""
+def dense_D(U, L, Ulong=None):
+    """Full 3V x 3V Dirac matrix (rows/cols ordered lex * 3 + colour).
+
+    With Ulong (improved operator, U = fat links) the three-hop entries
+    eta N(x) at x+3mu and -eta N(x-3mu)^+ at x-3mu are added as well."""
     L = tuple(int(v) for v in L)
     Lx, Ly, Lz, Lt = L
     V = Lx * Ly * Lz * Lt
     D = np.zeros((3 * V, 3 * V), dtype=np.complex128)
+    hops = [(1, U)] if Ulong is None else [(1, U), (3, Ulong)]
     for c in itertools.product(range(Lx), range(Ly), range(Lz), range(Lt)):
         x = _lex(c, L)
         for mu in range(4):
-            fwd = list(c)
-            fwd[mu] = (fwd[mu] + 1) % L[mu]
-            bwd = list(c)
-            bwd[mu] = (bwd[mu] - 1) % L[mu]
-            u_here = U[c[3], c[2], c[1], c[0], mu]
-            u_back = U[bwd[3], bwd[2], bwd[1], bwd[0], mu]
-            y_f = _lex(fwd, L)
-            y_b = _lex(bwd, L)
-            D[3 * x:3 * x + 3, 3 * y_f:3 * y_f + 3] += _eta(mu, c) * u_here
-            D[3 * x:3 * x + 3, 3 * y_b:3 * y_b + 3] -= _eta(mu, bwd) * np.conj(u_back.T)
+            for dist, W in hops:
+                fwd = list(c)
+                fwd[mu] = (fwd[mu] + dist) % L[mu]
+                bwd = list(c)
+                bwd[mu] = (bwd[mu] - dist) % L[mu]
+                w_here = W[c[3], c[2], c[1], c[0], mu]
+                w_back = W[bwd[3], bwd[2], bwd[1], bwd[0], mu]
+                y_f = _lex(fwd, L)
+                y_b = _lex(bwd, L)
+                D[3 * x:3 * x + 3, 3 * y_f:3 * y_f + 3] += _eta(mu, c) * w_here
+                D[3 * x:3 * x + 3, 3 * y_b:3 * y_b + 3] -= _eta(mu, bwd) * np.conj(w_back.T)
     return D
 
 
@@ -68,8 +77,8 @@ def even_rows(L):
     return np.array(idx)
 
 
-def dense_A_even(U, L, m):
-    D = dense_D(U, L)
+def dense_A_even(U, L, m, Ulong=None):
+    D = dense_D(U, L, Ulong)
     A = m * m * np.eye(D.shape[0]) - D @ D
     e = even_rows(L)
     return A[np.ix_(e, e)]
@@ -81,17 +90,26 @@ def _momenta(L):
     return [2 * np.pi * np.arange(n) / n for n in (Lx, Ly, Lz, Lt)]
 
 
-def free_spectrum(L, m):
+def _hop_symbol(q, naik):
+    """|D| symbol of one direction: 2 sin q, or 2 (c1 sin q + c3 sin 3q)."""
+    if naik is None:
+        return 2.0 * np.sin(q)
+    c1, c3 = naik
+    return 2.0 * (c1 * np.sin(q) + c3 * np.sin(3.0 * q))
+
+
+def free_spectrum(L, m, naik=None):
     """Sorted eigenvalues of A on the even sites for unit links (3 colours).
 
     Momenta p and p + (pi, pi, pi, pi) share one even-site eigenvector pair,
     so each value of the full-lattice set is counted once per such pair.
     """
-    return twisted_spectrum(L, m, np.zeros((4, 2)))
+    return twisted_spectrum(L, m, np.zeros((4, 2)), naik)
 
 
-def twisted_spectrum(L, m, theta):
-    """Sorted eigenvalues of A for constant links diag(e^{i a}, e^{i b}, e^{-i(a+b)})."""
+def twisted_spectrum(L, m, theta, naik=None):
+    """Sorted eigenvalues of A for constant links diag(e^{i a}, e^{i b}, e^{-i(a+b)})
+    (times c1, with long links c3 diag(e^{3i a}, ...), for naik = (c1, c3))."""
     theta = np.asarray(theta, dtype=np.float64).reshape(4, 2)
     ps = _momenta(L)
     vals = []
@@ -101,7 +119,7 @@ def twisted_spectrum(L, m, theta):
         for mu in range(4):
             shape = [1, 1, 1, 1]
             shape[mu] = len(ps[mu])
-            grid = grid + 4.0 * np.sin(ps[mu] + th[mu]).reshape(shape) ** 2
+            grid = grid + _hop_symbol(ps[mu] + th[mu], naik).reshape(shape) ** 2
         vals.append(m * m + grid.ravel())
     v = np.sort(np.concatenate(vals))
     # every eigenvalue of the full lattice operator appears twice (once per
@@ -109,9 +127,10 @@ def twisted_spectrum(L, m, theta):
     return v[::2]
 
 
-def fft_solve(b_even, L, m, theta=None):
+def fft_solve(b_even, L, m, theta=None, naik=None):
     """Exact solution of A x = b for constant diagonal links (unit links when
-    theta is None), by Fourier transform of the full lattice with b placed on
+    theta is None; the improved operator's fields of ``twisted_spectrum``
+    with naik), by Fourier transform of the full lattice with b placed on
     the even sites and zeros on the odd ones. Returns the even-site x."""
     from .stag import to_full, from_full
     L = tuple(int(v) for v in L)
@@ -128,6 +147,6 @@ def fft_solve(b_even, L, m, theta=None):
             th = (theta[mu, 0], theta[mu, 1], -theta[mu, 0] - theta[mu, 1])[c]
             shape = [1, 1, 1, 1]
             shape[ax] = len(n[ax])
-            lam = lam + 4.0 * np.sin(n[ax] + th).reshape(shape) ** 2
+            lam = lam + _hop_symbol(n[ax] + th, naik).reshape(shape) ** 2
         out[..., c] = np.fft.ifftn(np.fft.fftn(full[..., c]) / lam)
     return from_full(out, L, 0)

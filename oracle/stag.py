@@ -100,13 +100,19 @@ def _mhv(u, v):
     return (np.conj(np.swapaxes(u, -1, -2)) @ v[..., :, None])[..., 0]
 
 
-def dslash_full(U, chi, L, dtype=np.complex128):
+def dslash_full(U, chi, L, dtype=np.complex128, Ulong=None):
     """(D chi)(x) = sum_mu eta_mu(x) U_mu(x) chi(x+mu) - eta_mu(x-mu) U_mu(x-mu)^+ chi(x-mu).
 
     Eq.5 with the phases of Sec.2 multiplied into the links; chi is a
     full-lattice field [t, z, y, x, c]. Both hops are accumulated, so on an
     extent-2 direction (where x+mu and x-mu coincide) both terms count.
     ``dtype`` selects the arithmetic (complex64 emulates fp32 arithmetic).
+
+    With ``Ulong`` (the improved operator: U then holds the fat links) the
+    three-hop terms eta_mu(x) N_mu(x) chi(x+3mu) - eta_mu(x-3mu) N_mu(x-3mu)^+
+    chi(x-3mu) are added, N being the caller's long links (products of three
+    links along mu with the Naik coefficient folded in). The phase does not
+    depend on x_mu, so eta_mu(x-3mu) = eta_mu(x).
     """
     L = extents(L)
     e = eta(L).astype(np.float32 if dtype == np.complex64 else np.float64)
@@ -117,24 +123,30 @@ def dslash_full(U, chi, L, dtype=np.complex128):
         uf = (e[mu][..., None, None] * U[..., mu, :, :]).astype(dtype, copy=False)
         out += _mv(uf, np.roll(chi, -1, axis=ax))
         out -= np.roll(_mhv(uf, chi), 1, axis=ax)
+        if Ulong is not None:
+            nf = (e[mu][..., None, None] * Ulong[..., mu, :, :]).astype(dtype, copy=False)
+            out += _mv(nf, np.roll(chi, -3, axis=ax))
+            out -= np.roll(_mhv(nf, chi), 3, axis=ax)
     return out
 
 
-def dslash(U, v, L, p_in):
+def dslash(U, v, L, p_in, Ulong=None):
     """Parity-to-parity Dirac operator: D_oe for p_in = 0, D_eo for p_in = 1.
 
-    v has shape (Vh, 3) on parity p_in; the result lives on parity 1 - p_in.
+    v has shape (Vh, 3) on parity p_in; the result lives on parity 1 - p_in
+    (a three-hop also changes parity). Ulong: the improved operator.
     """
-    return from_full(dslash_full(U, to_full(v, L, p_in), L), L, 1 - p_in)
+    return from_full(dslash_full(U, to_full(v, L, p_in), L, Ulong=Ulong), L, 1 - p_in)
 
 
-def apply_A(U, chi_e, L, m):
+def apply_A(U, chi_e, L, m, Ulong=None):
     """h = A chi with A = -D^2 + m^2 (Eq.2-3), chi and h on even sites.
 
     D maps each parity to the other, so on even sites -D^2 = -D_eo D_oe.
+    Ulong: the improved operator (U then holds the fat links).
     """
     full = to_full(chi_e, L, 0)
-    dd = dslash_full(U, dslash_full(U, full, L), L)
+    dd = dslash_full(U, dslash_full(U, full, L, Ulong=Ulong), L, Ulong=Ulong)
     return m * m * chi_e - from_full(dd, L, 0)
 
 
@@ -262,18 +274,28 @@ def quantiser(prec):
     raise ValueError(prec)
 
 
-def f16s_link_scale(U, L):
+def f16s_link_scale(U, L, Ulong=None):
     """Per-site scale for fp16 links.
 
     A site x of either parity reads, in the hop stage that produces x, the
     four links U_mu(x) and the four links U_mu(x - mu); its scale is the
-    largest |Re| or |Im| over those 144 reals, rounded to fp32.
+    largest |Re| or |Im| over those 144 reals, rounded to fp32. The improved
+    operator also reads N_mu(x) and N_mu(x - 3mu), and the scale covers
+    those 288 reals.
     """
-    U32 = U.astype(np.complex64)
-    a = np.maximum(np.abs(U32.real), np.abs(U32.imag)).max(axis=(-1, -2))  # [t,z,y,x,mu]
+    def amax(W):
+        W32 = W.astype(np.complex64)
+        return np.maximum(np.abs(W32.real), np.abs(W32.imag)).max(axis=(-1, -2))  # [t,z,y,x,mu]
+
+    a = amax(U)
     s = a.max(axis=-1)
     for mu in range(4):
         s = np.maximum(s, np.roll(a[..., mu], 1, axis=MU_AXIS[mu]))
+    if Ulong is not None:
+        n = amax(Ulong)
+        s = np.maximum(s, n.max(axis=-1))
+        for mu in range(4):
+            s = np.maximum(s, np.roll(n[..., mu], 3, axis=MU_AXIS[mu]))
     return s.astype(np.float32)
 
 
@@ -292,35 +314,37 @@ class LowOperator:
     ``prec`` = "f16s": links stored as fp16 with the per-site scale of
     ``f16s_link_scale``; the intermediate odd-site vector and the result are
     stored with ``q_f16s``. Arithmetic is fp32 in both cases.
+    ``Ulong``: the improved operator (three-hop terms, U = fat links).
     """
 
-    def __init__(self, U, L, m, prec):
+    def __init__(self, U, L, m, prec, Ulong=None):
         self.L = extents(L)
         self.m2 = np.float32(m * m)
         self.prec = prec
         self.q = quantiser(prec)
         e = eta(self.L).astype(np.float32)
-        U32 = U.astype(np.complex64)
-        self.fwd = []
-        self.bwd = []
+        self.hops = []  # (distance, direction axis, forward link, backward link at x)
         if prec == "f16s":
-            s = f16s_link_scale(U, self.L)
-        for mu in range(4):
-            ax = MU_AXIS[mu]
-            u = U32[..., mu, :, :]
-            ub = np.roll(u, 1, axis=ax)           # U_mu(x - mu) stored at x
-            if prec == "f16s":
-                u = _q_link_f16(u, s)
-                ub = _q_link_f16(ub, s)
-            self.fwd.append((e[mu][..., None, None] * u).astype(np.complex64))
-            self.bwd.append((np.roll(e[mu], 1, axis=ax)[..., None, None] * ub).astype(np.complex64))
+            s = f16s_link_scale(U, self.L, Ulong)
+        fields = [(1, U)] if Ulong is None else [(1, U), (3, Ulong)]
+        for dist, W in fields:
+            W32 = W.astype(np.complex64)
+            for mu in range(4):
+                ax = MU_AXIS[mu]
+                u = W32[..., mu, :, :]
+                ub = np.roll(u, dist, axis=ax)        # W_mu(x - dist mu) stored at x
+                if prec == "f16s":
+                    u = _q_link_f16(u, s)
+                    ub = _q_link_f16(ub, s)
+                fwd = (e[mu][..., None, None] * u).astype(np.complex64)
+                bwd = (np.roll(e[mu], dist, axis=ax)[..., None, None] * ub).astype(np.complex64)
+                self.hops.append((dist, ax, fwd, bwd))
 
     def dslash_full(self, chi):
         out = np.zeros_like(chi, dtype=np.complex64)
-        for mu in range(4):
-            ax = MU_AXIS[mu]
-            out += _mv(self.fwd[mu], np.roll(chi, -1, axis=ax))
-            out -= _mhv(self.bwd[mu], np.roll(chi, 1, axis=ax))
+        for dist, ax, fwd, bwd in self.hops:
+            out += _mv(fwd, np.roll(chi, -dist, axis=ax))
+            out -= _mhv(bwd, np.roll(chi, dist, axis=ax))
         return out
 
     def __call__(self, d):
@@ -336,11 +360,12 @@ class LowOperator:
 # Fig.2 iterative refinement (outer fp64, fresh low-precision inner CG)
 # --------------------------------------------------------------------------
 
-def refinement_cg(U, L, m, b, tol, prec="f32", eps_in=0.1, max_iter=None):
+def refinement_cg(U, L, m, b, tol, prec="f32", eps_in=0.1, max_iter=None, Ulong=None):
     """Mixed CG by iterative refinement, Fig.2: the inner solve starts from
-    y = 0, r = r_k, d = r_k every outer step (no information carried over)."""
-    A64 = lambda v: apply_A(U, v, L, m)
-    Alow = LowOperator(U, L, m, prec)
+    y = 0, r = r_k, d = r_k every outer step (no information carried over).
+    Ulong: the improved operator (U = fat links)."""
+    A64 = lambda v: apply_A(U, v, L, m, Ulong)
+    Alow = LowOperator(U, L, m, prec, Ulong)
     q = quantiser(prec)
     b = np.asarray(b, dtype=np.complex128)
     max_iter = default_max_iter(b.size) if not max_iter or max_iter <= 0 else max_iter
@@ -380,7 +405,7 @@ def refinement_cg(U, L, m, b, tol, prec="f32", eps_in=0.1, max_iter=None):
 # --------------------------------------------------------------------------
 
 def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
-             max_iter=None, max_stall=20, carry_direction=True, update="both"):
+             max_iter=None, max_stall=20, carry_direction=True, update="both", Ulong=None):
     """Corrected mixed-precision CG of Sec.3.2, emulated on the CPU.
 
     Inner iterations run on stored low-precision vectors (fp32 arithmetic,
@@ -408,14 +433,15 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
     folds y into x and never recomputes r, the direction continuing with
     the iterated beta; when its iterated residual meets the tolerance the
     true residual is computed once and decides ("inaccurate" if it misses).
+    ``Ulong``: the improved operator (U = fat links), in both precisions.
     Returns (x, stats).
     """
     if update not in ("both", "reliable", "groupwise"):
         raise ValueError(update)
     if stall_iters is None:
         stall_iters = 100 if prec == "f16s" else math.inf
-    A64 = lambda v: apply_A(U, v, L, m)
-    Alow = LowOperator(U, L, m, prec)
+    A64 = lambda v: apply_A(U, v, L, m, Ulong)
+    Alow = LowOperator(U, L, m, prec, Ulong)
     q = quantiser(prec)
     b = np.asarray(b, dtype=np.complex128)
     max_iter = default_max_iter(b.size) if not max_iter or max_iter <= 0 else max_iter

@@ -36,6 +36,10 @@ __all__ = [
     "twisted_links",
     "random_gauge",
     "gauge_transform_links",
+    "gaussian_links",
+    "naik_links",
+    "NAIK_C1",
+    "NAIK_C3",
     "gaussian_rhs",
     "request_stream",
     "CONFIGS",
@@ -156,13 +160,46 @@ def random_gauge(L, seed: int) -> np.ndarray:
 _MU_AXIS = (3, 2, 1, 0)  # array axis of the x, y, z, t direction in [t, z, y, x]
 
 
-def gauge_transform_links(U: np.ndarray, g: np.ndarray) -> np.ndarray:
-    """U^g_mu(x) = g(x) U_mu(x) g(x + mu)^dagger (periodic lattice)."""
+def gauge_transform_links(U: np.ndarray, g: np.ndarray, dist: int = 1) -> np.ndarray:
+    """U^g_mu(x) = g(x) U_mu(x) g(x + dist mu)^dagger (periodic lattice).
+
+    dist = 3 transforms long links, which connect x to x + 3 mu."""
     out = np.empty_like(U)
     for mu in range(4):
-        g_fwd = np.roll(g, -1, axis=_MU_AXIS[mu])
+        g_fwd = np.roll(g, -int(dist), axis=_MU_AXIS[mu])
         out[..., mu, :, :] = g @ U[..., mu, :, :] @ np.conj(np.swapaxes(g_fwd, -1, -2))
     return out
+
+
+def gaussian_links(L, seed: int) -> np.ndarray:
+    """Links with independent unit-variance complex normal entries (not unitary)."""
+    return complex_gaussian(make_rng(seed), _link_shape(L) + (3, 3))
+
+
+# Coefficients of the one- and three-hop terms that cancel the leading
+# discretisation error of the symmetric difference (no factor 1/2 in front):
+# c1 (f(x+1) - f(x-1)) + c3 (f(x+3) - f(x-3)) = 2 f'(x) + O(f^(5)).
+NAIK_C1 = 9.0 / 8.0
+NAIK_C3 = -1.0 / 24.0
+
+
+def naik_links(U: np.ndarray, c1: float = NAIK_C1, c3: float = NAIK_C3,
+               fat_noise: float = 0.0, seed: int = 0):
+    """Input fields of the improved staggered operator built from links U.
+
+    Returns (fat, long): fat_mu(x) = c1 U_mu(x) (+ fat_noise times complex
+    normal entries, so that fat links are not unitary, like smeared links),
+    long_mu(x) = c3 U_mu(x) U_mu(x + mu) U_mu(x + 2 mu).
+    """
+    fat = c1 * U
+    if fat_noise:
+        fat = fat + fat_noise * complex_gaussian(make_rng(seed), U.shape)
+    long = np.empty_like(U)
+    for mu in range(4):
+        ax = _MU_AXIS[mu]
+        u = U[..., mu, :, :]
+        long[..., mu, :, :] = c3 * (u @ np.roll(u, -1, axis=ax) @ np.roll(u, -2, axis=ax))
+    return fat, long
 
 
 def gaussian_rhs(L, nrhs: int, seed: int) -> np.ndarray:

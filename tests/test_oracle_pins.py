@@ -376,6 +376,120 @@ def test_c_oracle_cg():
     assert rel(x, xd) < 1e-6
 
 
+# ---------------------------------------------------------------- improved operator
+
+# The improved (fat-link + three-hop) operator extends Eq.5 by the terms
+# eta N(x) chi(x+3mu) - eta N(x-3mu)^+ chi(x-3mu) with caller-supplied long
+# links N. Extents 4 alias x+3mu with x-mu, extent 6 aliases x+3mu with
+# x-3mu and extent 2 folds all four onto one neighbour.
+
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 2, 4, 2)])
+@pytest.mark.parametrize("p_in", [0, 1])
+def test_improved_dslash_matches_dense_bruteforce(L, p_in):
+    fat = synth.gaussian_links(L, 201)
+    lng = synth.gaussian_links(L, 202)
+    D = dense.dense_D(fat, L, lng)
+    e = dense.even_rows(L)
+    o = np.setdiff1d(np.arange(D.shape[0]), e)
+    rows_in, rows_out = (e, o) if p_in == 0 else (o, e)
+    v = synth.gaussian_rhs(L, 1, 203)[0]
+    out = stag.dslash(fat, v, L, p_in, Ulong=lng)
+    ref = D[np.ix_(rows_out, rows_in)] @ v.ravel()
+    assert rel(out, ref.reshape(-1, 3)) < 1e-13
+    # the three-hop terms really contribute
+    assert rel(stag.dslash(fat, v, L, p_in), ref.reshape(-1, 3)) > 1e-2
+
+
+def test_improved_dense_is_anti_hermitian_and_A_positive():
+    L, m = (4, 2, 6, 2), 0.2
+    fat = synth.gaussian_links(L, 211)
+    lng = synth.gaussian_links(L, 212)
+    D = dense.dense_D(fat, L, lng)
+    assert np.abs(D + D.conj().T).max() < 1e-14
+    A = dense.dense_A_even(fat, L, m, lng)
+    assert np.abs(A - A.conj().T).max() < 1e-13
+    assert np.linalg.eigvalsh(A).min() >= m * m - 1e-12
+
+
+def test_improved_free_spectrum_twisted_and_rotated():
+    # fat = c1 U, long = c3 U U U for constant diagonal U, gauge rotated:
+    # eigenvalues m^2 + sum_mu 4 (c1 sin q + c3 sin 3q)^2
+    L, m = (4, 6, 4, 4), 0.15
+    th = np.array([[0.3, 0.1], [0.5, -0.2], [0.7, 0.25], [-0.4, 0.9]])
+    U = synth.gauge_transform_links(synth.twisted_links(L, th), synth.random_gauge(L, 221))
+    fat, lng = synth.naik_links(U)
+    ev = np.linalg.eigvalsh(dense.dense_A_even(fat, L, m, lng))
+    ref = dense.twisted_spectrum(L, m, th, naik=(synth.NAIK_C1, synth.NAIK_C3))
+    assert np.abs(ev - ref).max() < 1e-12
+    # and not the one-hop spectrum with the fat links alone
+    assert np.abs(ev - dense.twisted_spectrum(L, m, th)).max() > 1e-2
+
+
+def test_naik_coefficients_cancel_leading_error():
+    # the improved symbol 2 (c1 sin p + c3 sin 3p) = 2p + O(p^5)
+    p = np.array([1e-2, 2e-2])
+    sym = 2 * (synth.NAIK_C1 * np.sin(p) + synth.NAIK_C3 * np.sin(3 * p))
+    err = np.abs(sym - 2 * p)
+    assert np.all(err < 2 * p ** 5)
+    assert abs(math.log2(err[1] / err[0]) - 5) < 0.05
+
+
+def test_improved_gauge_covariance():
+    L, m = (4, 6, 4, 8), 0.1
+    fat = synth.gaussian_links(L, 231)
+    lng = synth.gaussian_links(L, 232)
+    a = synth.gaussian_rhs(L, 1, 233)[0]
+    g = synth.random_gauge(L, 234)
+    fg = synth.gauge_transform_links(fat, g)
+    lg = synth.gauge_transform_links(lng, g, dist=3)
+    ge = g.reshape(-1, 3, 3)[stag.parity(L).reshape(-1) == 0]
+    lhs = stag.apply_A(fg, (ge @ a[..., None])[..., 0], L, m, Ulong=lg)
+    rhs = (ge @ stag.apply_A(fat, a, L, m, Ulong=lng)[..., None])[..., 0]
+    assert rel(lhs, rhs) < 1e-13
+
+
+def test_improved_cg_matches_fft_solve():
+    L, m, tol = (8, 8, 8, 8), 0.05, 1e-12
+    th = np.array([[0.1, 0.2], [0.3, 0.4], [-0.5, 0.6], [0.7, -0.8]])
+    g = synth.random_gauge(L, 241)
+    fat, lng = synth.naik_links(synth.gauge_transform_links(synth.twisted_links(L, th), g))
+    b = synth.gaussian_rhs(L, 1, 242)[0]
+    x, st = stag.cg(lambda v: stag.apply_A(fat, v, L, m, Ulong=lng), b, tol)
+    assert st["status"] == "ok"
+    ge = g.reshape(-1, 3, 3)[stag.parity(L).reshape(-1) == 0]
+    gh_b = (np.conj(np.swapaxes(ge, -1, -2)) @ b[..., None])[..., 0]
+    xe = (ge @ dense.fft_solve(gh_b, L, m, th, naik=(synth.NAIK_C1, synth.NAIK_C3))[..., None])[..., 0]
+    assert rel(x, xe) < 1e-9
+
+
+def test_improved_low_operator_error():
+    L, m = (4, 4, 4, 6), 0.1
+    fat, lng = synth.naik_links(synth.haar_links(L, 251), fat_noise=0.05, seed=252)
+    v = synth.gaussian_rhs(L, 1, 253)[0]
+    ref = stag.apply_A(fat, v, L, m, Ulong=lng)
+    e32 = rel(stag.LowOperator(fat, L, m, "f32", lng)(v), ref)
+    e16 = rel(stag.LowOperator(fat, L, m, "f16s", lng)(v), ref)
+    assert 1e-9 < e32 < 1e-6
+    assert 1e-5 < e16 < 1e-3
+    # the fp16 scale covers the long links: entries of N never exceed it
+    s = stag.f16s_link_scale(fat, L, lng)
+    assert np.all(s >= np.maximum(np.abs(lng.real), np.abs(lng.imag)).max(axis=(-1, -2, -3)))
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s"])
+def test_improved_mixed_cg_true_residual(prec):
+    L, m, tol = (6, 6, 6, 6), 0.05, 1e-10
+    fat, lng = synth.naik_links(synth.haar_links(L, 261), fat_noise=0.05, seed=262)
+    b = synth.gaussian_rhs(L, 1, 263)[0]
+    _, st64 = stag.cg(lambda v: stag.apply_A(fat, v, L, m, Ulong=lng), b, tol)
+    x, st = stag.mixed_cg(fat, L, m, b, tol, prec=prec, Ulong=lng)
+    assert st["status"] == "ok" and st["true_rel_res"] <= tol
+    r = b - stag.apply_A(fat, x, L, m, Ulong=lng)
+    assert math.sqrt(stag.norm2(r) / stag.norm2(b)) <= tol
+    if prec == "f32":
+        assert st["iters"] <= 1.1 * st64["iters"]
+
+
 # ---------------------------------------------------------------- pins bite
 
 def _mut_no_dagger(u, v):
