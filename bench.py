@@ -70,13 +70,13 @@ def csrc_digest():
     return h.hexdigest()
 
 
-def kernel_names(tune, inner):
+def kernel_names(tune, inner, npairs=4):
     """Symbol names of the three iteration kernels for a tuned shape (one RHS)."""
     p = {"f64": 0, "f32": 1, "f16s": 2}[inner]
     nt = "true" if tune["nt"] else "false"
     op = 2 if inner == "f64" else 3
-    return [f"void stag::k_hop<{p}, {tune['S1']}, 1, 0, {nt}>(stag::HopArgs)",
-            f"void stag::k_hop<{p}, {tune['S2']}, 1, 2, {nt}>(stag::HopArgs)",
+    return [f"void stag::k_hop<{p}, {tune['S1']}, 1, 0, {nt}, {npairs}>(stag::HopArgs)",
+            f"void stag::k_hop<{p}, {tune['S2']}, 1, 2, {nt}, {npairs}>(stag::HopArgs)",
             f"void stag::k_vec<{p}, 1, {op}>(stag::VecArgs)"]
 
 
@@ -100,6 +100,71 @@ def c3_inputs(synth):
     name = "c3_32x32x32x64"
     log("generating", name, "links ...")
     return synth.config_links(name), synth.config_rhs(name)
+
+
+def improved_32(stag, torch, costs, synth, reps=30):
+    """The improved operator (fat links + three-hop long links) on 32^3 x 64:
+    fields from the Haar links of the 32^3 x 64 workload (fat = 9/8 U plus
+    0.05 complex normal noise, long = -1/24 U U U), A-apply bandwidth per
+    precision and time to 1e-10 at m = 0.01, fp32-inner mixed CG against
+    plain fp64 CG."""
+    name = "c3_32x32x32x64"
+    cfg = synth.CONFIGS[name]
+    L, m, tol = cfg["L"], 0.01, 1e-10
+    U, b = c3_inputs(synth)
+    log("improved: building fat and long links")
+    fat, lng = synth.naik_links(U, fat_noise=0.05, seed=cfg["gauge_seed"] + 100)
+    out = {"lattice": list(L), "mass": m, "tol": tol,
+           "fields": "fat = 9/8 U + 0.05 N(0,1) complex, long = -1/24 U(x) U(x+mu) U(x+2mu)"}
+    v = synth.gaussian_rhs(L, 1, cfg["rhs_seed"])
+    with stag.Context(0) as ctx:
+        g = ctx.gauge(L, fat, precisions=("f64", "f32", "f16s"), long=lng)
+        del fat, lng
+        vh = g.vh
+        stream = torch.cuda.current_stream()
+        for prec in ("f64", "f32", "f16s"):
+            cfgt, _ = stag.stag_tune(ctx, g, prec, 1)
+            fi = ctx.field(g, 0, prec, 1).load(v)
+            fo = ctx.field(g, 0, prec, 1)
+            for _ in range(5):
+                stag.stag_apply_A(ctx, g, [m], fi, fo, stream=stream)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                stag.stag_apply_A(ctx, g, [m], fi, fo, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            byts = vh * costs.a_bytes_per_site(prec, improved=True)
+            gbs = byts / (ms * 1e-3) / 1e9
+            out["A_" + prec] = {"us_per_A": round(ms * 1e3, 2), "GB/s": round(gbs, 1),
+                                "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
+                                "GFLOP/s": round(vh * costs.a_flops_per_site(improved=True)
+                                                 / (ms * 1e-3) / 1e9, 1),
+                                "bytes_per_A": byts, "tune": cfgt}
+            log("improved A-apply", prec, out["A_" + prec])
+            fi.destroy()
+            fo.destroy()
+        fb = ctx.field(g, 0, "f64", 1).load(b)
+        fx = ctx.field(g, 0, "f64", 1)
+        for inner in ("f32", "f64"):
+            p = stag.cg_params(tol=tol, inner=inner)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st = stag.stag_cg_solve(ctx, g, [m], fb, fx, p)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            s0 = st[0]
+            out["solve_" + inner] = {"time_to_tol_s": round(dt, 4), "status": rc,
+                                     "iters": s0["iters"], "reliable_updates": s0["reliable_updates"],
+                                     "true_rel_res": s0["true_rel_res"],
+                                     "us_per_iteration": round(dt * 1e6 / max(s0["iters"], 1), 2)}
+            log("improved solve", inner, out["solve_" + inner])
+    if out["solve_f64"]["status"] == 0 and out["solve_f32"]["status"] == 0:
+        out["speedup_f32_vs_f64"] = round(out["solve_f64"]["time_to_tol_s"] /
+                                          out["solve_f32"]["time_to_tol_s"], 3)
+    return out
 
 
 def timed_solves(stag, torch, ctx, g, mass, fb, fx, params, k):
@@ -497,6 +562,8 @@ def main():
     if not args.no_extras:
         result["a_apply_32x32x32x64"] = a_apply_bandwidth(stag, torch, costs, synth)
         result["c3_32x32x32x64_solves"] = c3_solves(stag, torch, synth, costs)
+        result["improved_32x32x32x64"] = improved_32(stag, torch, costs, synth)
+        c3_inputs.cache_clear()
         result["batched_24x24x24x48_12rhs"] = batched_c4(stag, torch, synth)
         result["serving"] = serving(stag, synth, n_requests=args.serve_requests,
                                     full=args.serve_full)

@@ -125,6 +125,19 @@ int stag_memory_used(const stag_ctx* ctx, size_t* bytes);
  */
 int stag_gauge_create(stag_ctx* ctx, const int L[4], const double* U, int U_on_device,
                       int prec_mask, stag_gauge** out);
+/* stag_gauge_create_improved: the improved staggered operator, i.e. Eq.5
+ * with the fat links F in place of U plus the three-hop terms
+ *   + eta_mu(x) N_mu(x) chi(x + 3mu) - eta_mu(x - 3mu) N_mu(x - 3mu)^+ chi(x - 3mu)
+ * over the long links N (Sec.4's ensembles use such an action; the fields
+ * are inputs: smearing and the three-link products with their coefficients
+ * are the caller's). F and N are canonical complex128
+ * [t][z][y][x][mu][3][3] arrays without phases, both on the host or both on
+ * the device (links_on_device), copied. Neither needs to be unitary, so
+ * STAG_GAUGE_R12 is rejected (EINVAL); otherwise as stag_gauge_create, with
+ * sixteen hop links per output site. Every solver, operator, serving and
+ * tuning call takes the resulting gauge like any other. */
+int stag_gauge_create_improved(stag_ctx* ctx, const int L[4], const double* F, const double* N,
+                               int links_on_device, int prec_mask, stag_gauge** out);
 int stag_gauge_destroy(stag_gauge* gauge);
 /* Number of sites per parity (Vh = Lx*Ly*Lz*Lt/2) of a gauge's lattice. */
 int stag_gauge_sites(const stag_gauge* gauge, int64_t* vh);
@@ -281,14 +294,17 @@ int stag_solver_config(stag_ctx* ctx, int slots_per_batch, int graph_k, int queu
  * (1, 2 or 4) for stage 1 (D_oe) and stage 2 (D_eo with the m^2 update),
  * nt = non-temporal link loads, swizzle = XCD-aware block order. Every
  * shape computes bit-identical results; only speed differs.
- * stag_tune_get / stag_tune_set: the shape used for (prec, nrhs, vh).
- * stag_tune: time the solver's own iteration kernels (see
- * stag_time_kernels) in every shape on the gauge's actual links and keep
- * the fastest (synchronous; uses a solver workspace for nrhs right-hand
+ * stag_tune_get / stag_tune_set: the shape used for (prec, nrhs, vh) by
+ * gauges of Eq.5's operator, or with STAG_TUNE_IMPROVED or-ed into prec by
+ * gauges of the improved operator. stag_tune: time the solver's own iteration
+ * kernels (see stag_time_kernels) in every shape on the gauge's actual
+ * links and keep the fastest for gauges of its kind (Eq.5 or improved) (synchronous; uses a solver workspace for nrhs right-hand
  * sides, allocated if none is free). best / best_ms may be NULL; best_ms is
  * the time of the two hop stages in milliseconds. Errors: EINVAL, ENOMEM,
  * EDEVICE.
  */
+#define STAG_TUNE_IMPROVED (1 << 8)
+
 typedef struct stag_tune_cfg {
     int S1, S2, nt, swizzle;
 } stag_tune_cfg;

@@ -39,6 +39,7 @@ F64, F32, F16S = 0, 1, 2
 PREC = {"f64": F64, "f32": F32, "f16s": F16S}
 MIXED_CARRY, MIXED_RESTART, MIXED_RELIABLE, MIXED_GROUPWISE = 0, 1, 2, 3
 GAUGE_R12 = 1 << 4
+TUNE_IMPROVED = 1 << 8
 MAX_RHS = 16
 
 STATUS_NAME = {
@@ -112,6 +113,7 @@ def _load():
         "stag_last_error": ([vp], ctypes.c_char_p),
         "stag_memory_used": ([vp, ctypes.POINTER(ctypes.c_size_t)], ip),
         "stag_gauge_create": ([vp, ctypes.POINTER(ctypes.c_int), vp, ip, ip, pp], ip),
+        "stag_gauge_create_improved": ([vp, ctypes.POINTER(ctypes.c_int), vp, vp, ip, ip, pp], ip),
         "stag_gauge_destroy": ([vp], ip),
         "stag_gauge_sites": ([vp, ctypes.POINTER(ctypes.c_int64)], ip),
         "stag_field_create": ([vp, vp, ip, ip, ip, pp], ip),
@@ -215,8 +217,8 @@ class Context:
         except Exception:
             pass
 
-    def gauge(self, L, U, precisions=("f64", "f32"), r12=False) -> "Gauge":
-        return Gauge(self, L, U, precisions, r12)
+    def gauge(self, L, U, precisions=("f64", "f32"), r12=False, long=None) -> "Gauge":
+        return Gauge(self, L, U, precisions, r12, long)
 
     def field(self, gauge, parity=0, prec="f64", nrhs=1) -> "Field":
         return Field(self, gauge, parity, prec, nrhs)
@@ -224,20 +226,32 @@ class Context:
 
 class Gauge:
     """A resident gauge field (stag_gauge_create); r12: 12-parameter F64 / F32
-    copies (SU(3) links only)."""
+    copies (SU(3) links only). With ``long`` (stag_gauge_create_improved) the
+    improved operator: U holds the fat links, ``long`` the long links, both
+    host arrays or both device tensors."""
 
-    def __init__(self, ctx: Context, L, U, precisions=("f64", "f32"), r12=False):
+    def __init__(self, ctx: Context, L, U, precisions=("f64", "f32"), r12=False, long=None):
         L = tuple(int(v) for v in L)
         Lx, Ly, Lz, Lt = L
-        U = _check_c128(U, (Lt, Lz, Ly, Lx, 4, 3, 3), "links")
+        shape = (Lt, Lz, Ly, Lx, 4, 3, 3)
+        U = _check_c128(U, shape, "links")
         mask = GAUGE_R12 if r12 else 0
         for p in precisions:
             mask |= 1 << PREC[p]
         h = ctypes.c_void_p()
         ptr, dev = _ptr(U)
         Lc = (ctypes.c_int * 4)(*L)
-        ctx.check(lib.stag_gauge_create(ctx.h, Lc, ptr, dev, mask, ctypes.byref(h)))
+        if long is None:
+            ctx.check(lib.stag_gauge_create(ctx.h, Lc, ptr, dev, mask, ctypes.byref(h)))
+        else:
+            long = _check_c128(long, shape, "long links")
+            lptr, ldev = _ptr(long)
+            if ldev != dev:
+                raise ValueError("fat and long links must both be on the host or both on the device")
+            ctx.check(lib.stag_gauge_create_improved(ctx.h, Lc, ptr, lptr, dev, mask,
+                                                     ctypes.byref(h)))
         self.ctx, self.h, self.L, self.mask, self.r12 = ctx, h, L, mask, bool(r12)
+        self.improved = long is not None
         self.vh = Lx * Ly * Lz * Lt // 2
 
     def destroy(self):
@@ -332,17 +346,23 @@ def stag_tune(ctx: Context, gauge: Gauge, prec="f32", nrhs=1):
     return cfg.as_dict(), ms.value
 
 
-def stag_tune_get(ctx: Context, prec, nrhs, vh):
+def _tune_prec(prec, improved):
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    return p | (TUNE_IMPROVED if improved else 0)
+
+
+def stag_tune_get(ctx: Context, prec, nrhs, vh, improved=False):
+    """Launch shape for (prec, nrhs, vh) of Eq.5 gauges, or of improved-operator gauges."""
     cfg = TuneCfg()
-    ctx.check(lib.stag_tune_get(ctx.h, PREC[prec] if isinstance(prec, str) else prec, int(nrhs),
-                                int(vh), ctypes.byref(cfg)))
+    ctx.check(lib.stag_tune_get(ctx.h, _tune_prec(prec, improved), int(nrhs), int(vh),
+                                ctypes.byref(cfg)))
     return cfg.as_dict()
 
 
-def stag_tune_set(ctx: Context, prec, nrhs, vh, S1=1, S2=1, nt=1, swizzle=1):
+def stag_tune_set(ctx: Context, prec, nrhs, vh, S1=1, S2=1, nt=1, swizzle=1, improved=False):
     cfg = TuneCfg(S1, S2, nt, swizzle)
-    return ctx.check(lib.stag_tune_set(ctx.h, PREC[prec] if isinstance(prec, str) else prec,
-                                       int(nrhs), int(vh), ctypes.byref(cfg)))
+    return ctx.check(lib.stag_tune_set(ctx.h, _tune_prec(prec, improved), int(nrhs), int(vh),
+                                       ctypes.byref(cfg)))
 
 
 def stag_timing_enable(ctx: Context, on=True):

@@ -30,9 +30,12 @@ CXXFLAGS = [
 
 # (source, object name, extra flags)
 UNITS = [
-    ("hop.hip", "hop_f64.o", ["-DHOP_PREC=0"]),
-    ("hop.hip", "hop_f32.o", ["-DHOP_PREC=1"]),
-    ("hop.hip", "hop_f16s.o", ["-DHOP_PREC=2"]),
+    ("hop.hip", "hop_f64.o", ["-DHOP_PREC=0", "-DHOP_NP=4"]),
+    ("hop.hip", "hop_f32.o", ["-DHOP_PREC=1", "-DHOP_NP=4"]),
+    ("hop.hip", "hop_f16s.o", ["-DHOP_PREC=2", "-DHOP_NP=4"]),
+    ("hop.hip", "hop_f64_improved.o", ["-DHOP_PREC=0", "-DHOP_NP=8"]),
+    ("hop.hip", "hop_f32_improved.o", ["-DHOP_PREC=1", "-DHOP_NP=8"]),
+    ("hop.hip", "hop_f16s_improved.o", ["-DHOP_PREC=2", "-DHOP_NP=8"]),
     ("blas.hip", "blas.o", []),
     ("layout.hip", "layout.o", []),
     ("capi.cpp", "capi.o", []),

@@ -14,6 +14,11 @@ Bytes per stored link matrix / colour vector:
   f64  144 / 48   (12-parameter storage: 96 per link)
   f32   72 / 24   (12-parameter storage: 48 per link)
   f16s  36 (+ one 4-byte scale per site shared by its 8 links) / 16
+
+The improved operator (``improved=True``: fat links plus three-hop long
+links) reads sixteen links per output site and does sixteen hops, so its
+link bytes and D flops double; the vector bytes are unchanged (the extra
+neighbours are again the caches' job).
 """
 
 LINK_BYTES = {"f64": 144, "f32": 72, "f16s": 36}
@@ -28,7 +33,7 @@ FLOPS_PER_SITE_DOT = 12         # Re<x, h> over 3 complex numbers
 
 
 def hop_bytes_per_site(prec: str, stage: int, nrhs: int = 1, lazy: bool = False,
-                       r12: bool = False) -> int:
+                       r12: bool = False, improved: bool = False) -> int:
     """Compulsory bytes per output site of one hop launch.
 
     stage 1 (D_oe, plain output): 8 links + nrhs x (read input + write output)
@@ -37,7 +42,8 @@ def hop_bytes_per_site(prec: str, stage: int, nrhs: int = 1, lazy: bool = False,
     formed in the kernel): stage 1 also reads r; stage 2 also reads r and
     writes the new d.
     """
-    links = 8 * (LINK_BYTES_R12 if r12 else LINK_BYTES)[prec] + SITE_SCALE_BYTES[prec]
+    nlinks = 16 if improved else 8
+    links = nlinks * (LINK_BYTES_R12 if r12 else LINK_BYTES)[prec] + SITE_SCALE_BYTES[prec]
     if stage == 1:
         nvec = 3 if lazy else 2
     else:
@@ -45,13 +51,15 @@ def hop_bytes_per_site(prec: str, stage: int, nrhs: int = 1, lazy: bool = False,
     return links + nrhs * nvec * SPINOR_BYTES[prec]
 
 
-def a_bytes_per_site(prec: str, nrhs: int = 1, r12: bool = False) -> int:
+def a_bytes_per_site(prec: str, nrhs: int = 1, r12: bool = False, improved: bool = False) -> int:
     """One application of A = both stages, per even site."""
-    return hop_bytes_per_site(prec, 1, nrhs, r12=r12) + hop_bytes_per_site(prec, 2, nrhs, r12=r12)
+    return (hop_bytes_per_site(prec, 1, nrhs, r12=r12, improved=improved)
+            + hop_bytes_per_site(prec, 2, nrhs, r12=r12, improved=improved))
 
 
-def a_flops_per_site(nrhs: int = 1) -> int:
-    return nrhs * (2 * FLOPS_PER_SITE_D + FLOPS_PER_SITE_XPAY)
+def a_flops_per_site(nrhs: int = 1, improved: bool = False) -> int:
+    d = 2 * FLOPS_PER_SITE_D if improved else FLOPS_PER_SITE_D
+    return nrhs * (2 * d + FLOPS_PER_SITE_XPAY)
 
 
 def update_bytes_per_site(prec: str, mixed: bool) -> int:
@@ -62,10 +70,11 @@ def update_bytes_per_site(prec: str, mixed: bool) -> int:
     return 2 * SPINOR_BYTES["f32"] + 4 * SPINOR_BYTES[prec]
 
 
-def cg_iteration_bytes_per_site(prec: str, mixed: bool, nrhs: int = 1, r12: bool = False) -> int:
+def cg_iteration_bytes_per_site(prec: str, mixed: bool, nrhs: int = 1, r12: bool = False,
+                                improved: bool = False) -> int:
     """One CG iteration as run (three kernels: lazy stage 1, lazy stage 2, update)."""
-    return (hop_bytes_per_site(prec, 1, nrhs, lazy=True, r12=r12)
-            + hop_bytes_per_site(prec, 2, nrhs, lazy=True, r12=r12)
+    return (hop_bytes_per_site(prec, 1, nrhs, lazy=True, r12=r12, improved=improved)
+            + hop_bytes_per_site(prec, 2, nrhs, lazy=True, r12=r12, improved=improved)
             + nrhs * update_bytes_per_site(prec, mixed))
 
 

@@ -293,15 +293,28 @@ hipError_t issue_kernel(const Issue& is, const void* func, uint32_t grid, uint32
 
 // ------------------------------------------------------------------ hop dispatch
 
-hipError_t launch_hop_p0(int S, int N, int epi, bool nt, const HopArgs& a, const Issue& is);
-hipError_t launch_hop_p1(int S, int N, int epi, bool nt, const HopArgs& a, const Issue& is);
-hipError_t launch_hop_p2(int S, int N, int epi, bool nt, const HopArgs& a, const Issue& is);
+hipError_t launch_hop_p0_n4(int S, int N, int epi, bool nt, const HopArgs& a, const Issue& is);
+hipError_t launch_hop_p1_n4(int S, int N, int epi, bool nt, const HopArgs& a, const Issue& is);
+hipError_t launch_hop_p2_n4(int S, int N, int epi, bool nt, const HopArgs& a, const Issue& is);
+hipError_t launch_hop_p0_n8(int S, int N, int epi, bool nt, const HopArgs& a, const Issue& is);
+hipError_t launch_hop_p1_n8(int S, int N, int epi, bool nt, const HopArgs& a, const Issue& is);
+hipError_t launch_hop_p2_n8(int S, int N, int epi, bool nt, const HopArgs& a, const Issue& is);
 
 hipError_t launch_hop(int prec, int S, int N, int epi, bool nt, const HopArgs& a, const Issue& is) {
+    if (a.npairs == 8) {
+        if (a.r12) return hipErrorInvalidValue;  // long and fat links are stored in full
+        switch (prec) {
+            case P64: return launch_hop_p0_n8(S, N, epi, nt, a, is);
+            case P32: return launch_hop_p1_n8(S, N, epi, nt, a, is);
+            case P16S: return launch_hop_p2_n8(S, N, epi, nt, a, is);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (a.npairs != 4) return hipErrorInvalidValue;
     switch (prec) {
-        case P64: return launch_hop_p0(S, N, epi, nt, a, is);
-        case P32: return launch_hop_p1(S, N, epi, nt, a, is);
-        case P16S: return launch_hop_p2(S, N, epi, nt, a, is);
+        case P64: return launch_hop_p0_n4(S, N, epi, nt, a, is);
+        case P32: return launch_hop_p1_n4(S, N, epi, nt, a, is);
+        case P16S: return launch_hop_p2_n4(S, N, epi, nt, a, is);
         default: return hipErrorInvalidValue;
     }
 }

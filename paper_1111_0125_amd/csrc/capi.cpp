@@ -71,32 +71,34 @@ Geom make_geom(const int L[4]) {
     return g;
 }
 
-static long long tune_key(int prec, int N, uint32_t Vh) {
+static long long tune_key(int prec, int N, uint32_t Vh, int npairs) {
     int bucket = 0;
     while ((1u << bucket) < Vh && bucket < 31) ++bucket;
-    return ((long long)prec << 40) | ((long long)N << 32) | bucket;
+    return ((long long)npairs << 48) | ((long long)prec << 40) | ((long long)N << 32) | bucket;
 }
 
-HopTune get_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh) {
+HopTune get_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh, int npairs) {
     {
         std::lock_guard<std::mutex> lk(ctx->tune_mu);
-        auto it = ctx->tune.find(tune_key(prec, N, Vh));
+        auto it = ctx->tune.find(tune_key(prec, N, Vh, npairs));
         if (it != ctx->tune.end()) return it->second;
     }
     // Default (what the autotuner finds best on most lattices measured, from
-    // 16^3x32 to 32^3x64): one lane per site, non-temporal link loads,
-    // XCD-aware block order.
+    // 16^3x32 to 32^3x64): one lane per site (two for the improved
+    // operator's eight hop pairs: the same four pairs per lane, which keeps
+    // the link registers of one lane within the register file), non-temporal
+    // link loads, XCD-aware block order.
     (void)Vh;
     HopTune t;
-    t.S1 = t.S2 = 1;
+    t.S1 = t.S2 = npairs == 8 ? 2 : 1;
     t.nt = 1;
     t.swizzle = 1;
     return t;
 }
 
-void set_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh, const HopTune& t) {
+void set_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh, int npairs, const HopTune& t) {
     std::lock_guard<std::mutex> lk(ctx->tune_mu);
-    ctx->tune[tune_key(prec, N, Vh)] = t;
+    ctx->tune[tune_key(prec, N, Vh, npairs)] = t;
 }
 
 hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, const HopTune& t,
@@ -119,6 +121,7 @@ hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, con
     a.gauge = g->G[prec][p_out];
     a.gscale = prec == P16S ? g->gscale[p_out] : nullptr;
     a.r12 = g->r12 && prec != P16S;
+    a.npairs = g->npairs;
     a.in = in;
     a.in_rs = in_rs;
     a.out = out;
@@ -252,12 +255,21 @@ static hipStream_t pick_stream(stag_ctx* ctx, void* s) {
     return s ? (hipStream_t)s : ctx->stream;
 }
 
-int stag_gauge_create(stag_ctx* ctx, const int L[4], const double* U, int U_on_device,
-                      int prec_mask, stag_gauge** out) {
+namespace {
+
+// Shared body of stag_gauge_create (Ulong null) and
+// stag_gauge_create_improved (U = fat links, Ulong = long links).
+int gauge_create(stag_ctx* ctx, const int L[4], const double* U, const double* Ulong,
+                 int U_on_device, int prec_mask, stag_gauge** out) {
     if (!ctx) return STAG_EINVAL;
     if (!out || !L || !U)
         return set_error(ctx, STAG_EINVAL, "stag_gauge_create: NULL argument");
     *out = nullptr;
+    if (Ulong && (prec_mask & STAG_GAUGE_R12))
+        return set_error(ctx, STAG_EINVAL,
+                         "stag_gauge_create_improved: fat and long links are stored in full "
+                         "(STAG_GAUGE_R12 needs SU(3) links)");
+    const int npairs = Ulong ? 8 : 4;
     uint64_t V = 1;
     for (int i = 0; i < 4; ++i) {
         if (L[i] < 2 || (L[i] & 1))
@@ -278,27 +290,31 @@ int stag_gauge_create(stag_ctx* ctx, const int L[4], const double* U, int U_on_d
     g->g = make_geom(L);
     g->mask = prec_mask;
     g->r12 = r12;
+    g->npairs = npairs;
     const size_t Vh = g->g.Vh;
     const size_t ubytes = (size_t)V * 4 * 9 * 16;
-    void* Ud = nullptr;
+    void* Ud = nullptr;  // staging of U (and Ulong behind it) for host links
     int rc = STAG_OK;
     auto cleanup = [&]() {
         for (int p = 0; p < 3; ++p)
             for (int q = 0; q < 2; ++q)
-                if (g->G[p][q]) dev_free(ctx, g->G[p][q], link_bytes(p, Vh, r12));
+                if (g->G[p][q]) dev_free(ctx, g->G[p][q], link_bytes(p, Vh, r12, npairs));
         for (int q = 0; q < 2; ++q)
             if (g->gscale[q]) dev_free(ctx, g->gscale[q], Vh * 4);
         delete g;
     };
     if (!U_on_device) {
-        hipError_t e = hipMalloc(&Ud, ubytes);
+        const size_t sbytes = Ulong ? 2 * ubytes : ubytes;
+        hipError_t e = hipMalloc(&Ud, sbytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             cleanup();
             return set_error(ctx, STAG_ENOMEM, "stag_gauge_create: staging hipMalloc(%zu): %s",
-                             ubytes, hipGetErrorString(e));
+                             sbytes, hipGetErrorString(e));
         }
         e = hipMemcpy(Ud, U, ubytes, hipMemcpyHostToDevice);
+        if (e == hipSuccess && Ulong)
+            e = hipMemcpy((char*)Ud + ubytes, Ulong, ubytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             (void)hipFree(Ud);
@@ -307,6 +323,7 @@ int stag_gauge_create(stag_ctx* ctx, const int L[4], const double* U, int U_on_d
         }
     }
     const void* Usrc = U_on_device ? (const void*)U : Ud;
+    const void* Nsrc = !Ulong ? nullptr : U_on_device ? (const void*)Ulong : (const char*)Ud + ubytes;
     if (r12) {
         // the third row is rebuilt from the first two: only valid for SU(3)
         int* bad = nullptr;
@@ -331,13 +348,13 @@ int stag_gauge_create(stag_ctx* ctx, const int L[4], const double* U, int U_on_d
     }
     for (int p = 0; p < 3 && rc == STAG_OK; ++p) {
         if (!(prec_mask & (1 << p))) continue;
-        const size_t gb = link_bytes(p, Vh, r12);
+        const size_t gb = link_bytes(p, Vh, r12, npairs);
         for (int q = 0; q < 2 && rc == STAG_OK; ++q) {
             rc = dev_alloc(ctx, gb, &g->G[p][q]);
             if (rc == STAG_OK && p == P16S) rc = dev_alloc(ctx, Vh * 4, (void**)&g->gscale[q]);
             if (rc == STAG_OK) {
-                hipError_t e =
-                    launch_gauge_pack(p, Usrc, g->G[p][q], g->gscale[q], g->g, q, r12, ctx->stream);
+                hipError_t e = launch_gauge_pack(p, Usrc, Nsrc, g->G[p][q], g->gscale[q], g->g, q,
+                                                 r12, ctx->stream);
                 if (e != hipSuccess) {
                     (void)hipGetLastError();
                     rc = set_error(ctx, STAG_EDEVICE, "gauge pack: %s", hipGetErrorString(e));
@@ -362,6 +379,19 @@ int stag_gauge_create(stag_ctx* ctx, const int L[4], const double* U, int U_on_d
     }
     *out = g;
     return STAG_OK;
+}
+
+}  // namespace
+
+int stag_gauge_create(stag_ctx* ctx, const int L[4], const double* U, int U_on_device,
+                      int prec_mask, stag_gauge** out) {
+    return gauge_create(ctx, L, U, nullptr, U_on_device, prec_mask, out);
+}
+
+int stag_gauge_create_improved(stag_ctx* ctx, const int L[4], const double* F, const double* N,
+                               int links_on_device, int prec_mask, stag_gauge** out) {
+    if (ctx && !N) return set_error(ctx, STAG_EINVAL, "stag_gauge_create_improved: NULL argument");
+    return gauge_create(ctx, L, F, N, links_on_device, prec_mask, out);
 }
 
 int stag_gauge_destroy(stag_gauge* g) {
@@ -392,7 +422,7 @@ int stag_gauge_destroy(stag_gauge* g) {
     const size_t Vh = g->g.Vh;
     for (int p = 0; p < 3; ++p)
         for (int q = 0; q < 2; ++q)
-            if (g->G[p][q]) dev_free(ctx, g->G[p][q], link_bytes(p, Vh, g->r12));
+            if (g->G[p][q]) dev_free(ctx, g->G[p][q], link_bytes(p, Vh, g->r12, g->npairs));
     for (int q = 0; q < 2; ++q)
         if (g->gscale[q]) dev_free(ctx, g->gscale[q], Vh * 4);
     delete g;
@@ -551,7 +581,7 @@ int stag_dslash(stag_ctx* ctx, const stag_gauge* g, const stag_field* in, stag_f
                     break;
                 }
         }
-        HopTune t = get_tune(ctx, in->prec, Nk, g->g.Vh);
+        HopTune t = get_tune(ctx, in->prec, Nk, g->g.Vh, g->npairs);
         const char* ip = (const char*)in->data + (size_t)done * in->rs;
         char* op = (char*)out->data + (size_t)done * out->rs;
         HIPCK(ctx, enqueue_hop(g, in->prec, t.S1, Nk, EPI_PLAIN, t, ip, in->rs, op, out->rs,
@@ -589,7 +619,7 @@ int stag_apply_A(stag_ctx* ctx, const stag_gauge* g, const double* mass, const s
             }
         double m2[kMaxN] = {0};
         for (int r = 0; r < Nk; ++r) m2[r] = mass[done + r] * mass[done + r];
-        HopTune tu = get_tune(ctx, in->prec, Nk, g->g.Vh);
+        HopTune tu = get_tune(ctx, in->prec, Nk, g->g.Vh, g->npairs);
         const char* ip = (const char*)in->data + (size_t)done * in->rs;
         char* tp = (char*)t + (size_t)done * in->rs;
         char* op = (char*)out->data + (size_t)done * out->rs;

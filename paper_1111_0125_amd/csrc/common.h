@@ -88,6 +88,29 @@ __device__ __forceinline__ void neighbours(const Geom& g, uint32_t s, int x, int
     }
 }
 
+// The same for the three-hop neighbours x + 3 mu and x - 3 mu of the
+// improved operator (also on the opposite parity: the hop length is odd).
+// Extents are even and >= 2, so at most two periods are folded.
+__device__ __forceinline__ void neighbours3(const Geom& g, uint32_t s, int x, int y, int z, int t,
+                                            int mu, uint32_t& nf, uint32_t& nb) {
+    const int c = mu == 0 ? x : mu == 1 ? y : mu == 2 ? z : t;
+    const int L = g.L[mu];
+    int cf = c + 3, cb = c - 3;
+    if (cf >= L) cf -= L;
+    if (cf >= L) cf -= L;
+    if (cb < 0) cb += L;
+    if (cb < 0) cb += L;
+    if (mu == 0) {
+        const uint32_t base = s - (uint32_t)(x >> 1);
+        nf = base + (uint32_t)(cf >> 1);
+        nb = base + (uint32_t)(cb >> 1);
+    } else {
+        const int stride = (int)(mu == 1 ? g.sy : mu == 2 ? g.sz : g.st);
+        nf = (uint32_t)((int)s + (cf - c) * stride);
+        nb = (uint32_t)((int)s + (cb - c) * stride);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Field storage (per right-hand side; a field with nrhs > 1 holds nrhs such
 // blocks back to back, each `rhs_bytes` long):
@@ -127,13 +150,23 @@ inline size_t spinor_rhs_bytes(int prec, size_t Vh) {
 // each third row as the conjugated cross product of the first two and apply
 // +eta_mu(x) to the forward and -eta_mu(x) to the backward link
 // (eta_mu(x - mu) = eta_mu(x): the phase depends on the coordinates before mu).
-inline size_t link_bytes(int prec, size_t Vh, bool r12 = false) {
-    if (prec == P64) return Vh * (r12 ? 48 : 72) * 16;
-    if (prec == P32) return Vh * (r12 ? 24 : 36) * 16;
-    return Vh * 36 * 8;
+// ---------------------------------------------------------------------------
+// Improved operator (fat links F in place of U, long links N): eight hop
+// pairs per output site, pairs 0..3 as above from F and pairs 4 + mu the
+// three-hop pair
+// hop 8+2mu  : L = eta_mu(x) N_mu(x)                       applied to chi(x + 3mu)
+// hop 9+2mu  : L = -(eta_mu(x - 3mu) N_mu(x - 3mu))^dagger applied to chi(x - 3mu)
+// in the same word-major layout (P64 144 words, P32 / P16S 72 words; the
+// P16S scale covers all 288 reals). Always the full 18-parameter form:
+// fat and long links are not unitary.
+inline size_t link_bytes(int prec, size_t Vh, bool r12 = false, int npairs = 4) {
+    const size_t k = (size_t)npairs / 4;
+    if (prec == P64) return k * Vh * (r12 ? 48 : 72) * 16;
+    if (prec == P32) return k * Vh * (r12 ? 24 : 36) * 16;
+    return k * Vh * 36 * 8;
 }
-inline size_t gauge_parity_bytes(int prec, size_t Vh, bool r12 = false) {
-    return link_bytes(prec, Vh, r12) + (prec == P16S ? Vh * 4 : 0);
+inline size_t gauge_parity_bytes(int prec, size_t Vh, bool r12 = false, int npairs = 4) {
+    return link_bytes(prec, Vh, r12, npairs) + (prec == P16S ? Vh * 4 : 0);
 }
 
 // ---------------------------------------------------------------------------

@@ -2,19 +2,25 @@
 // folded into the links) applied from one parity to the other, with optional
 // second-stage epilogues that complete A = m^2 - D_eo D_oe (Eq.3).
 //
-// One output site is handled by S lanes of a wavefront (S = 1, 2 or 4); lane
-// j of a site takes the hop pairs mu in [j*4/S, (j+1)*4/S), each pair being a
-// forward and a backward hop whose two 3x3 links are stored contiguously per
-// site. The S partial colour vectors are summed with cross-lane adds. With
-// N > 1 right-hand sides every link is loaded once and applied to all of
-// them (the block operator sharing gauge loads).
+// The operator is a sum over NP hop pairs, each a forward and a backward hop
+// whose two 3x3 links are stored contiguously per site: NP = 4 for Eq.5
+// (pair mu: x +- mu), NP = 8 for the improved operator (pairs 4 + mu add the
+// three-hops x +- 3mu over the long links). One output site is handled by S
+// lanes of a wavefront (S = 1, 2 or 4); lane j of a site takes the pairs
+// [j*NP/S, (j+1)*NP/S), and the S partial colour vectors are summed with
+// cross-lane adds. With N > 1 right-hand sides every link is loaded once and
+// applied to all of them (the block operator sharing gauge loads).
 //
-// This file is compiled once per storage precision (HOP_PREC).
+// This file is compiled once per storage precision (HOP_PREC) and pair
+// count (HOP_NP).
 #include "kern.h"
 #include "launch.h"
 
 #ifndef HOP_PREC
 #error "HOP_PREC must be defined"
+#endif
+#ifndef HOP_NP
+#define HOP_NP 4
 #endif
 
 namespace stag {
@@ -81,8 +87,23 @@ __device__ __forceinline__ void load_operand(const HopArgs& a, const char* in_r,
     combine<P>(a, w, r, n, lazy, beta, true, vr, vi);
 }
 
-template <int P, int S, int N, int EPI, bool NT>
+// Neighbours of hop pair pr (pairs 4..7 are the three-hops of the improved operator).
+template <int NP>
+__device__ __forceinline__ void pair_neighbours(const Geom& g, uint32_t s, int x, int y, int z,
+                                                int t, int pr, uint32_t& nf, uint32_t& nb) {
+    if (NP == 4 || pr < 4) {
+        neighbours(g, s, x, y, z, t, pr & 3, nf, nb);
+    } else {
+        neighbours3(g, s, x, y, z, t, pr & 3, nf, nb);
+    }
+}
+
+template <int P, int S, int N, int EPI, bool NT, int NP>
 __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
+    // NP: hop pairs per site
+    constexpr int B = NP / S;   // pairs per lane
+    constexpr int LOGB = B >= 8 ? 3 : B >= 4 ? 2 : B >= 2 ? 1 : 0;
+    static_assert(B >= 1 && (1 << LOGB) == B, "pairs per lane must be a power of two");
     using T = typename Real<P>::T;
     const uint32_t blk = logical_block(a.swizzle);
     const uint32_t gt = blk * kBlock + threadIdx.x;
@@ -112,9 +133,9 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
             if (!(s1.flags & a.run_mask)) act = 0;
         }
         if (valid && act) {
-            const int mu = j * (4 / S);
-            neighbours(a.g, s, x, y, z, t, mu, nf0, nb0);
-            load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, a.r12, eta_sign(mu, x, y, z), lr0, li0);
+            const int pr = j * B;
+            pair_neighbours<NP>(a.g, s, x, y, z, t, pr, nf0, nb0);
+            load_pair<P, NT>(a.gauge, a.gscale, Vh, s, pr, a.r12, eta_sign(pr & 3, x, y, z), lr0, li0);
             load_raw<P>(a, (const char*)a.in, 0, nf0, lazy_nb, wf0);
             load_raw<P>(a, (const char*)a.in, 0, nb0, lazy_nb, wb0);
         }
@@ -147,21 +168,28 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
     };
 
     T ar[N][3], ai[N][3];
-    [[maybe_unused]] T hr2[N][3], hi2[N][3];  // S = 1: sum of pairs 2 and 3 in progress
+    // pending sums of the lane's pair tree: pd[l] holds the sum of the
+    // 2^l pairs that wait for their right-hand sibling
+    [[maybe_unused]] T pdr[LOGB > 0 ? LOGB : 1][N][3], pdi[LOGB > 0 ? LOGB : 1][N][3];
 #pragma unroll
     for (int r = 0; r < N; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) ar[r][c] = ai[r][c] = hr2[r][c] = hi2[r][c] = T(0);
+        for (int c = 0; c < 3; ++c) {
+            ar[r][c] = ai[r][c] = T(0);
+#pragma unroll
+            for (int l = 0; l < (LOGB > 0 ? LOGB : 1); ++l) pdr[l][r][c] = pdi[l][r][c] = T(0);
+        }
 
     if (valid && act) {
-        // Each hop pair mu contributes p_mu = F_mu chi(x+mu) + B_mu chi(x-mu),
-        // accumulated from zero; the pairs are combined as
-        // (p0 + p1) + (p2 + p3), lane-locally for the pairs this lane owns
-        // and across the S lanes of the site below. This fixes the rounding
-        // independently of S and of the number of right-hand sides.
+        // Each hop pair contributes p = F chi(x+h) + B chi(x-h), accumulated
+        // from zero; the pairs are summed along a balanced binary tree
+        // ((p0 + p1) + (p2 + p3)) + ..., lane-locally over the aligned block
+        // of pairs this lane owns and across the S lanes of the site below.
+        // This fixes the rounding independently of S and of the number of
+        // right-hand sides.
 #pragma unroll
-        for (int k = 0; k < 4 / S; ++k) {
-            const int mu = j * (4 / S) + k;
+        for (int k = 0; k < B; ++k) {
+            const int mu = j * B + k;  // hop pair index
             uint32_t nf, nb;
             T lr[18], li[18];
             if (N == 1 && k == 0) {
@@ -173,8 +201,8 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                     li[e] = li0[e];
                 }
             } else {
-                neighbours(a.g, s, x, y, z, t, mu, nf, nb);
-                load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, a.r12, eta_sign(mu, x, y, z), lr, li);
+                pair_neighbours<NP>(a.g, s, x, y, z, t, mu, nf, nb);
+                load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, a.r12, eta_sign(mu & 3, x, y, z), lr, li);
             }
 #pragma unroll
             for (int r = 0; r < N; ++r) {
@@ -195,50 +223,49 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                 matvec_acc(lr, li, 0, vr, vi, pr, pi);
                 combine<P>(a, wb, r, nb, lazy_nb, be, EPI == EPI_PLAIN, vr, vi);
                 matvec_acc(lr, li, 9, vr, vi, pr, pi);
-                if constexpr (S == 1) {
-                    // k = 0, 2 start a pair sum; k = 1, 3 complete it;
-                    // k = 3 also adds the two pair sums
+                // binary-counter walk of the tree: the new pair sum is
+                // the right sibling of every pending sum at the levels
+                // where k has a 1 bit, and waits at the first 0 bit
+                T cr[3], ci[3];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        if (k == 0) {
-                            ar[r][c] = pr[c];
-                            ai[r][c] = pi[c];
-                        } else if (k == 1) {
-                            ar[r][c] = ar[r][c] + pr[c];
-                            ai[r][c] = ai[r][c] + pi[c];
-                        } else if (k == 2) {
-                            hr2[r][c] = pr[c];
-                            hi2[r][c] = pi[c];
-                        } else {
-                            ar[r][c] = ar[r][c] + (hr2[r][c] + pr[c]);
-                            ai[r][c] = ai[r][c] + (hi2[r][c] + pi[c]);
+                for (int c = 0; c < 3; ++c) {
+                    cr[c] = pr[c];
+                    ci[c] = pi[c];
+                }
+                bool done = false;
+#pragma unroll
+                for (int l = 0; l < LOGB; ++l) {
+                    if (done) continue;
+                    if ((k >> l) & 1) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            cr[c] = pdr[l][r][c] + cr[c];
+                            ci[c] = pdi[l][r][c] + ci[c];
                         }
-                    }
-                } else if constexpr (S == 2) {
+                    } else {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        if (k == 0) {
-                            ar[r][c] = pr[c];
-                            ai[r][c] = pi[c];
-                        } else {
-                            ar[r][c] = ar[r][c] + pr[c];
-                            ai[r][c] = ai[r][c] + pi[c];
+                        for (int c = 0; c < 3; ++c) {
+                            pdr[l][r][c] = cr[c];
+                            pdi[l][r][c] = ci[c];
                         }
+                        done = true;
                     }
-                } else {
+                }
+                if (k == B - 1) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        ar[r][c] = pr[c];
-                        ai[r][c] = pi[c];
+                        ar[r][c] = cr[c];
+                        ai[r][c] = ci[c];
                     }
                 }
             }
         }
     }
     if constexpr (S > 1) {
-        // lanes 2i and 2i + 1 hold consecutive pair sums; xor 1 forms
-        // (p0 + p1) and (p2 + p3), xor 2 adds them. IEEE addition is
-        // commutative, so both lanes of each exchange hold the same value.
+        // lanes 2i and 2i + 1 hold the sums of consecutive aligned blocks;
+        // xor 1 forms the sums of their parent nodes, xor 2 of the next
+        // level. IEEE addition is commutative, so both lanes of each
+        // exchange hold the same value.
 #pragma unroll
         for (int r = 0; r < N; ++r)
 #pragma unroll
@@ -335,7 +362,7 @@ template <int P, int S, int N, int EPI, bool NT>
 static hipError_t run_hop(const HopArgs& a, const Issue& is) {
     HopArgs arg = a;
     void* args[] = {&arg};
-    return issue_kernel(is, reinterpret_cast<const void*>(&k_hop<P, S, N, EPI, NT>),
+    return issue_kernel(is, reinterpret_cast<const void*>(&k_hop<P, S, N, EPI, NT, HOP_NP>),
                         hop_blocks(a.g.Vh, S), kBlock, args);
 }
 
@@ -374,11 +401,11 @@ static hipError_t dispatch_epi(int S, int N, bool nt, const HopArgs& a, const Is
     }
 }
 
-#define HOP_FN_NAME_(p) launch_hop_p##p
-#define HOP_FN_NAME(p) HOP_FN_NAME_(p)
+#define HOP_FN_NAME_(p, np) launch_hop_p##p##_n##np
+#define HOP_FN_NAME(p, np) HOP_FN_NAME_(p, np)
 
-hipError_t HOP_FN_NAME(HOP_PREC)(int S, int N, int epi, bool nt, const HopArgs& a,
-                                  const Issue& is) {
+hipError_t HOP_FN_NAME(HOP_PREC, HOP_NP)(int S, int N, int epi, bool nt, const HopArgs& a,
+                                          const Issue& is) {
     constexpr int P = HOP_PREC;
     switch (epi) {
         case EPI_PLAIN: return dispatch_epi<P, EPI_PLAIN>(S, N, nt, a, is);

@@ -78,6 +78,7 @@ struct stag_gauge {
     void* G[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
     float* gscale[2] = {nullptr, nullptr};  // P16S
     bool r12 = false;                       // P64 / P32 copies in 12-parameter form
+    int npairs = 4;                         // hop pairs per site: 8 for the improved operator
     size_t bytes = 0;
 };
 
@@ -184,8 +185,9 @@ struct DeviceGuard {
 };
 
 Geom make_geom(const int L[4]);
-HopTune get_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh);
-void set_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh, const HopTune& t);
+// Launch shapes per (precision, kernel N, lattice size, hop pairs per site).
+HopTune get_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh, int npairs);
+void set_tune(stag_ctx* ctx, int prec, int N, uint32_t Vh, int npairs, const HopTune& t);
 
 // Engines (solver.cpp)
 int engine_acquire(stag_ctx* ctx, const stag_gauge* g, int prec, int N, stag_engine** out);

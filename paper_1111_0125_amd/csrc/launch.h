@@ -50,6 +50,7 @@ struct HopArgs {
     int p_out;
     int swizzle;
     int r12;               // links in 12-parameter form (P64 / P32)
+    int npairs;            // hop pairs per site: 4 (Eq.5) or 8 (improved operator)
     Geom g;
     Reduce red;            // XPAY_DOT / RESID: where the chunk partials go
     // Reduction finalised at kernel start (fin.partials null: none): every
@@ -111,8 +112,10 @@ hipError_t launch_finalize(int N, const Reduce& R, unsigned run_mask, const Issu
 
 // Layout conversion kernels (canonical complex128 <-> internal storage).
 // r12: 12-parameter layout (P64 / P32 only; P16S is always full).
-hipError_t launch_gauge_pack(int prec, const void* U_dev, void* G, float* gscale, const Geom& g,
-                             int p_out, bool r12, hipStream_t stream);
+// Ulong_dev: long links of the improved operator (U_dev then holds the fat
+// links), or null; never together with r12.
+hipError_t launch_gauge_pack(int prec, const void* U_dev, const void* Ulong_dev, void* G,
+                             float* gscale, const Geom& g, int p_out, bool r12, hipStream_t stream);
 // Sets *bad_dev = 1 when a link is not SU(3) within tol (bad_dev zeroed by the caller).
 hipError_t launch_su3_check(const void* U_dev, uint64_t nlinks, double tol, int* bad_dev,
                             hipStream_t stream);

@@ -2,9 +2,10 @@
 //
 // Gauge packing folds the staggered phases into the links (Sec.2: the phase
 // eta_mu(x) is multiplied into U_mu in advance), builds the eight hop links
-// of every output site (backward links daggered and negated, so the Dirac
-// operator of Eq.5 becomes a plain sum), splits by parity and writes the
-// word-major layout of common.h, rounding to the storage precision.
+// of every output site (sixteen for the improved operator; backward links
+// daggered and negated, so the Dirac operator of Eq.5 becomes a plain sum),
+// splits by parity and writes the word-major layout of common.h, rounding
+// to the storage precision.
 #include "kern.h"
 #include "launch.h"
 
@@ -19,79 +20,102 @@ __device__ __forceinline__ double eta_of(int mu, int x, int y, int z) {
     return (s & 1) ? -1.0 : 1.0;
 }
 
+// Hop pair pr of output site c (pairs 0..3: one-hop over U, pairs 4..7 of
+// the improved operator: three-hop over Ulong): 18 complex in fp64, the
+// forward link eta W(x) then -(eta W(x - h))^dagger.
+__device__ __forceinline__ void hop_pair(const d2v* __restrict__ U, const d2v* __restrict__ Ulong,
+                                         const Geom& g, const int (&c)[4], int pr, double (&lr)[18],
+                                         double (&li)[18]) {
+    const int mu = pr & 3;
+    const int dist = pr < 4 ? 1 : 3;
+    const d2v* W = pr < 4 ? U : Ulong;
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];
+    auto lex_of = [&](const int* q) -> size_t {
+        return (size_t)q[0] + (size_t)Lx * ((size_t)q[1] + (size_t)Ly * ((size_t)q[2] + (size_t)Lz * q[3]));
+    };
+    int b[4] = {c[0], c[1], c[2], c[3]};
+    b[mu] -= dist;
+    while (b[mu] < 0) b[mu] += g.L[mu];
+    const double ef = eta_of(mu, c[0], c[1], c[2]);
+    const double eb = eta_of(mu, b[0], b[1], b[2]);
+    const d2v* uf = W + (lex_of(c) * 4 + mu) * 9;
+    const d2v* ub = W + (lex_of(b) * 4 + mu) * 9;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const d2v f = uf[i * 3 + k];
+            lr[3 * i + k] = ef * f.x;
+            li[3 * i + k] = ef * f.y;
+            // -(eb W)^dagger: entry (i, k) = -eb conj(W[k][i])
+            const d2v v = ub[k * 3 + i];
+            lr[9 + 3 * i + k] = -eb * v.x;
+            li[9 + 3 * i + k] = eb * v.y;
+        }
+}
+
+// Full (18-parameter) packing of every hop pair; Ulong null: Eq.5's four
+// pairs, else the improved operator's eight.
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_gauge_pack(const d2v* __restrict__ U, void* G,
+__global__ __launch_bounds__(kBlock) void k_gauge_pack(const d2v* __restrict__ U,
+                                                       const d2v* __restrict__ Ulong, void* G,
                                                        float* gscale, Geom g, int p_out) {
     const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= g.Vh) return;
     int c[4];
     site_coords(g, s, p_out, c[0], c[1], c[2], c[3]);
-    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];
-    auto lex_of = [&](const int* q) -> size_t {
-        return (size_t)q[0] + (size_t)Lx * ((size_t)q[1] + (size_t)Ly * ((size_t)q[2] + (size_t)Lz * q[3]));
-    };
-    // gather the 8 hop links (72 complex) in fp64
-    double lr[72], li[72];
-    const size_t lex = lex_of(c);
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        int b[4] = {c[0], c[1], c[2], c[3]};
-        b[mu] = (b[mu] == 0) ? g.L[mu] - 1 : b[mu] - 1;
-        const double ef = eta_of(mu, c[0], c[1], c[2]);
-        const double eb = eta_of(mu, b[0], b[1], b[2]);
-        const d2v* uf = U + (lex * 4 + mu) * 9;
-        const d2v* ub = U + (lex_of(b) * 4 + mu) * 9;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const d2v f = uf[i * 3 + k];
-                lr[18 * mu + 3 * i + k] = ef * f.x;
-                li[18 * mu + 3 * i + k] = ef * f.y;
-                // -(eb U)^dagger: entry (i, k) = -eb conj(U[k][i])
-                const d2v v = ub[k * 3 + i];
-                lr[18 * mu + 9 + 3 * i + k] = -eb * v.x;
-                li[18 * mu + 9 + 3 * i + k] = eb * v.y;
-            }
-    }
+    const int np = Ulong ? 8 : 4;
     const size_t Vh = g.Vh;
-    if constexpr (P == P64) {
-        d2v* o = (d2v*)G;
+    double lr[18], li[18];
+    float sc = 0.f;
+    if constexpr (P == P16S) {
+        // one fp32 scale per output site over all the reals it reads
+#pragma unroll 1
+        for (int pr = 0; pr < np; ++pr) {
+            hop_pair(U, Ulong, g, c, pr, lr, li);
 #pragma unroll
-        for (int e = 0; e < 72; ++e) {
-            d2v v;
-            v.x = lr[e];
-            v.y = li[e];
-            o[(size_t)e * Vh + s] = v;
+            for (int e = 0; e < 18; ++e)
+                sc = fmaxf(sc, fmaxf(fabsf((float)lr[e]), fabsf((float)li[e])));
         }
-    } else if constexpr (P == P32) {
-        f4v* o = (f4v*)G;
-#pragma unroll
-        for (int w = 0; w < 36; ++w) {
-            f4v v;
-            v.x = (float)lr[2 * w];
-            v.y = (float)li[2 * w];
-            v.z = (float)lr[2 * w + 1];
-            v.w = (float)li[2 * w + 1];
-            o[(size_t)w * Vh + s] = v;
-        }
-    } else {
-        // one fp32 scale per output site over the 144 reals it reads
-        float sc = 0.f;
-#pragma unroll
-        for (int e = 0; e < 72; ++e) sc = fmaxf(sc, fmaxf(fabsf((float)lr[e]), fabsf((float)li[e])));
         gscale[s] = sc;
-        u2v* o = (u2v*)G;
+    }
+#pragma unroll 1
+    for (int pr = 0; pr < np; ++pr) {
+        hop_pair(U, Ulong, g, c, pr, lr, li);
+        if constexpr (P == P64) {
+            d2v* o = (d2v*)G + (size_t)(18 * pr) * Vh;
 #pragma unroll
-        for (int w = 0; w < 36; ++w) {
-            u2v v;
-            if (sc == 0.f) {
-                v.x = v.y = 0u;
-            } else {
-                v.x = f2h_pair(__fdiv_rn((float)lr[2 * w], sc), __fdiv_rn((float)li[2 * w], sc));
-                v.y = f2h_pair(__fdiv_rn((float)lr[2 * w + 1], sc), __fdiv_rn((float)li[2 * w + 1], sc));
+            for (int e = 0; e < 18; ++e) {
+                d2v v;
+                v.x = lr[e];
+                v.y = li[e];
+                o[(size_t)e * Vh + s] = v;
             }
-            o[(size_t)w * Vh + s] = v;
+        } else if constexpr (P == P32) {
+            f4v* o = (f4v*)G + (size_t)(9 * pr) * Vh;
+#pragma unroll
+            for (int w = 0; w < 9; ++w) {
+                f4v v;
+                v.x = (float)lr[2 * w];
+                v.y = (float)li[2 * w];
+                v.z = (float)lr[2 * w + 1];
+                v.w = (float)li[2 * w + 1];
+                o[(size_t)w * Vh + s] = v;
+            }
+        } else {
+            u2v* o = (u2v*)G + (size_t)(9 * pr) * Vh;
+#pragma unroll
+            for (int w = 0; w < 9; ++w) {
+                u2v v;
+                if (sc == 0.f) {
+                    v.x = v.y = 0u;
+                } else {
+                    v.x = f2h_pair(__fdiv_rn((float)lr[2 * w], sc), __fdiv_rn((float)li[2 * w], sc));
+                    v.y = f2h_pair(__fdiv_rn((float)lr[2 * w + 1], sc),
+                                   __fdiv_rn((float)li[2 * w + 1], sc));
+                }
+                o[(size_t)w * Vh + s] = v;
+            }
         }
     }
 }
@@ -210,8 +234,9 @@ hipError_t launch_su3_check(const void* U_dev, uint64_t nlinks, double tol, int*
     return hipGetLastError();
 }
 
-hipError_t launch_gauge_pack(int prec, const void* U_dev, void* G, float* gscale, const Geom& g,
-                             int p_out, bool r12, hipStream_t st) {
+hipError_t launch_gauge_pack(int prec, const void* U_dev, const void* Ulong_dev, void* G,
+                             float* gscale, const Geom& g, int p_out, bool r12, hipStream_t st) {
+    if (r12 && Ulong_dev) return hipErrorInvalidValue;
     if (r12 && prec != P16S) {
         const dim3 grid((g.Vh + kBlock - 1) / kBlock), block(kBlock);
         const d2v* U = (const d2v*)U_dev;
@@ -223,10 +248,11 @@ hipError_t launch_gauge_pack(int prec, const void* U_dev, void* G, float* gscale
     }
     const dim3 grid((g.Vh + kBlock - 1) / kBlock), block(kBlock);
     const d2v* U = (const d2v*)U_dev;
+    const d2v* N = (const d2v*)Ulong_dev;
     switch (prec) {
-        case P64: hipLaunchKernelGGL((k_gauge_pack<P64>), grid, block, 0, st, U, G, gscale, g, p_out); break;
-        case P32: hipLaunchKernelGGL((k_gauge_pack<P32>), grid, block, 0, st, U, G, gscale, g, p_out); break;
-        case P16S: hipLaunchKernelGGL((k_gauge_pack<P16S>), grid, block, 0, st, U, G, gscale, g, p_out); break;
+        case P64: hipLaunchKernelGGL((k_gauge_pack<P64>), grid, block, 0, st, U, N, G, gscale, g, p_out); break;
+        case P32: hipLaunchKernelGGL((k_gauge_pack<P32>), grid, block, 0, st, U, N, G, gscale, g, p_out); break;
+        case P16S: hipLaunchKernelGGL((k_gauge_pack<P16S>), grid, block, 0, st, U, N, G, gscale, g, p_out); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

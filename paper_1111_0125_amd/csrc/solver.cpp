@@ -132,8 +132,8 @@ int engine_create(stag_ctx* ctx, const stag_gauge* g, int prec, int N, bool serv
         engine_destroy(e);
         return set_error(ctx, STAG_EDEVICE, "solver workspace: init");
     }
-    e->tune_lo = get_tune(ctx, prec, pick_n(N), e->Vh);
-    e->tune_64 = get_tune(ctx, P64, pick_n(N), e->Vh);
+    e->tune_lo = get_tune(ctx, prec, pick_n(N), e->Vh, g->npairs);
+    e->tune_64 = get_tune(ctx, P64, pick_n(N), e->Vh, g->npairs);
     *out = e;
     return STAG_OK;
 }

@@ -104,9 +104,11 @@ int stag_timing_read(stag_ctx* ctx, int kind, int64_t* count, double* total_ms) 
 }
 
 int stag_tune_get(stag_ctx* ctx, int prec, int nrhs, int64_t vh, stag_tune_cfg* out) {
+    const int npairs = (prec & STAG_TUNE_IMPROVED) ? 8 : 4;
+    prec &= ~STAG_TUNE_IMPROVED;
     if (!ctx || !out || prec < 0 || prec > 2 || nrhs < 1 || nrhs > STAG_MAX_RHS || vh <= 0)
         return STAG_EINVAL;
-    HopTune t = get_tune(ctx, prec, pick_n(nrhs), (uint32_t)vh);
+    HopTune t = get_tune(ctx, prec, pick_n(nrhs), (uint32_t)vh, npairs);
     out->S1 = t.S1;
     out->S2 = t.S2;
     out->nt = t.nt;
@@ -120,13 +122,15 @@ static void apply_tune_to_engines(stag_ctx* ctx) {
     std::lock_guard<std::mutex> lk(ctx->mu);
     for (auto* e : ctx->engines) {
         if (e->in_use) continue;
-        e->tune_lo = get_tune(ctx, e->prec, e->N, e->Vh);
-        e->tune_64 = get_tune(ctx, P64, e->N, e->Vh);
+        e->tune_lo = get_tune(ctx, e->prec, e->N, e->Vh, e->gauge->npairs);
+        e->tune_64 = get_tune(ctx, P64, e->N, e->Vh, e->gauge->npairs);
         engine_drop_graphs(e);
     }
 }
 
 int stag_tune_set(stag_ctx* ctx, int prec, int nrhs, int64_t vh, const stag_tune_cfg* cfg) {
+    const int npairs = (prec & STAG_TUNE_IMPROVED) ? 8 : 4;
+    prec &= ~STAG_TUNE_IMPROVED;
     if (!ctx || !cfg || prec < 0 || prec > 2 || nrhs < 1 || nrhs > STAG_MAX_RHS || vh <= 0)
         return STAG_EINVAL;
     if (!valid_S(cfg->S1) || !valid_S(cfg->S2))
@@ -136,7 +140,7 @@ int stag_tune_set(stag_ctx* ctx, int prec, int nrhs, int64_t vh, const stag_tune
     t.S2 = cfg->S2;
     t.nt = cfg->nt ? 1 : 0;
     t.swizzle = cfg->swizzle ? 1 : 0;
-    set_tune(ctx, prec, pick_n(nrhs), (uint32_t)vh, t);
+    set_tune(ctx, prec, pick_n(nrhs), (uint32_t)vh, npairs, t);
     apply_tune_to_engines(ctx);
     return STAG_OK;
 }
@@ -162,8 +166,8 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, stag_tune_
     // The default shape is measured first and kept unless another is at
     // least 5 % faster, so repeated tunings settle on the same shape.
     constexpr double kGain = 0.95;
-    HopTune bestT = get_tune(ctx, prec, N, Vh);
-    bestT.S1 = bestT.S2 = 1;
+    HopTune bestT = get_tune(ctx, prec, N, Vh, g->npairs);
+    bestT.S1 = bestT.S2 = g->npairs == 8 ? 2 : 1;
     bestT.nt = 1;
     bestT.swizzle = 1;
     double us0[3];
@@ -208,7 +212,7 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, stag_tune_
     }
     engine_release(e);
     if (rc) return rc;
-    set_tune(ctx, prec, N, Vh, bestT);
+    set_tune(ctx, prec, N, Vh, g->npairs, bestT);
     apply_tune_to_engines(ctx);
     if (best) {
         best->S1 = bestT.S1;

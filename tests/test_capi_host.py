@@ -38,6 +38,7 @@ def test_null_and_bad_arguments_rejected_on_host():
     assert lib.stag_create(0, 0, None) == s.STAG_EINVAL
     assert lib.stag_destroy(None) == s.STAG_OK
     assert lib.stag_gauge_create(None, None, None, 0, 1, None) == s.STAG_EINVAL
+    assert lib.stag_gauge_create_improved(None, None, None, None, 0, 1, None) == s.STAG_EINVAL
     assert lib.stag_field_create(None, None, 0, 0, 1, None) == s.STAG_EINVAL
     assert lib.stag_field_import(None, None, 0, None) == s.STAG_EINVAL
     assert lib.stag_dslash(None, None, None, None, None) == s.STAG_EINVAL
@@ -80,8 +81,9 @@ int main(void) {
     F(stag_cg_stats, status); F(stag_cg_stats, true_rel_res); F(stag_cg_stats, iter_rel_res);
     F(stag_cg_stats, seconds); F(stag_cg_stats, inner_final);
     F(stag_tune_cfg, S1); F(stag_tune_cfg, S2); F(stag_tune_cfg, nt); F(stag_tune_cfg, swizzle);
-    printf("STAG_GAUGE_R12 %d STAG_MIXED_CARRY %d STAG_MIXED_RESTART %d\n", STAG_GAUGE_R12,
-           STAG_MIXED_CARRY, STAG_MIXED_RESTART);
+    printf("STAG_GAUGE_R12 %d STAG_MIXED_CARRY %d STAG_MIXED_RESTART %d STAG_MIXED_RELIABLE %d "
+           "STAG_MIXED_GROUPWISE %d STAG_TUNE_IMPROVED %d\n", STAG_GAUGE_R12, STAG_MIXED_CARRY,
+           STAG_MIXED_RESTART, STAG_MIXED_RELIABLE, STAG_MIXED_GROUPWISE, STAG_TUNE_IMPROVED);
     return 0;
 }
 """
@@ -123,7 +125,10 @@ def test_binding_structs_match_the_header(tmp_path):
             off, size = fields[f"{cname}.{f}"]
             assert getattr(py, f).offset == off and getattr(py, f).size == size, (cname, f)
     assert consts == {"STAG_GAUGE_R12": s.GAUGE_R12, "STAG_MIXED_CARRY": s.MIXED_CARRY,
-                      "STAG_MIXED_RESTART": s.MIXED_RESTART}
+                      "STAG_MIXED_RESTART": s.MIXED_RESTART,
+                      "STAG_MIXED_RELIABLE": s.MIXED_RELIABLE,
+                      "STAG_MIXED_GROUPWISE": s.MIXED_GROUPWISE,
+                      "STAG_TUNE_IMPROVED": s.TUNE_IMPROVED}
 
 
 def test_param_defaults():
