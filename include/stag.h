@@ -128,9 +128,10 @@ int stag_gauge_create(stag_ctx* ctx, const int L[4], const double* U, int U_on_d
 /* stag_gauge_create_improved: the improved staggered operator, i.e. Eq.5
  * with the fat links F in place of U plus the three-hop terms
  *   + eta_mu(x) N_mu(x) chi(x + 3mu) - eta_mu(x - 3mu) N_mu(x - 3mu)^+ chi(x - 3mu)
- * over the long links N (Sec.4's ensembles use such an action; the fields
- * are inputs: smearing and the three-link products with their coefficients
- * are the caller's). F and N are canonical complex128
+ * over the long links N (Sec.2 sizes its workload on a MILC fine lattice,
+ * an ensemble generated with such an action). The fields are inputs:
+ * smearing and the three-link products with their coefficients are the
+ * caller's. F and N are canonical complex128
  * [t][z][y][x][mu][3][3] arrays without phases, both on the host or both on
  * the device (links_on_device), copied. Neither needs to be unitary, so
  * STAG_GAUGE_R12 is rejected (EINVAL); otherwise as stag_gauge_create, with
