@@ -268,8 +268,9 @@ def batched_c4(stag, torch, synth):
     b = synth.config_rhs(name)
     with stag.Context(0) as ctx:
         g = ctx.gauge(L, U, precisions=("f64", "f32"), r12=True)
-        stag.stag_tune(ctx, g, "f32", n)
-        stag.stag_tune(ctx, g, "f32", 1)
+        # the solver runs 12 right-hand sides as kernels of 8 and 4
+        for k in (8, 4, 1):
+            stag.stag_tune(ctx, g, "f32", k)
         fb = ctx.field(g, 0, "f64", n).load(b)
         fx = ctx.field(g, 0, "f64", n)
         p = stag.cg_params(tol=tol, inner="f32")

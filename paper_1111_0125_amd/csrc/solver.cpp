@@ -383,7 +383,7 @@ hipError_t enqueue_update(const Ctx& c) {
 // One block: K iterations in segments of at most F, each segment followed by
 // the fix-up of the slots it flagged (predicated on the flags: a no-op for
 // the others), so a flagged slot waits at most F iterations.
-hipError_t enqueue_block(const Ctx& c, int K, int F) {
+hipError_t enqueue_block_group(const Ctx& c, int K, int F) {
     const bool mixed = c.e->prec != P64;
     hipError_t err;
     for (int done = 0; done < K; done += F) {
@@ -391,6 +391,65 @@ hipError_t enqueue_block(const Ctx& c, int K, int F) {
         if ((err = mixed ? enqueue_update(c) : enqueue_check(c))) return err;
     }
     return hipSuccess;
+}
+
+// The engine as the kernels of slots [g0, ...) see it: every slot-strided
+// buffer, state and partial array starts at slot g0 (launch shapes for
+// kernels of nk right-hand sides).
+void slot_view(const stag_engine* e, int g0, int nk, stag_engine* v) {
+    v->ctx = e->ctx;
+    v->gauge = e->gauge;
+    v->prec = e->prec;
+    v->N = e->N - g0;
+    v->Vh = e->Vh;
+    v->rs64 = e->rs64;
+    v->rsP = e->rsP;
+    v->rs32 = e->rs32;
+    auto off = [g0](void* p, size_t rs) -> void* {
+        return p ? (void*)((char*)p + (size_t)g0 * rs) : nullptr;
+    };
+    v->x64 = off(e->x64, e->rs64);
+    v->r64 = off(e->r64, e->rs64);
+    v->t64 = off(e->t64, e->rs64);
+    v->d64 = off(e->d64, e->rs64);
+    v->Ad64 = off(e->Ad64, e->rs64);
+    v->b64 = off(e->b64, e->rs64);
+    v->y32 = off(e->y32, e->rs32);
+    v->rs = off(e->rs, e->rsP);
+    v->d = off(e->d, e->rsP);
+    v->t = off(e->t, e->rsP);
+    v->Ad = off(e->Ad, e->rsP);
+    v->st = e->st + g0;
+    v->st1 = e->st1 + g0;
+    const size_t np = num_chunks(e->Vh);
+    v->partials = e->partials + (size_t)g0 * np;
+    v->partials1 = e->partials1 + (size_t)g0 * np;
+    v->tune_lo = get_tune(e->ctx, e->prec, nk, e->Vh, e->gauge->npairs);
+    v->tune_64 = get_tune(e->ctx, P64, nk, e->Vh, e->gauge->npairs);
+}
+
+// Block kernels serve at most this many right-hand sides: per right-hand
+// side an iteration costs less with 8 per kernel than with 12 or 16 (whose
+// neighbour gathers miss the caches more), so larger batches run as groups
+// of 8 (and the rest), each its own chain of kernels.
+constexpr int kMaxGroup = 8;
+
+// One block (K iterations with their fix-ups) for the slots below nk. In a
+// graph the groups are independent branches.
+hipError_t enqueue_block(const Ctx& c, int K, int F) {
+    if (c.nk <= kMaxGroup) return enqueue_block_group(c, K, F);
+    hipError_t err = hipSuccess;
+    for (int g0 = 0; g0 < c.nk && err == hipSuccess; g0 += kMaxGroup) {
+        const int nk = pick_n(std::min(kMaxGroup, c.nk - g0));
+        stag_engine v;
+        slot_view(c.e, g0, nk, &v);
+        Ctx cg = c;
+        cg.e = &v;
+        cg.nk = nk;
+        if (c.is.gb) c.is.gb->last = nullptr;  // a new branch from the graph's start
+        err = enqueue_block_group(cg, K, F);
+    }
+    return err;
 }
 
 }  // namespace
