@@ -169,6 +169,19 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
                 for (int c = 0; c < 3; ++c)
                     acc += (double)u.sr[c] * (double)u.sr[c] + (double)u.si[c] * (double)u.si[c];
                 dv[r] = acc;
+            } else if constexpr (OP == OP_XPAY) {
+                // d = q(r + beta d): the arithmetic of the hop stages' deferred form
+                T rr[3], ri[3], dr[3], di[3];
+                load_site<P>(slot(a, 0, r), Vh, s, rr, ri);
+                load_site<P>(slot(a, 1, r), Vh, s, dr, di);
+                const T be = (T)stv(r).beta;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    dr[c] = fma(be, dr[c], rr[c]);
+                    di[c] = fma(be, di[c], ri[c]);
+                }
+                round_site<P>(dr, di);
+                store_site<P>(slot(a, 1, r), Vh, s, dr, di);
             } else if constexpr (OP == OP_FOLD) {
                 // x64 += y, y = 0
                 double xr[3], xi[3];
@@ -202,6 +215,7 @@ template <int P, int N>
 static hipError_t run_vec_n(int op, const VecArgs& a, const Issue& is) {
     switch (op) {
         case OP_START: return issue_vec<P, N, OP_START>(a, is);
+        case OP_XPAY: return issue_vec<P, N, OP_XPAY>(a, is);
         default: break;
     }
     if constexpr (P == P64) {

@@ -35,7 +35,7 @@ enum KernelKind : int {
     KK_HOP1_64 = 2,   // fp64 hop stage 1 of a true-residual recompute
     KK_HOP2_64 = 3,   // fp64 hop stage 2 of a true-residual recompute
     KK_UPDATE = 4,    // fused axpy + norm
-    KK_XPAY = 5,      // reserved (the direction update is fused into the hop stages)
+    KK_XPAY = 5,      // direction update pass (blocks of several RHS on large lattices)
     KK_OTHER = 6,
     KK_COUNT = 7,
 };

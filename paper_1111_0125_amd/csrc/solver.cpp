@@ -174,6 +174,10 @@ void engine_release(stag_engine* e) {
 // is finalised by a one-block kernel and consumers read the state.
 constexpr size_t kFuseMaxPartials = 2048;
 
+// Sites per parity from which blocks of several right-hand sides run the
+// direction update as its own pass.
+constexpr uint32_t kXpayMinSites = 131072;
+
 bool fuse_finalize(const stag_engine* e, int nk) {
     return (size_t)num_chunks(e->Vh) * (size_t)nk <= kFuseMaxPartials;
 }
@@ -267,6 +271,78 @@ hipError_t vec(const Ctx& c, int prec, int op, std::initializer_list<std::pair<v
 
 constexpr int kKernelsPerIteration = 3;
 
+// Several right-hand sides on a large lattice: the direction update
+// d = q(r + beta d) as a pass of its own before stage 1, which then gathers
+// one field per neighbour and right-hand side instead of two (the gathers,
+// not the compulsory traffic, bound the block hop kernels there); stage 2
+// reads d as stored. Four kernels per iteration, bitwise the same results.
+bool separate_xpay(const stag_engine* e, int nk) {
+    return nk > 1 && e->Vh >= kXpayMinSites;
+}
+
+hipError_t enqueue_iterations_xpay(const Ctx& c, int K) {
+    stag_engine* e = c.e;
+    const bool mixed = e->prec != P64;
+    const int P = e->prec;
+    const int kind_r = mixed ? FIN_MIXED : FIN_CG;
+    void* d = mixed ? e->d : e->d64;
+    void* t = mixed ? e->t : e->t64;
+    void* ad = mixed ? e->Ad : e->Ad64;
+    void* r = mixed ? e->rs : e->r64;
+    const size_t rs = mixed ? e->rsP : e->rs64;
+    const bool fuse = fuse_finalize(e, c.nk);
+    Reduce pend_r = make_red(e, kind_r, e->partials1);
+    pend_r.st = e->st1;
+    pend_r.st_out = e->st;
+    Reduce pend_a = make_red(e, FIN_ALPHA, e->partials);
+    pend_a.st = e->st;
+    pend_a.st_out = e->st1;
+    hipError_t err;
+    for (int k = 0; k < K; ++k) {
+        Opt ox;
+        if (fuse && k > 0) {
+            ox.st = e->st1;
+            ox.fin = &pend_r;
+        }
+        if ((err = timed_launch(c, KK_XPAY, [&]() {
+                 VecArgs a{};
+                 a.f[0] = r;
+                 a.rs[0] = rs;
+                 a.f[1] = d;
+                 a.rs[1] = rs;
+                 a.Vh = e->Vh;
+                 a.st = ox.st ? ox.st : e->st;
+                 a.run_mask = F_ACTIVE;
+                 a.swizzle = e->tune_lo.swizzle;
+                 if (ox.fin) a.fin = *ox.fin;
+                 return launch_vec(P, c.nk, OP_XPAY, a, c.is);
+             })))
+            return err;
+        if ((err = hop(c, P, 1, EPI_PLAIN, d, t, nullptr, FIN_STORE, F_ACTIVE))) return err;
+        Opt o2;
+        o2.finalize = !fuse;
+        if ((err = hop(c, P, 2, EPI_XPAY_DOT, t, ad, d, FIN_ALPHA, F_ACTIVE, nullptr, o2))) return err;
+        Opt ou;
+        if (fuse) {
+            ou.fin = &pend_a;
+            ou.finalize = false;
+            ou.partials = e->partials1;
+        }
+        if (mixed) {
+            err = vec(c, P, OP_UPD_MIXED,
+                      {{e->y32, e->rs32}, {e->rs, e->rsP}, {e->d, e->rsP}, {e->Ad, e->rsP}},
+                      kind_r, F_ACTIVE, ou);
+        } else {
+            err = vec(c, P64, OP_UPD_CG,
+                      {{e->x64, e->rs64}, {e->r64, e->rs64}, {e->d64, e->rs64}, {e->Ad64, e->rs64}},
+                      kind_r, F_ACTIVE, ou);
+        }
+        if (err) return err;
+    }
+    if (!fuse) return hipSuccess;
+    return timed_launch(c, KK_OTHER, [&]() { return launch_finalize(c.nk, pend_r, F_ACTIVE, c.is); });
+}
+
 // K CG iterations (Fig.1; Sec.3.2 for a low-precision inner solve), three
 // kernels each:
 //   stage 1  t = D_oe d, where d = r + beta d (the previous iteration's
@@ -293,6 +369,7 @@ hipError_t enqueue_iterations(const Ctx& c, int K) {
     void* ad = mixed ? e->Ad : e->Ad64;
     void* r = mixed ? e->rs : e->r64;
     const bool fuse = fuse_finalize(e, c.nk);
+    if (separate_xpay(e, c.nk)) return enqueue_iterations_xpay(c, K);
     Reduce pend_r = make_red(e, kind_r, e->partials1);
     pend_r.st = e->st1;
     pend_r.st_out = e->st;
@@ -779,13 +856,20 @@ int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps,
         void* rr = mixed ? e->rs : e->r64;
         void* tt = mixed ? e->t : e->t64;
         void* ad = mixed ? e->Ad : e->Ad64;
+        // blocks on large lattices run the direction update as its own pass
+        // (not timed here): their hop stages read d as stored
+        const bool xp = separate_xpay(e, N);
+        if (which == 0 && xp)
+            return enqueue_hop(g, prec, t.S1, N, EPI_PLAIN, t, dd, rs, tt, rs, 1, nullptr, 0,
+                               nullptr, 0, nullptr, e->st, F_ACTIVE, nullptr, is);
         if (which == 0)
             return enqueue_hop(g, prec, t.S1, N, EPI_PLAIN, t, dd, rs, tt, rs, 1, nullptr,
                                0, nullptr, 0, nullptr, fuse ? e->st1 : e->st, F_ACTIVE, nullptr, is,
                                rr, rs, fuse ? &pend_r : nullptr);
         if (which == 1)
             return enqueue_hop(g, prec, t.S2, N, EPI_XPAY_DOT, t, tt, rs, ad, rs, 0, dd,
-                               rs, nullptr, 0, nullptr, e->st, F_ACTIVE, &red, is, rr, rs);
+                               rs, nullptr, 0, nullptr, e->st, F_ACTIVE, &red, is,
+                               xp ? nullptr : rr, rs);
         VecArgs a{};
         if (mixed) {
             void* f[] = {e->y32, e->rs, e->d, e->Ad};
