@@ -213,6 +213,12 @@ typedef struct stag_cg_params {
                           STAG_MIXED_GROUPWISE folds y into x but never recomputes r and
                           checks the true residual once, when the iterated one has met
                           tol (ENOCONV if the true one misses it). */
+    int small_lattice; /* 1 (default): tiny lattices solve each right-hand side inside
+                          one workgroup, which loops over the iterations itself (no
+                          kernel launch per stage): up to 128 sites per parity (4^4),
+                          and up to 648 (6^4) for calls with several right-hand sides;
+                          plain CG and the CARRY / RESTART mixed variants without use_x0
+                          on Eq.5 gauges. 0: always the kernel-per-stage solver */
 } stag_cg_params;
 
 #define STAG_MIXED_CARRY 0

@@ -79,6 +79,7 @@ class CgParams(ctypes.Structure):
         ("use_x0", ctypes.c_int),
         ("escalate", ctypes.c_int),
         ("mixed_variant", ctypes.c_int),
+        ("small_lattice", ctypes.c_int),
     ]
 
 
@@ -306,7 +307,7 @@ def stag_apply_A(ctx: Context, gauge: Gauge, mass, fin: Field, fout: Field, stre
 
 def cg_params(tol=1e-8, inner="f64", max_iter=0, delta=0.1, stall_iters=0, max_stall=20,
               graph_k=0, use_graph=True, use_x0=False, escalate=True,
-              mixed_variant="carry") -> CgParams:
+              mixed_variant="carry", small_lattice=True) -> CgParams:
     p = CgParams()
     lib.stag_cg_params_default(ctypes.byref(p))
     p.tol = tol
@@ -321,6 +322,7 @@ def cg_params(tol=1e-8, inner="f64", max_iter=0, delta=0.1, stall_iters=0, max_s
     p.escalate = 1 if escalate else 0
     p.mixed_variant = {"carry": MIXED_CARRY, "restart": MIXED_RESTART, "reliable": MIXED_RELIABLE,
                        "groupwise": MIXED_GROUPWISE}[mixed_variant]
+    p.small_lattice = 1 if small_lattice else 0
     return p
 
 

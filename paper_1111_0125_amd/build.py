@@ -38,6 +38,7 @@ UNITS = [
     ("hop.hip", "hop_f16s_improved.o", ["-DHOP_PREC=2", "-DHOP_NP=8"]),
     ("blas.hip", "blas.o", []),
     ("layout.hip", "layout.o", []),
+    ("tiny.hip", "tiny.o", []),
     ("capi.cpp", "capi.o", []),
     ("solver.cpp", "solver.o", []),
     ("serve.cpp", "serve.o", []),

@@ -647,6 +647,7 @@ void stag_cg_params_default(stag_cg_params* p) {
     p->use_x0 = 0;
     p->escalate = 1;
     p->mixed_variant = STAG_MIXED_CARRY;
+    p->small_lattice = 1;
 }
 
 // Stall restarts without a halving of the true residual after which an

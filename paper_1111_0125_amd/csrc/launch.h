@@ -137,6 +137,34 @@ inline int pick_n(int n) {
 
 constexpr int kBlock = 256;  // threads per block of every kernel
 
+// One-workgroup solves of tiny lattices (tiny.hip): one workgroup of
+// kTinyBlock threads per right-hand side runs the whole solve.
+constexpr int kTinyBlock = 512;
+
+struct TinyArgs {
+    const void* G[2];        // inner-precision hop links by output parity
+    const float* gscale[2];  // P16S site scales
+    const void* G64[2];      // fp64 hop links (true residuals)
+    int r12;                 // inner links in 12-parameter form
+    int r12_64;              // fp64 links in 12-parameter form
+    Geom g;
+    // slot-strided buffers (slot = right-hand side = workgroup)
+    const void* b64;
+    void* x64;
+    void* r64;
+    void* t64;
+    void* d;                 // direction, D_oe d, A d, iterated residual: inner precision
+    void* t;                 // (plain CG: the fp64 buffers, rs = r64)
+    void* Ad;
+    void* rs;
+    void* y;                 // fp32 correction (plain CG: x64)
+    size_t rs64, rsP, rsY;
+    RhsState* st;            // [nrhs]: start state in (before FIN_INIT), final state out
+    int cap;                 // loop turns after which the kernel stops whatever the state says
+};
+
+hipError_t launch_tiny(int prec, int nrhs, const TinyArgs& a, hipStream_t stream);
+
 // Reduction partials: one per 64-site chunk, whatever the launch shape.
 inline uint32_t num_chunks(uint32_t Vh) { return (Vh + 63) / 64; }
 

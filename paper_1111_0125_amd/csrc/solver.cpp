@@ -585,25 +585,30 @@ int default_graph_k(uint32_t Vh) { return Vh >= 262144 ? 16 : (Vh >= 32768 ? 32 
 // fp64 and its norm (FIN_X0), then the first direction d = r (rounded to the
 // inner precision, y = 0) and the switch to F_ACTIVE. b = 0 finishes a slot
 // at once (FIN_INIT: F_DONE), a non-finite b with F_BADINPUT.
+// The state of a slot about to start (before FIN_INIT).
+static void start_state(const stag_engine* e, double mass, const stag_cg_params& p, bool x0,
+                        RhsState& s) {
+    const uint64_t n_unknowns = 3ull * e->Vh;
+    std::memset(&s, 0, sizeof(s));
+    s.tol2 = p.tol * p.tol;
+    s.m2 = mass * mass;
+    s.delta = p.delta > 0 ? p.delta : 0.1;
+    // the stall safeguard is for fp16 storage; fp32 runs without it
+    s.stall_iters = p.stall_iters > 0 ? p.stall_iters
+                                      : (e->prec == P16S ? 100 : std::numeric_limits<int>::max());
+    s.max_stall = p.max_stall > 0 ? p.max_stall : 20;
+    s.max_iter = p.max_iter > 0 ? p.max_iter : (int)std::min<uint64_t>(10 * n_unknowns, 1000000);
+    s.flags = F_NEW | (x0 ? F_X0 : 0u);
+    s.variant = p.mixed_variant;
+}
+
 int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots) {
     stag_engine* e = R.e;
     if (slots.empty()) return STAG_OK;
-    const uint64_t n_unknowns = 3ull * e->Vh;
     bool any_x0 = false;
     for (const SlotInit& si : slots) {
         RhsState& s = e->hstage[si.slot];
-        std::memset(&s, 0, sizeof(s));
-        const stag_cg_params& p = si.params;
-        s.tol2 = p.tol * p.tol;
-        s.m2 = si.mass * si.mass;
-        s.delta = p.delta > 0 ? p.delta : 0.1;
-        // the stall safeguard is for fp16 storage; fp32 runs without it
-        s.stall_iters = p.stall_iters > 0 ? p.stall_iters
-                                          : (e->prec == P16S ? 100 : std::numeric_limits<int>::max());
-        s.max_stall = p.max_stall > 0 ? p.max_stall : 20;
-        s.max_iter = p.max_iter > 0 ? p.max_iter : (int)std::min<uint64_t>(10 * n_unknowns, 1000000);
-        s.flags = F_NEW | (si.x0 ? F_X0 : 0u);
-        s.variant = p.mixed_variant;
+        start_state(e, si.mass, si.params, si.x0 != nullptr, s);
         RCK(hipMemcpyAsync(e->st + si.slot, &s, sizeof(RhsState), hipMemcpyHostToDevice, R.s));
         if (si.x0) {
             RCK(hipMemcpyAsync((char*)e->x64 + (size_t)si.slot * e->rs64, si.x0, e->rs64,
@@ -730,12 +735,114 @@ void fill_stats(const RhsState& s, double secs, int inner_prec, stag_cg_stats* o
 
 // ------------------------------------------------------------------ one-shot solve
 
+// Where one workgroup per right-hand side (tiny.hip) beats the kernel-per-
+// stage solver (measured, 1 and 8 RHS): one pass of four lanes per site
+// covers the lattice (128 sites per parity, 4^4: 7.3 against 7.8 ms for a
+// 1e-10 fp64 solve, 5.2 against 7.4 ms fp32, and 3.5-5x with 8 RHS), or a
+// batch of several right-hand sides on up to 648 sites (6^4: 8 RHS in 51
+// against 104 ms fp32, 87 against 104 ms fp64). An iteration costs a few
+// microseconds of barriers and memory round trips whatever the size, so
+// single solves of 6^4 and anything on 8^4 are faster with a kernel per
+// stage.
+constexpr uint32_t kTinySitesOnePass = 128;
+constexpr uint32_t kTinySitesBatch = 648;
+
+static bool tiny_solve_eligible(const stag_engine* e, int n, const stag_cg_params& p) {
+    const bool variant_ok = e->prec == P64 || p.mixed_variant == MIXED_CARRY ||
+                            p.mixed_variant == MIXED_RESTART;
+    const bool size_ok = e->Vh <= kTinySitesOnePass || (n >= 2 && e->Vh <= kTinySitesBatch);
+    return p.small_lattice != 0 && size_ok && e->gauge->npairs == 4 && !p.use_x0 && variant_ok &&
+           !e->ctx->timing.on;
+}
+
+// One-workgroup solves of the n right-hand sides already in e->b64; the final
+// states are copied to fin.
+static int tiny_solve(stag_engine* e, int n, const double* mass, const stag_cg_params& p,
+                      hipStream_t stream, std::vector<RhsState>& fin) {
+    const stag_gauge* g = e->gauge;
+    const int P = e->prec;
+    int max_iter = 0;
+    for (int r = 0; r < n; ++r) {
+        start_state(e, mass[r], p, false, e->hstage[r]);
+        max_iter = std::max(max_iter, e->hstage[r].max_iter);
+    }
+    RCK(hipMemcpyAsync(e->st, e->hstage, sizeof(RhsState) * n, hipMemcpyHostToDevice, stream));
+    TinyArgs a{};
+    for (int q = 0; q < 2; ++q) {
+        a.G[q] = g->G[P][q];
+        a.gscale[q] = P == P16S ? g->gscale[q] : nullptr;
+        a.G64[q] = g->G[P64][q];
+    }
+    a.r12 = g->r12 && P != P16S;
+    a.r12_64 = g->r12;
+    a.g = g->g;
+    a.b64 = e->b64;
+    a.x64 = e->x64;
+    a.r64 = e->r64;
+    a.t64 = e->t64;
+    a.rs64 = e->rs64;
+    if (P == P64) {
+        a.d = e->d64;
+        a.t = e->t64;
+        a.Ad = e->Ad64;
+        a.rs = e->r64;
+        a.y = e->x64;
+        a.rsP = a.rsY = e->rs64;
+    } else {
+        a.d = e->d;
+        a.t = e->t;
+        a.Ad = e->Ad;
+        a.rs = e->rs;
+        a.y = e->y32;
+        a.rsP = e->rsP;
+        a.rsY = e->rs32;
+    }
+    a.st = e->st;
+    // every iteration and every fix-up is one loop turn; the state stops at max_iter
+    a.cap = (int)std::min<long long>(2ll * max_iter + 64, 1ll << 30);
+    RCK(launch_tiny(P, n, a, stream));
+    fin.resize(n);
+    RCK(hipMemcpyAsync(fin.data(), e->st, sizeof(RhsState) * n, hipMemcpyDeviceToHost, stream));
+    RCK(hipStreamSynchronize(stream));
+    return STAG_OK;
+}
+
+// Copy the solutions out (b = 0 gives x = 0 whatever x0 was) and fill the
+// statistics from the final states.
+static int engine_solve_finish(stag_engine* e, int n, void* x_out, size_t x_rs,
+                               stag_cg_stats* stats, hipStream_t stream,
+                               const std::vector<RhsState>& fin,
+                               std::chrono::steady_clock::time_point t0) {
+    RCK(hipMemcpy2DAsync(x_out, x_rs, e->x64, e->rs64, e->rs64, n, hipMemcpyDeviceToDevice, stream));
+    for (int r = 0; r < n; ++r)
+        if (fin[r].bb == 0.0 && fin[r].flags == F_DONE)
+            RCK(hipMemsetAsync((char*)x_out + (size_t)r * x_rs, 0, e->rs64, stream));
+    RCK(hipStreamSynchronize(stream));
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int rc = STAG_OK;
+    for (int r = 0; r < n; ++r) {
+        stag_cg_stats s;
+        fill_stats(fin[r], secs, e->prec, &s);
+        if (stats) stats[r] = s;
+        if (rc == STAG_OK && s.status != STAG_OK) rc = s.status;
+    }
+    if (rc == STAG_EINVAL) set_error(e->ctx, rc, "stag_cg_solve: right-hand side is not finite");
+    return rc;
+}
+
 int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, size_t b_rs,
                  void* x_out, size_t x_rs, const stag_cg_params& p, stag_cg_stats* stats,
                  hipStream_t stream) {
     const auto t0 = std::chrono::steady_clock::now();
     const int K = p.graph_k > 0 ? p.graph_k : default_graph_k(e->Vh);
     RCK(hipMemcpy2DAsync(e->b64, e->rs64, b64, b_rs, e->rs64, n, hipMemcpyDeviceToDevice, stream));
+    std::vector<RhsState> fin(n);
+    if (tiny_solve_eligible(e, n, p)) {
+        int rc = tiny_solve(e, n, mass, p, stream, fin);
+        if (rc) return rc;
+        return engine_solve_finish(e, n, x_out, x_rs, stats, stream, fin, t0);
+    }
     EngineRun R;
     run_init(R, e, stream, e->b64, e->rs64, K, p.use_graph != 0);
     R.variant = e->prec != P64 ? p.mixed_variant : MIXED_CARRY;
@@ -749,7 +856,6 @@ int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, siz
     const long long max_blocks = (2ll * (p.max_iter > 0 ? p.max_iter : 1000000)) / K + 4096;
     rc = run_enqueue_block(R);
     if (rc) return rc;
-    std::vector<RhsState> fin(n);
     for (;;) {
         rc = run_enqueue_block(R);
         if (rc) return rc;
@@ -776,23 +882,8 @@ int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, siz
         RCK(hipMemcpyAsync(fin.data(), e->st, sizeof(RhsState) * n, hipMemcpyDeviceToHost, stream));
     }
     RCK(hipStreamSynchronize(stream));
-    RCK(hipMemcpy2DAsync(x_out, x_rs, e->x64, e->rs64, e->rs64, n, hipMemcpyDeviceToDevice, stream));
-    for (int r = 0; r < n; ++r)  // b = 0 (finished at its start): x = 0 whatever x0 was
-        if (fin[r].bb == 0.0 && fin[r].flags == F_DONE)
-            RCK(hipMemsetAsync((char*)x_out + (size_t)r * x_rs, 0, e->rs64, stream));
-    RCK(hipStreamSynchronize(stream));
     if (R.timed) timing_collect(e->ctx);
-    const double secs =
-        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    rc = STAG_OK;
-    for (int r = 0; r < n; ++r) {
-        stag_cg_stats s;
-        fill_stats(fin[r], secs, e->prec, &s);
-        if (stats) stats[r] = s;
-        if (rc == STAG_OK && s.status != STAG_OK) rc = s.status;
-    }
-    if (rc == STAG_EINVAL) set_error(e->ctx, rc, "stag_cg_solve: right-hand side is not finite");
-    return rc;
+    return engine_solve_finish(e, n, x_out, x_rs, stats, stream, fin, t0);
 }
 
 }  // namespace stag

@@ -76,7 +76,7 @@ int main(void) {
     F(stag_cg_params, tol); F(stag_cg_params, max_iter); F(stag_cg_params, inner_prec);
     F(stag_cg_params, delta); F(stag_cg_params, stall_iters); F(stag_cg_params, max_stall);
     F(stag_cg_params, graph_k); F(stag_cg_params, use_graph); F(stag_cg_params, use_x0);
-    F(stag_cg_params, escalate); F(stag_cg_params, mixed_variant);
+    F(stag_cg_params, escalate); F(stag_cg_params, mixed_variant); F(stag_cg_params, small_lattice);
     F(stag_cg_stats, iters); F(stag_cg_stats, reliable_updates); F(stag_cg_stats, restarts);
     F(stag_cg_stats, status); F(stag_cg_stats, true_rel_res); F(stag_cg_stats, iter_rel_res);
     F(stag_cg_stats, seconds); F(stag_cg_stats, inner_final);
@@ -137,7 +137,7 @@ def test_param_defaults():
     s.lib.stag_cg_params_default(ctypes.byref(p))
     assert (p.tol, p.max_iter, p.inner_prec, p.delta) == (1e-8, 0, s.F64, 0.1)
     assert (p.stall_iters, p.max_stall, p.graph_k, p.use_graph) == (0, 20, 0, 1)
-    assert (p.use_x0, p.escalate, p.mixed_variant) == (0, 1, s.MIXED_CARRY)
+    assert (p.use_x0, p.escalate, p.mixed_variant, p.small_lattice) == (0, 1, s.MIXED_CARRY, 1)
     q = s.cg_params()
     assert (q.stall_iters, q.use_x0, q.escalate, q.mixed_variant) == (0, 0, 1, s.MIXED_CARRY)
     r = s.cg_params(inner="f16s", use_x0=True, mixed_variant="restart", escalate=False)
