@@ -41,8 +41,8 @@ def lib():
         ip = ctypes.POINTER(ctypes.c_int)
         dp = ctypes.c_void_p
         l.oracle_threads.restype = ctypes.c_int
-        l.oracle_dslash.argtypes = [ip, dp, dp, dp, ctypes.c_int]
-        l.oracle_apply_A.argtypes = [ip, dp, ctypes.c_double, dp, dp]
+        l.oracle_dslash.argtypes = [ip, dp, dp, dp, dp, ctypes.c_int]
+        l.oracle_apply_A.argtypes = [ip, dp, dp, ctypes.c_double, dp, dp]
         l.oracle_cg.argtypes = [ip, dp, ctypes.c_double, dp, dp, ctypes.c_double,
                                 ctypes.c_long, ctypes.POINTER(ctypes.c_long),
                                 ctypes.POINTER(ctypes.c_double)]
@@ -63,21 +63,27 @@ def threads() -> int:
     return int(lib().oracle_threads())
 
 
-def dslash(U, v, L, p_in):
+def dslash(U, v, L, p_in, Ulong=None):
+    """D of Eq.5 (Ulong: the improved operator, U = fat links)."""
     U = _c128(U)
     v = _c128(v)
+    N = None if Ulong is None else _c128(Ulong)
     out = np.empty_like(v)
-    rc = lib().oracle_dslash(_L(L), U.ctypes.data, v.ctypes.data, out.ctypes.data, int(p_in))
+    rc = lib().oracle_dslash(_L(L), U.ctypes.data, None if N is None else N.ctypes.data,
+                             v.ctypes.data, out.ctypes.data, int(p_in))
     if rc:
         raise ValueError(f"oracle_dslash failed ({rc})")
     return out
 
 
-def apply_A(U, v, L, m):
+def apply_A(U, v, L, m, Ulong=None):
+    """A = m^2 - D_eo D_oe on even vectors (Ulong: the improved operator)."""
     U = _c128(U)
     v = _c128(v)
+    N = None if Ulong is None else _c128(Ulong)
     out = np.empty_like(v)
-    rc = lib().oracle_apply_A(_L(L), U.ctypes.data, float(m), v.ctypes.data, out.ctypes.data)
+    rc = lib().oracle_apply_A(_L(L), U.ctypes.data, None if N is None else N.ctypes.data,
+                              float(m), v.ctypes.data, out.ctypes.data)
     if rc:
         raise ValueError(f"oracle_apply_A failed ({rc})")
     return out

@@ -12,6 +12,9 @@
  *         with eta_mu(x) = (-1)^(x_0+...+x_{mu-1}) multiplied into the links
  *         (Sec.2), periodic boundaries;
  *   Eq.3  A = -D^2 + m^2 on the even sites, i.e. A chi = m^2 chi - D_eo D_oe chi;
+ *   the improved operator: Eq.5 over fat links plus the three-hop terms
+ *         eta_mu(x) N_mu(x) chi(x+3mu) - eta_mu(x-3mu) N_mu(x-3mu)^+ chi(x-3mu)
+ *         over caller-supplied long links N;
  *   Fig.1 conjugate gradient in fp64, stopping on |r| <= tol |b|, then a
  *         true-residual check that restarts from r = b - A x if it fails.
  *
@@ -67,8 +70,32 @@ static double eta_of(int mu, const int c[4]) {
 
 static const cplx* link_at(const cplx* U, long lex, int mu) { return U + (lex * 4 + mu) * 9; }
 
-/* out (parity 1 - p_in) = D in (parity p_in) */
-static void dslash(const lat_t* lt, const cplx* U, const cplx* in, cplx* out, int p_in) {
+/* acc += eta W(x) in(x + dist mu) - eta W(x - dist mu)^+ in(x - dist mu) */
+static void add_hops(const lat_t* lt, const cplx* W, const cplx* in, const int c[4], int mu,
+                     int dist, cplx acc[3]) {
+    int f[4] = {c[0], c[1], c[2], c[3]};
+    int b[4] = {c[0], c[1], c[2], c[3]};
+    f[mu] = (f[mu] + dist) % lt->L[mu];
+    b[mu] = ((b[mu] - dist) % lt->L[mu] + lt->L[mu]) % lt->L[mu];
+    long lf = lex_of(lt, f), lb = lex_of(lt, b);
+    const cplx* uf = link_at(W, lex_of(lt, c), mu);
+    const cplx* ub = link_at(W, lb, mu);
+    const cplx* vf = in + (lf / 2) * 3;
+    const cplx* vb = in + (lb / 2) * 3;
+    double ef = eta_of(mu, c), eb = eta_of(mu, b);
+    for (int a = 0; a < 3; ++a) {
+        cplx sf = 0, sb = 0;
+        for (int k = 0; k < 3; ++k) {
+            sf += uf[a * 3 + k] * vf[k];
+            sb += conj(ub[k * 3 + a]) * vb[k];
+        }
+        acc[a] += ef * sf - eb * sb;
+    }
+}
+
+/* out (parity 1 - p_in) = D in (parity p_in); N (long links) may be NULL */
+static void dslash(const lat_t* lt, const cplx* U, const cplx* N, const cplx* in, cplx* out,
+                   int p_in) {
     int p_out = 1 - p_in;
 #pragma omp parallel for schedule(static)
     for (long s = 0; s < lt->Vh; ++s) {
@@ -76,32 +103,17 @@ static void dslash(const lat_t* lt, const cplx* U, const cplx* in, cplx* out, in
         coords_of(lt, s, p_out, c);
         cplx acc[3] = {0, 0, 0};
         for (int mu = 0; mu < 4; ++mu) {
-            int f[4] = {c[0], c[1], c[2], c[3]};
-            int b[4] = {c[0], c[1], c[2], c[3]};
-            f[mu] = (f[mu] + 1) % lt->L[mu];
-            b[mu] = (b[mu] + lt->L[mu] - 1) % lt->L[mu];
-            long lf = lex_of(lt, f), lb = lex_of(lt, b);
-            const cplx* uf = link_at(U, lex_of(lt, c), mu);
-            const cplx* ub = link_at(U, lb, mu);
-            const cplx* vf = in + (lf / 2) * 3;
-            const cplx* vb = in + (lb / 2) * 3;
-            double ef = eta_of(mu, c), eb = eta_of(mu, b);
-            for (int a = 0; a < 3; ++a) {
-                cplx sf = 0, sb = 0;
-                for (int k = 0; k < 3; ++k) {
-                    sf += uf[a * 3 + k] * vf[k];
-                    sb += conj(ub[k * 3 + a]) * vb[k];
-                }
-                acc[a] += ef * sf - eb * sb;
-            }
+            add_hops(lt, U, in, c, mu, 1, acc);
+            if (N) add_hops(lt, N, in, c, mu, 3, acc);
         }
         for (int a = 0; a < 3; ++a) out[s * 3 + a] = acc[a];
     }
 }
 
-static void apply_A(const lat_t* lt, const cplx* U, double m, const cplx* in, cplx* out, cplx* tmp) {
-    dslash(lt, U, in, tmp, 0);
-    dslash(lt, U, tmp, out, 1);
+static void apply_A(const lat_t* lt, const cplx* U, const cplx* N, double m, const cplx* in,
+                    cplx* out, cplx* tmp) {
+    dslash(lt, U, N, in, tmp, 0);
+    dslash(lt, U, N, tmp, out, 1);
     long n = lt->Vh * 3;
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) out[i] = m * m * in[i] - out[i];
@@ -122,19 +134,22 @@ int oracle_threads(void) {
 #endif
 }
 
-int oracle_dslash(const int* L, const double* U, const double* in, double* out, int p_in) {
+/* N: long links of the improved operator, or NULL for Eq.5 */
+int oracle_dslash(const int* L, const double* U, const double* N, const double* in, double* out,
+                  int p_in) {
     lat_t lt;
     if (lat_init(&lt, L) || (p_in != 0 && p_in != 1)) return -1;
-    dslash(&lt, (const cplx*)U, (const cplx*)in, (cplx*)out, p_in);
+    dslash(&lt, (const cplx*)U, (const cplx*)N, (const cplx*)in, (cplx*)out, p_in);
     return 0;
 }
 
-int oracle_apply_A(const int* L, const double* U, double m, const double* in, double* out) {
+int oracle_apply_A(const int* L, const double* U, const double* N, double m, const double* in,
+                   double* out) {
     lat_t lt;
     if (lat_init(&lt, L)) return -1;
     cplx* tmp = malloc(sizeof(cplx) * lt.Vh * 3);
     if (!tmp) return -2;
-    apply_A(&lt, (const cplx*)U, m, (const cplx*)in, (cplx*)out, tmp);
+    apply_A(&lt, (const cplx*)U, (const cplx*)N, m, (const cplx*)in, (cplx*)out, tmp);
     free(tmp);
     return 0;
 }
@@ -174,7 +189,7 @@ int oracle_cg(const int* L, const double* U_, double m, const double* b_, double
         double delta_new = bb;
         for (;;) {
             while (i < max_iter && delta_new > stop) {
-                apply_A(&lt, U, m, d, q, tmp);
+                apply_A(&lt, U, NULL, m, d, q, tmp);
                 double dq = dot_re(d, q, n);
                 if (!(dq > 0.0) || !isfinite(dq)) { status = 2; break; }
                 double alpha = delta_new / dq;
@@ -190,7 +205,7 @@ int oracle_cg(const int* L, const double* U_, double m, const double* b_, double
                 for (long k = 0; k < n; ++k) d[k] = r[k] + beta * d[k];
                 ++i;
             }
-            apply_A(&lt, U, m, x, q, tmp);
+            apply_A(&lt, U, NULL, m, x, q, tmp);
 #pragma omp parallel for schedule(static)
             for (long k = 0; k < n; ++k) tmp[k] = b[k] - q[k];
             true_rr = dot_re(tmp, tmp, n);

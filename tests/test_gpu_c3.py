@@ -48,3 +48,27 @@ def test_c3_solve_true_residual(stag, problem, inner):
     assert res <= tol
     # the library's own fp64 residual agrees with the oracle's
     assert abs(st[0]["true_rel_res"] - res) <= 0.05 * res + 1e-14
+
+
+@pytest.mark.parametrize("inner", ["f32", "f64"])
+def test_c3_improved_solve_true_residual(stag, problem, inner):
+    """The improved operator on the same 32^3 x 64 Haar links (fat = 9/8 U +
+    0.05 complex normal noise, long = -1/24 U U U), m = 0.01, 1e-10, as the
+    benchmark runs it: the answer checked with the C oracle's fp64 A."""
+    cfg, U, b = problem
+    L, m, tol = cfg["L"], 0.01, 1e-10
+    fat, lng = synth.naik_links(U, fat_noise=0.05, seed=cfg["gauge_seed"] + 100)
+    with stag.Context(0) as ctx:
+        g = ctx.gauge(L, fat, precisions=("f64", "f32"), long=lng)
+        fb = ctx.field(g, 0, "f64", 1).load(b)
+        fx = ctx.field(g, 0, "f64", 1)
+        rc, st = stag.stag_cg_solve(ctx, g, [m], fb, fx, stag.cg_params(tol=tol, inner=inner))
+        log("improved", inner, rc, st[0])
+        assert rc == 0, st
+        x = fx.store()
+    from oracle import c as oc
+    r = b[0] - oc.apply_A(fat, x[0], L, m, Ulong=lng)
+    res = math.sqrt(ostag.norm2(r) / ostag.norm2(b[0]))
+    log(inner, "true residual (oracle A)", res)
+    assert res <= tol
+    assert abs(st[0]["true_rel_res"] - res) <= 0.05 * res + 1e-14

@@ -365,6 +365,18 @@ def test_c_oracle_matches_numpy(L):
         assert rel(oc.dslash(U, v, L, p), stag.dslash(U, v, L, p)) < 1e-13
 
 
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 2, 4, 2), (4, 6, 2, 8)])
+def test_c_oracle_improved_matches_numpy(L):
+    from oracle import c as oc
+    fat = synth.gaussian_links(L, 301)
+    lng = synth.gaussian_links(L, 302)
+    v = synth.gaussian_rhs(L, 1, 303)[0]
+    assert rel(oc.apply_A(fat, v, L, 0.05, Ulong=lng),
+               stag.apply_A(fat, v, L, 0.05, Ulong=lng)) < 1e-13
+    for p in (0, 1):
+        assert rel(oc.dslash(fat, v, L, p, Ulong=lng), stag.dslash(fat, v, L, p, Ulong=lng)) < 1e-13
+
+
 def test_c_oracle_cg():
     from oracle import c as oc
     L, m, tol = (4, 4, 4, 4), 0.1, 1e-10
