@@ -102,7 +102,7 @@ def c3_inputs(synth):
     return synth.config_links(name), synth.config_rhs(name)
 
 
-def improved_32(stag, torch, costs, synth, reps=30):
+def improved_32(stag, torch, costs, synth, reps=30, solves=True):
     """The improved operator (fat links + three-hop long links) on 32^3 x 64:
     fields from the Haar links of the 32^3 x 64 workload (fat = 9/8 U plus
     0.05 complex normal noise, long = -1/24 U U U), A-apply bandwidth per
@@ -148,7 +148,7 @@ def improved_32(stag, torch, costs, synth, reps=30):
             fo.destroy()
         fb = ctx.field(g, 0, "f64", 1).load(b)
         fx = ctx.field(g, 0, "f64", 1)
-        for inner in ("f32", "f64"):
+        for inner in (("f32", "f64") if solves else ()):
             p = stag.cg_params(tol=tol, inner=inner)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -161,7 +161,7 @@ def improved_32(stag, torch, costs, synth, reps=30):
                                      "true_rel_res": s0["true_rel_res"],
                                      "us_per_iteration": round(dt * 1e6 / max(s0["iters"], 1), 2)}
             log("improved solve", inner, out["solve_" + inner])
-    if out["solve_f64"]["status"] == 0 and out["solve_f32"]["status"] == 0:
+    if solves and out["solve_f64"]["status"] == 0 and out["solve_f32"]["status"] == 0:
         out["speedup_f32_vs_f64"] = round(out["solve_f64"]["time_to_tol_s"] /
                                           out["solve_f32"]["time_to_tol_s"], 3)
     return out
@@ -408,6 +408,10 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only tune and launch the iteration kernels (as timed for the roofline), "
                          "then a 256 MiB copy kernel: the program that hardware-counter runs profile")
+    ap.add_argument("--a-apply-only", action="store_true",
+                    help="only the 32^3x64 A applications (Eq.5 full and 12-parameter links, and "
+                         "the improved operator), autotuned: the program the A-apply kernel "
+                         "profiles trace")
     ap.add_argument("--full-links", action="store_true",
                     help="store the gauge copies in full (18 reals per link) instead of 12 parameters")
     args = ap.parse_args()
@@ -423,6 +427,13 @@ def main():
     import paper_1111_0125_amd as stag
     import synth
     from paper_1111_0125_amd import costs
+
+    if args.a_apply_only:
+        torch.cuda.init()
+        out = {"a_apply_32x32x32x64": a_apply_bandwidth(stag, torch, costs, synth),
+               "improved_32x32x32x64": improved_32(stag, torch, costs, synth, solves=False)}
+        print(json.dumps(out), flush=True)
+        return
 
     cfg = synth.CONFIGS[WORKLOAD]
     L, mass, tol = cfg["L"], cfg["mass"], cfg["tol"]
