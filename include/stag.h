@@ -16,6 +16,10 @@
  *                    iterations, fp64 reliable and group-wise updates, the
  *                    search direction carried over across updates, all inner
  *                    products in fp64.
+ *   Improved operator (stag_gauge_create_improved): Eq.5 over fat links plus
+ *                    the three-hop terms over long links, the action of the
+ *                    MILC ensembles Sec.2 sizes its workload on; every call
+ *                    below computes with it when given such a gauge.
  *
  * Conventions (fixed by this library; the paper does not state them):
  *   - Lattice extents L = {Lx, Ly, Lz, Lt}, each even and >= 2, periodic.
@@ -164,7 +168,8 @@ int stag_field_destroy(stag_field* f);
 
 /* ---------------------------------------------------------------- operators
  * stag_dslash (Sec.2, Eq.5): out = D in, from parity p of `in` to parity
- * 1 - p of `out`, for every right-hand side. `in` and `out` must be distinct
+ * 1 - p of `out`, for every right-hand side (the improved D for a gauge of
+ * stag_gauge_create_improved). `in` and `out` must be distinct
  * fields of the same gauge, precision and nrhs; the gauge must hold that
  * precision. F32 / F16S compute in fp32. Asynchronous on `stream`.
  * Errors: EINVAL, EDEVICE.
