@@ -62,6 +62,24 @@ def a_flops_per_site(nrhs: int = 1, improved: bool = False) -> int:
     return nrhs * (2 * d + FLOPS_PER_SITE_XPAY)
 
 
+REAL_BYTES = {"f64": 8, "f32": 4, "f16s": 2}
+
+
+def paper_d_bytes_per_site(prec: str = "f64", r12: bool = False, improved: bool = False) -> int:
+    """Bytes of one D at one site in the paper's convention (Sec.2, after
+    Eq.5: 1584 in fp64): every link and every neighbour vector read with no
+    reuse, one output vector written; 18 reals per link (12 stored with
+    12-parameter links), 6 per colour vector."""
+    nhops = 16 if improved else 8
+    reals = nhops * (12 if r12 else 18) + nhops * 6 + 6
+    return reals * REAL_BYTES[prec]
+
+
+def paper_a_bytes_per_site(prec: str = "f64", r12: bool = False, improved: bool = False) -> int:
+    """One A (two D) per even site in the paper's convention."""
+    return 2 * paper_d_bytes_per_site(prec, r12, improved)
+
+
 def update_bytes_per_site(prec: str, mixed: bool) -> int:
     """Fused update: fp64 CG reads x, r, d, Ad and writes x, r; mixed reads
     y (fp32), rs, d, Ad and writes y, rs."""

@@ -346,6 +346,8 @@ def test_paper_cost_model_golden():
     g = json.load(open(os.path.join(GOLDEN, "paper_cost_model.json")))
     reals = 8 * 18 + 8 * 6 + 6
     assert reals * 8 == g["bytes_per_site_D_fp64"]
+    from paper_1111_0125_amd import costs
+    assert costs.paper_d_bytes_per_site("f64") == g["bytes_per_site_D_fp64"]
     assert 8 * 9 * 8 == g["flops_per_site_D"]
     Lx, Ly, Lz, Lt = g["lattice"]
     ve = Lx * Ly * Lz * Lt // 2
