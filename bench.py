@@ -182,6 +182,25 @@ def timed_solves(stag, torch, ctx, g, mass, fb, fx, params, k):
     return (time.perf_counter() - t0) / k, last
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
+    """GB/s of a plain elementwise read-and-write kernel (torch.mul, nbytes
+    each way): the streaming rate this chip reaches in practice, for scale."""
+    x = torch.ones(nbytes // 4, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 2.0, out=y)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.mul(x, 2.0, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes / (e0.elapsed_time(e1) * 1e-3 / reps) / 1e9
+    del x, y
+    return round(gbs, 1)
+
+
 def a_apply_bandwidth(stag, torch, costs, synth, reps=50):
     """GB/s of A = both hop stages on the 32^3 x 64 lattice, per precision,
     full and 12-parameter links, timed with torch events on the stream the
@@ -388,8 +407,15 @@ def cpu_baseline(synth, L, U, b, mass, gpu_fp64_iters, target_s):
     oc.cg_fixed(U, b, L, mass, n)
     per_iter = (time.perf_counter() - t0) / n
     solve_s = per_iter * gpu_fp64_iters
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": 1.0 / solve_s, "unit": "solves/s", "cores": oc.threads(), "kind": "oracle",
+        "host_cpus": os.cpu_count(), "cpu_model": model,
         "sample": (f"{n} Fig.1 fp64 CG iterations of the C+OpenMP oracle on the same 16^3x32 "
                    f"system, scaled to the {gpu_fp64_iters} iterations a full 1e-8 fp64 solve "
                    f"takes ({per_iter * 1e3:.2f} ms/iteration)"),
@@ -436,7 +462,8 @@ def main():
     if args.a_apply_only:
         torch.cuda.init()
         out = {"a_apply_32x32x32x64": a_apply_bandwidth(stag, torch, costs, synth),
-               "improved_32x32x32x64": improved_32(stag, torch, costs, synth, solves=False)}
+               "improved_32x32x32x64": improved_32(stag, torch, costs, synth, solves=False),
+               "copy_kernel_GB/s": copy_bandwidth(torch)}
         print(json.dumps(out), flush=True)
         return
 
@@ -578,6 +605,11 @@ def main():
 
     if not args.no_extras:
         result["a_apply_32x32x32x64"] = a_apply_bandwidth(stag, torch, costs, synth)
+        # for scale: what a plain streaming kernel reaches (1 GiB each way)
+        cb = copy_bandwidth(torch)
+        result["copy_kernel_GB/s"] = cb
+        for v in result["a_apply_32x32x32x64"].values():
+            v["frac_of_copy_kernel"] = round(v["GB/s"] / cb, 4)
         result["c3_32x32x32x64_solves"] = c3_solves(stag, torch, synth, costs)
         result["improved_32x32x32x64"] = improved_32(stag, torch, costs, synth)
         c3_inputs.cache_clear()
