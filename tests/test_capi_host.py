@@ -142,3 +142,15 @@ def test_param_defaults():
     assert (q.stall_iters, q.use_x0, q.escalate, q.mixed_variant) == (0, 0, 1, s.MIXED_CARRY)
     r = s.cg_params(inner="f16s", use_x0=True, mixed_variant="restart", escalate=False)
     assert (r.inner_prec, r.use_x0, r.mixed_variant, r.escalate) == (s.F16S, 1, s.MIXED_RESTART, 0)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """One lattice per GPU on a single GPU: --gpus N > 1 exits with a message
+    before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "single GPU" in r.stderr
+    assert r.stdout == ""
