@@ -436,6 +436,8 @@ def main():
     ap.add_argument("--serve-full", action="store_true",
                     help="serving stream over all four lattice sizes (long)")
     ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="request arrival rate per second (default: 50 light, 2 full)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only tune and launch the iteration kernels (as timed for the roofline), "
                          "then a 256 MiB copy kernel: the program that hardware-counter runs profile")
@@ -615,7 +617,7 @@ def main():
         c3_inputs.cache_clear()
         result["batched_24x24x24x48_12rhs"] = batched_c4(stag, torch, synth)
         result["serving"] = serving(stag, synth, n_requests=args.serve_requests,
-                                    full=args.serve_full)
+                                    rate=args.serve_rate or None, full=args.serve_full)
 
     if not args.no_cpu:
         if fp64_iters is None:
