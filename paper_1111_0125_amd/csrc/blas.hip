@@ -49,20 +49,19 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
     const bool valid = s < Vh;
     // Per-RHS state, finalised here from the previous reduction's partials
     // when a.fin is set. One RHS: each wavefront keeps it in registers (no
-    // barrier) and an update requests its operands before alpha is summed.
-    // Several RHS: the block shares one copy in LDS.
+    // barrier) and an update requests its operands and the partials before
+    // the state is known (an inactive slot discards them). Several RHS: the
+    // block shares one copy in LDS.
     constexpr bool UPD = OP == OP_UPD_CG || OP == OP_UPD_MIXED;
     __shared__ RhsState ls[N];
     RhsState s1{};
     unsigned act = (1u << N) - 1u;
     [[maybe_unused]] UpdOps<P, OP> u0;
     if constexpr (N == 1) {
-        if (a.st) {
-            s1 = *a.st;
-            if (!(s1.flags & a.run_mask)) act = 0;
-        }
+        s1 = *(a.st ? a.st : &kNoState);
+        if (a.st && !(s1.flags & a.run_mask)) act = 0;
         if constexpr (UPD) {
-            if (valid && act) load_upd<P, OP>(a, 0, s, u0);
+            if (valid) load_upd<P, OP>(a, 0, s, u0);
         }
         if (a.st && a.fin.partials) {
             // always: block 0 must pass the state on even when it is inactive

@@ -116,28 +116,40 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
 
     // Per-RHS state, finalised here from the previous reduction's partials
     // when a.fin is set. One RHS: each wavefront keeps it in registers (no
-    // barrier), and the operands of the first hop pair are requested before
-    // the partials are summed, so the two memory latencies overlap. Several
-    // RHS: the block shares one copy in LDS.
+    // barrier); the state, the operands of the lane's hop pairs (all of them
+    // when they fit in registers, else the first), the own-site operand of
+    // the second stage and the partials are all requested before any of them
+    // is used, so their memory latencies overlap (an inactive slot reads the
+    // operands and discards them). Neighbours go before links: rebuilding
+    // 12-parameter links waits for the link loads, and would hold back loads
+    // issued after them. Several RHS: the block shares one copy in LDS.
+    constexpr bool PRE = N == 1 && P != P16S && B * sizeof(T) <= 8;
+    constexpr int PB = N == 1 ? (PRE ? B : 1) : 1;  // pairs requested up front
     __shared__ RhsState ls[N];
     RhsState s1{};
     unsigned act = (1u << N) - 1u;
     int x = 0, y = 0, z = 0, t = 0;
     if (valid) site_coords(a.g, s, a.p_out, x, y, z, t);
-    [[maybe_unused]] uint32_t nf0 = 0, nb0 = 0;
-    [[maybe_unused]] T lr0[18], li0[18];
-    [[maybe_unused]] Raw<P> wf0, wb0;
+    [[maybe_unused]] uint32_t pnf[PB], pnb[PB];
+    [[maybe_unused]] PairRaw<P> pl[PB];
+    [[maybe_unused]] Raw<P> pwf[PB], pwb[PB], pown;
     if constexpr (N == 1) {
-        if (a.st) {
-            s1 = *a.st;
-            if (!(s1.flags & a.run_mask)) act = 0;
-        }
-        if (valid && act) {
-            const int pr = j * B;
-            pair_neighbours<NP>(a.g, s, x, y, z, t, pr, nf0, nb0);
-            load_pair<P, NT>(a.gauge, a.gscale, Vh, s, pr, a.r12, eta_sign(pr & 3, x, y, z), lr0, li0);
-            load_raw<P>(a, (const char*)a.in, 0, nf0, lazy_nb, wf0);
-            load_raw<P>(a, (const char*)a.in, 0, nb0, lazy_nb, wb0);
+        s1 = *(a.st ? a.st : &kNoState);
+        if (a.st && !(s1.flags & a.run_mask)) act = 0;
+        if (valid) {
+            static_for<0, PB>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                pair_neighbours<NP>(a.g, s, x, y, z, t, j * B + k, pnf[k], pnb[k]);
+                load_raw<P>(a, (const char*)a.in, 0, pnf[k], lazy_nb, pwf[k]);
+                load_raw<P>(a, (const char*)a.in, 0, pnb[k], lazy_nb, pwb[k]);
+            });
+            if constexpr (PRE && EPI != EPI_PLAIN) {
+                if (j == 0) load_raw<P>(a, (const char*)a.x, 0, s, a.lazy_r != nullptr, pown);
+            }
+            static_for<0, PB>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                load_pair_raw<P, NT>(a.gauge, a.gscale, Vh, s, j * B + k, a.r12, pl[k]);
+            });
         }
         if (a.st && a.fin.partials) {
             // always: block 0 must pass the state on even when it is inactive
@@ -187,21 +199,25 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
         // of pairs this lane owns and across the S lanes of the site below.
         // This fixes the rounding independently of S and of the number of
         // right-hand sides.
-#pragma unroll
-        for (int k = 0; k < B; ++k) {
+        // (a loop over the lane's pairs with a compile-time index, so that
+        // the arrays of operands requested up front stay in registers)
+        static_for<0, B>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
             const int mu = j * B + k;  // hop pair index
             uint32_t nf, nb;
             T lr[18], li[18];
-            if (N == 1 && k == 0) {
-                nf = nf0;
-                nb = nb0;
-#pragma unroll
-                for (int e = 0; e < 18; ++e) {
-                    lr[e] = lr0[e];
-                    li[e] = li0[e];
-                }
+            [[maybe_unused]] Raw<P> wfk, wbk;
+            if constexpr (N == 1 && k < PB) {
+                nf = pnf[k];
+                nb = pnb[k];
+                finish_pair<P>(a.r12, eta_sign(mu & 3, x, y, z), pl[k], lr, li);
             } else {
                 pair_neighbours<NP>(a.g, s, x, y, z, t, mu, nf, nb);
+                if constexpr (N == 1) {
+                    // one RHS: neighbours before links, as for the first pair
+                    load_raw<P>(a, (const char*)a.in, 0, nf, lazy_nb, wfk);
+                    load_raw<P>(a, (const char*)a.in, 0, nb, lazy_nb, wbk);
+                }
                 load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, a.r12, eta_sign(mu & 3, x, y, z), lr, li);
             }
 #pragma unroll
@@ -210,9 +226,12 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                 const char* in_r = (const char*)a.in + (size_t)r * a.in_rs;
                 const double be = lazy_nb ? stv(r).beta : 0.0;
                 Raw<P> wf, wb;
-                if (N == 1 && k == 0) {
-                    wf = wf0;
-                    wb = wb0;
+                if constexpr (N == 1 && k < PB) {
+                    wf = pwf[k];
+                    wb = pwb[k];
+                } else if constexpr (N == 1) {
+                    wf = wfk;
+                    wb = wbk;
                 } else {
                     load_raw<P>(a, in_r, r, nf, lazy_nb, wf);
                     load_raw<P>(a, in_r, r, nb, lazy_nb, wb);
@@ -259,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                     }
                 }
             }
-        }
+        });
     }
     if constexpr (S > 1) {
         // lanes 2i and 2i + 1 hold the sums of consecutive aligned blocks;
@@ -290,8 +309,13 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                 store_site<P>(out_r, Vh, s, ar[r], ai[r]);
             } else {
                 T xr[3], xi[3], hr[3], hi[3];
-                load_operand<P>(a, (const char*)a.x + (size_t)r * a.x_rs, r, s, a.lazy_r != nullptr,
-                                a.lazy_r ? stv(r).beta : 0.0, xr, xi);
+                if constexpr (PRE) {
+                    combine<P>(a, pown, r, s, a.lazy_r != nullptr, a.lazy_r ? stv(r).beta : 0.0, true,
+                               xr, xi);
+                } else {
+                    load_operand<P>(a, (const char*)a.x + (size_t)r * a.x_rs, r, s, a.lazy_r != nullptr,
+                                    a.lazy_r ? stv(r).beta : 0.0, xr, xi);
+                }
                 if (a.lazy_r) store_site<P>((char*)a.x + (size_t)r * a.x_rs, Vh, s, xr, xi);
                 if constexpr (P == P64) {
                     if (a.lazy_y && !a.keep_y) {

@@ -171,88 +171,135 @@ __device__ __forceinline__ void third_row(T (&lr)[18], T (&li)[18], int o) {
     }
 }
 
-// Load the 18 complex entries of hop pair mu (forward link then backward
-// link, each row-major) of output site s. With r12 the links are stored as
-// two rows without phases: the third rows are rebuilt and the forward link
-// is multiplied by eta, the backward one by -eta (eta = eta_mu(x) = +-1).
+// Hop pair mu of output site s as stored (forward link then backward link,
+// each row-major): with r12 the links are stored as two rows without phases
+// (entries 0-5 and 9-14 of the pair). load_pair_raw only issues the loads,
+// so that a caller can request several pairs before using any; the 12- or
+// 18-entry form is chosen by address and count, not by separate code paths
+// (separate paths writing different array positions make the compiler index
+// the arrays dynamically, in scratch memory).
+template <int P>
+struct PairRaw;
+template <>
+struct PairRaw<P64> {
+    d2v v[18];  // r12: entries 0-5 then 9-14; full: entries 0-17
+};
+template <>
+struct PairRaw<P32> {
+    f4v v[9];   // two entries each; r12: rows 0-1 forward in v[0..2], backward in v[3..5]
+};
+template <>
+struct PairRaw<P16S> {
+    u2v v[9];
+    float sc;
+};
+
+template <int P, bool NT>
+__device__ __forceinline__ void load_pair_raw(const void* G, const float* gscale, uint32_t Vh,
+                                              uint32_t s, int mu, int r12, PairRaw<P>& w) {
+    if constexpr (P == P64) {
+        const d2v* g = (const d2v*)G + (size_t)((r12 ? 12 : 18) * mu) * Vh + s;
+#pragma unroll
+        for (int e = 0; e < 12; ++e) w.v[e] = ldg<NT>(g + (size_t)e * Vh);
+        if (!r12) {
+#pragma unroll
+            for (int e = 12; e < 18; ++e) w.v[e] = ldg<NT>(g + (size_t)e * Vh);
+        }
+    } else if constexpr (P == P32) {
+        const f4v* g = (const f4v*)G + (size_t)((r12 ? 6 : 9) * mu) * Vh + s;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) w.v[e] = ldg<NT>(g + (size_t)e * Vh);
+        if (!r12) {
+#pragma unroll
+            for (int e = 6; e < 9; ++e) w.v[e] = ldg<NT>(g + (size_t)e * Vh);
+        }
+    } else {
+        const u2v* g = (const u2v*)G + (size_t)(9 * mu) * Vh + s;
+        w.sc = gscale[s];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) w.v[e] = ldg<NT>(g + (size_t)e * Vh);
+    }
+}
+
+// The 18 complex entries of a pair from what load_pair_raw loaded: with r12
+// the third rows are rebuilt and the forward link is multiplied by eta, the
+// backward one by -eta (eta = eta_mu(x) = +-1); stored full links already
+// hold the phases. Both forms are formed and one is selected per entry.
+template <int P>
+__device__ __forceinline__ void finish_pair(int r12, int eta, const PairRaw<P>& w,
+                                            typename Real<P>::T (&lr)[18],
+                                            typename Real<P>::T (&li)[18]) {
+    using T = typename Real<P>::T;
+    if constexpr (P == P16S) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            lr[2 * e] = h2f_lo(w.v[e].x) * w.sc;
+            li[2 * e] = h2f_hi(w.v[e].x) * w.sc;
+            lr[2 * e + 1] = h2f_lo(w.v[e].y) * w.sc;
+            li[2 * e + 1] = h2f_hi(w.v[e].y) * w.sc;
+        }
+    } else {
+        T fr[18], fi[18], cr[18], ci[18];  // full, compressed
+        if constexpr (P == P64) {
+#pragma unroll
+            for (int e = 0; e < 18; ++e) {
+                fr[e] = w.v[e].x;
+                fi[e] = w.v[e].y;
+            }
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                cr[e] = w.v[e].x;
+                ci[e] = w.v[e].y;
+                cr[9 + e] = w.v[6 + e].x;
+                ci[9 + e] = w.v[6 + e].y;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 9; ++e) {
+                fr[2 * e] = w.v[e].x;
+                fi[2 * e] = w.v[e].y;
+                fr[2 * e + 1] = w.v[e].z;
+                fi[2 * e + 1] = w.v[e].w;
+            }
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                cr[2 * e] = w.v[e].x;
+                ci[2 * e] = w.v[e].y;
+                cr[2 * e + 1] = w.v[e].z;
+                ci[2 * e + 1] = w.v[e].w;
+                cr[9 + 2 * e] = w.v[3 + e].x;
+                ci[9 + 2 * e] = w.v[3 + e].y;
+                cr[9 + 2 * e + 1] = w.v[3 + e].z;
+                ci[9 + 2 * e + 1] = w.v[3 + e].w;
+            }
+        }
+        third_row(cr, ci, 0);
+        third_row(cr, ci, 9);
+        const T sf = (T)eta, sb = -(T)eta;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            cr[e] *= sf;
+            ci[e] *= sf;
+            cr[9 + e] *= sb;
+            ci[9 + e] *= sb;
+        }
+#pragma unroll
+        for (int e = 0; e < 18; ++e) {
+            lr[e] = r12 ? cr[e] : fr[e];
+            li[e] = r12 ? ci[e] : fi[e];
+        }
+    }
+}
+
+// Both steps at once: hop pair mu of output site s, ready to apply.
 template <int P, bool NT>
 __device__ __forceinline__ void load_pair(const void* G, const float* gscale, uint32_t Vh,
                                           uint32_t s, int mu, int r12, int eta,
                                           typename Real<P>::T (&lr)[18],
                                           typename Real<P>::T (&li)[18]) {
-    using T = typename Real<P>::T;
-    if constexpr (P != P16S) {
-        if (r12) {
-            if constexpr (P == P64) {
-                const d2v* g = (const d2v*)G + (size_t)(12 * mu) * Vh + s;
-#pragma unroll
-                for (int e = 0; e < 6; ++e) {
-                    const d2v f = ldg<NT>(g + (size_t)e * Vh);
-                    const d2v b = ldg<NT>(g + (size_t)(6 + e) * Vh);
-                    lr[e] = f.x;
-                    li[e] = f.y;
-                    lr[9 + e] = b.x;
-                    li[9 + e] = b.y;
-                }
-            } else {
-                const f4v* g = (const f4v*)G + (size_t)(6 * mu) * Vh + s;
-#pragma unroll
-                for (int w = 0; w < 3; ++w) {
-                    const f4v f = ldg<NT>(g + (size_t)w * Vh);
-                    const f4v b = ldg<NT>(g + (size_t)(3 + w) * Vh);
-                    lr[2 * w] = f.x;
-                    li[2 * w] = f.y;
-                    lr[2 * w + 1] = f.z;
-                    li[2 * w + 1] = f.w;
-                    lr[9 + 2 * w] = b.x;
-                    li[9 + 2 * w] = b.y;
-                    lr[9 + 2 * w + 1] = b.z;
-                    li[9 + 2 * w + 1] = b.w;
-                }
-            }
-            third_row(lr, li, 0);
-            third_row(lr, li, 9);
-            const T sf = (T)eta, sb = -(T)eta;
-#pragma unroll
-            for (int e = 0; e < 9; ++e) {
-                lr[e] *= sf;
-                li[e] *= sf;
-                lr[9 + e] *= sb;
-                li[9 + e] *= sb;
-            }
-            return;
-        }
-    }
-    if constexpr (P == P64) {
-        const d2v* g = (const d2v*)G + (size_t)(18 * mu) * Vh + s;
-#pragma unroll
-        for (int e = 0; e < 18; ++e) {
-            d2v v = ldg<NT>(g + (size_t)e * Vh);
-            lr[e] = v.x;
-            li[e] = v.y;
-        }
-    } else if constexpr (P == P32) {
-        const f4v* g = (const f4v*)G + (size_t)(9 * mu) * Vh + s;
-#pragma unroll
-        for (int w = 0; w < 9; ++w) {
-            f4v v = ldg<NT>(g + (size_t)w * Vh);
-            lr[2 * w] = v.x;
-            li[2 * w] = v.y;
-            lr[2 * w + 1] = v.z;
-            li[2 * w + 1] = v.w;
-        }
-    } else {
-        const u2v* g = (const u2v*)G + (size_t)(9 * mu) * Vh + s;
-        float sc = gscale[s];
-#pragma unroll
-        for (int w = 0; w < 9; ++w) {
-            u2v v = ldg<NT>(g + (size_t)w * Vh);
-            lr[2 * w] = h2f_lo(v.x) * sc;
-            li[2 * w] = h2f_hi(v.x) * sc;
-            lr[2 * w + 1] = h2f_lo(v.y) * sc;
-            li[2 * w + 1] = h2f_hi(v.y) * sc;
-        }
-    }
+    PairRaw<P> w;
+    load_pair_raw<P, NT>(G, gscale, Vh, s, mu, r12, w);
+    finish_pair<P>(r12, eta, w, lr, li);
 }
 
 // eta_mu(x) = (-1)^(x_0 + ... + x_{mu-1}) of the site with coordinates x, y, z.
@@ -594,14 +641,32 @@ __device__ __forceinline__ void finalize_block(const Reduce& R, unsigned run_mas
     }
 }
 
+// f(std::integral_constant<int, I>()) for I = I0 .. I1 - 1: a loop whose
+// index is a compile-time constant in the body.
+template <int I0, int I1, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (I0 < I1) {
+        f(std::integral_constant<int, I0>());
+        static_for<I0 + 1, I1>(f);
+    }
+}
+
+// The state a single-RHS kernel without per-RHS state reads (no flags set,
+// never written): the read then needs no branch, whose join would make every
+// later load wait for it. In global memory like the states themselves, so
+// the read stays a scalar load.
+static __device__ RhsState kNoState{};
+
 // Single right-hand side, many-block consumer: every wavefront holds the
 // input state s (read by the caller), sums the partials and applies R.kind
 // in its own registers, bit-identically in every wave, so no barrier or LDS
 // is needed; thread 0 of block 0 writes the result to R.st_out (never to the
 // input: other waves may still be reading it).
 __device__ __forceinline__ void finalize_wave1(const Reduce& R, unsigned run_mask, RhsState& s) {
+    // summed before the flags are read: the partials' loads then need not
+    // wait for the state's
+    const double sum = wave_sum_partials(R.partials, R.nparts);
     if (s.flags & run_mask) {
-        const double sum = wave_sum_partials(R.partials, R.nparts);
         const bool t0 = blockIdx.x == 0 && threadIdx.x == 0;
         finalize_one(R.kind, &s, sum, t0 && R.out ? R.out : nullptr);
     }
