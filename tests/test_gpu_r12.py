@@ -93,3 +93,83 @@ def test_r12_solves_and_block_equals_single(stag, ctx, inner):
     assert rc1 == 0 and st1[0]["iters"] == st[1]["iters"]
     assert np.array_equal(x1.store()[0], x[1])
     g.destroy()
+
+
+def _shapes(nrhs):
+    for S1 in (1, 2, 4):
+        for S2 in (1, 2, 4):
+            for nt in ((0, 1) if nrhs == 1 else (1,)):
+                for sw in (0, 1):
+                    yield S1, S2, nt, sw
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("r12", [False, True])
+@pytest.mark.parametrize("nrhs", [1, 2])
+def test_launch_shapes_bitwise_identical(stag, ctx, prec, r12, nrhs):
+    """A through every launch shape gives the same bits (one RHS takes
+    different load orders by shape: all of a lane's hop pairs requested up
+    front when they fit in registers, else the first), with full and
+    12-parameter links, and meets the oracle."""
+    if prec == "f16s" and r12:
+        pytest.skip("fp16 links are stored full")
+    L = (4, 6, 4, 8)
+    U = links(L, "haar", 31)
+    g = ctx.gauge(L, U, precisions=(prec,), r12=r12)
+    v = synth.gaussian_rhs(L, nrhs, 32)
+    masses = [0.1, 0.2][:nrhs]
+    fi = ctx.field(g, 0, prec, nrhs).load(v)
+    fo = ctx.field(g, 0, prec, nrhs)
+    saved = stag.stag_tune_get(ctx, prec, nrhs, g.vh)
+    outs = {}
+    try:
+        for shape in _shapes(nrhs):
+            log("shape", prec, r12, nrhs, shape)
+            stag.stag_tune_set(ctx, prec, nrhs, g.vh, *shape)
+            stag.stag_apply_A(ctx, g, masses, fi, fo)
+            outs[shape] = fo.store()
+    finally:
+        stag.stag_tune_set(ctx, prec, nrhs, g.vh, saved["S1"], saved["S2"], saved["nt"],
+                           saved["swizzle"])
+    ref = next(iter(outs.values()))
+    for k, o in outs.items():
+        assert np.array_equal(o, ref), k
+    tol = {"f64": 1e-12, "f32": 1e-6, "f16s": 1e-3}[prec]
+    assert rel_max(ref, oracle_apply_A(U, v, L, masses)) <= tol
+    for o in (fi, fo, g):
+        o.destroy()
+
+
+@pytest.mark.parametrize("inner", ["f32", "f16s"])
+def test_mixed_solve_bitwise_across_shapes(stag, ctx, inner):
+    """A mixed solve (deferred direction in stage 1, own-site operand in
+    stage 2, fp64 fix-ups) gives the same iterations and bits whatever launch
+    shapes the iteration and fix-up kernels take."""
+    L = (8, 8, 8, 8)
+    U = links(L, "haar", 33)
+    b = synth.gaussian_rhs(L, 1, 34)
+    m, tol = 0.05, 1e-9
+    g = ctx.gauge(L, U, precisions=("f64", inner), r12=inner == "f32")
+    fb = ctx.field(g, 0, "f64", 1).load(b)
+    fx = ctx.field(g, 0, "f64", 1)
+    saved = {p: stag.stag_tune_get(ctx, p, 1, g.vh) for p in ("f64", inner)}
+    res = []
+    try:
+        for S in (1, 2, 4):
+            for p in ("f64", inner):
+                stag.stag_tune_set(ctx, p, 1, g.vh, S, S, S % 2, S // 4)
+            rc, st = stag.stag_cg_solve(ctx, g, [m], fb, fx,
+                                        stag.cg_params(tol=tol, inner=inner, small_lattice=False))
+            log(inner, S, st[0]["iters"], st[0]["true_rel_res"])
+            assert rc == 0
+            res.append((st[0]["iters"], fx.store()))
+    finally:
+        for p, c in saved.items():
+            stag.stag_tune_set(ctx, p, 1, g.vh, c["S1"], c["S2"], c["nt"], c["swizzle"])
+    for it, x in res[1:]:
+        assert it == res[0][0]
+        assert np.array_equal(x, res[0][1])
+    Ax = oracle_apply_A(U, res[0][1], L, [m])
+    assert math.sqrt(ostag.norm2(b[0] - Ax[0]) / ostag.norm2(b[0])) <= tol
+    for o in (fb, fx, g):
+        o.destroy()
