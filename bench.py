@@ -423,6 +423,37 @@ def cpu_baseline(synth, L, U, b, mass, gpu_fp64_iters, target_s):
     }
 
 
+def cpu_a_apply(synth, costs):
+    """The C oracle's fp64 A (Eq.2-3 over Eq.5, full links) on the host cores:
+    median of 10 applications on 4^4 and 16^3x32, of 3 on 32^3x64, with the
+    same compulsory bytes per even site as the GPU's fp64 A; and the oracle's
+    full Fig.1 CG on 4^4 (m = 0.1, 1e-10)."""
+    import statistics
+    from oracle import c as oc
+    out = {}
+    for name, reps in (("c1_4x4x4x4", 10), ("c2_16x16x16x32", 10), ("c3_32x32x32x64", 3)):
+        cfg = synth.CONFIGS[name]
+        L, m = cfg["L"], cfg["mass"]
+        U, b = synth.config_links(name), synth.config_rhs(name)[0]
+        oc.apply_A(U, b, L, m)
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oc.apply_A(U, b, L, m)
+            ts.append(time.perf_counter() - t0)
+        t = statistics.median(ts)
+        nbytes = b.shape[0] * costs.a_bytes_per_site("f64")
+        out[name] = {"ms_per_A": round(t * 1e3, 3), "GB/s": round(nbytes / t / 1e9, 2), "reps": reps}
+        if name == "c1_4x4x4x4":
+            t0 = time.perf_counter()
+            _, st = oc.cg(U, b, L, m, cfg["tol"])
+            out[name]["cg_to_tol_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+            out[name]["cg_iters"] = st["iters"]
+        del U, b
+    log("cpu A", out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -628,6 +659,7 @@ def main():
                 _, st = stag.stag_cg_solve(c2, g2, [mass], fb2, fx2, stag.cg_params(tol=tol))
                 fp64_iters = st[0]["iters"]
         result["cpu_baseline"] = cpu_baseline(synth, L, U, b[0], mass, fp64_iters, args.cpu_seconds)
+        result["cpu_baseline"]["a_apply_fp64"] = cpu_a_apply(synth, costs)
     print(json.dumps(result), flush=True)
 
 
