@@ -174,3 +174,34 @@ def test_apply_A_full_size(stag, ctx, name):
         fi.destroy()
         fo.destroy()
     g.destroy()
+
+
+@pytest.mark.parametrize("shift", [(2, 0, 0, 0), (0, 2, 0, 0), (0, 0, 2, 0), (0, 0, 0, 2), (2, 2, 0, 4)])
+@pytest.mark.parametrize("prec,r12", [("f64", False), ("f64", True), ("f32", True)])
+def test_even_shift_covariance_on_gpu(stag, ctx, shift, prec, r12):
+    """Shifting links and vector by an even displacement (the phases of
+    Sec.2 are unchanged by it) shifts A of the vector the same way, to the
+    bit: every site does the same operations in the same order."""
+    L, m = (4, 6, 4, 8), 0.1
+    axes = (3, 2, 1, 0)
+
+    def sh(f):
+        for mu in range(4):
+            f = np.roll(f, shift[mu], axis=axes[mu])
+        return f
+
+    U = links(L, "haar", 41)
+    v = synth.gaussian_rhs(L, 1, 42)
+    vs = ostag.from_full(sh(ostag.to_full(v[0], L, 0)), L, 0)[None]
+    out = []
+    for UU, vv in ((U, v), (sh(U), vs)):
+        g = ctx.gauge(L, UU, precisions=(prec,), r12=r12)
+        fi = ctx.field(g, 0, prec, 1).load(vv)
+        fo = ctx.field(g, 0, prec, 1)
+        stag.stag_apply_A(ctx, g, [m], fi, fo)
+        out.append(fo.store())
+        for o in (fi, fo, g):
+            o.destroy()
+    moved = ostag.from_full(sh(ostag.to_full(out[0][0], L, 0)), L, 0)
+    log("even shift", shift, prec, r12, rel_max(out[1][0][None], moved[None]))
+    assert np.array_equal(out[1][0], moved)
