@@ -616,7 +616,7 @@ def main():
         # the two update methods of Sec.3.2 alone (capped at 4x the iterations
         # of the scheme that applies both)
         abl = {}
-        for var in ("reliable", "groupwise"):
+        for var in ("reliable", "fold_only"):
             pv = stag.cg_params(tol=tol, inner=inner, mixed_variant=var, max_iter=4 * iters)
             torch.cuda.synchronize()
             t0 = time.perf_counter()

@@ -65,7 +65,7 @@ extern "C" {
 #define STAG_ENOCONV (-4)     /* iteration cap reached before the tolerance */
 #define STAG_EBREAKDOWN (-5)  /* <d, A d> <= 0 or a non-finite scalar in the recurrence */
 #define STAG_ESTALL (-6)      /* low-precision iteration stopped making progress */
-#define STAG_EBUSY (-7)       /* serving queue full */
+#define STAG_EBUSY (-7)       /* serving queue full, or a gauge still used by serving requests */
 #define STAG_ENOTFOUND (-8)   /* unknown or already collected ticket */
 
 /* ------------------------------------------------------------- precisions */
@@ -143,6 +143,10 @@ int stag_gauge_create(stag_ctx* ctx, const int L[4], const double* U, int U_on_d
  * tuning call takes the resulting gauge like any other. */
 int stag_gauge_create_improved(stag_ctx* ctx, const int L[4], const double* F, const double* N,
                                int links_on_device, int prec_mask, stag_gauge** out);
+/* stag_gauge_destroy: frees the gauge's device copies (and the solver
+ * workspaces and serving batches built on it). Errors: EBUSY while a serving
+ * request submitted on this gauge has not been collected by stag_solver_poll
+ * (the gauge stays valid; collect the tickets and call again). NULL is a no-op. */
 int stag_gauge_destroy(stag_gauge* gauge);
 /* Number of sites per parity (Vh = Lx*Ly*Lz*Lt/2) of a gauge's lattice. */
 int stag_gauge_sites(const stag_gauge* gauge, int64_t* vh);
@@ -186,6 +190,7 @@ int stag_dslash(stag_ctx* ctx, const stag_gauge* gauge, const stag_field* in, st
 int stag_apply_A(stag_ctx* ctx, const stag_gauge* gauge, const double* mass, const stag_field* in,
                  stag_field* out, void* stream);
 
+
 /* ---------------------------------------------------------------- solver */
 typedef struct stag_cg_params {
     double tol;        /* relative true-residual target, > 0 and < 1 */
@@ -212,12 +217,15 @@ typedef struct stag_cg_params {
                           STAG_MIXED_RESTART: restart it, d = r, every update (the plain
                           iterative refinement of Fig.2); the cycle ends when
                           |r| < delta |r at the cycle start|.
-                          Ablations of the two update methods that Sec.3.2 applies
-                          together: STAG_MIXED_RELIABLE recomputes r = b - A (x + y) in
-                          fp64 but never folds y into x (the solution stays in fp32);
-                          STAG_MIXED_GROUPWISE folds y into x but never recomputes r and
-                          checks the true residual once, when the iterated one has met
-                          tol (ENOCONV if the true one misses it). */
+                          Ablations that split Sec.3.2's update into its two
+                          ingredients (the paper's group-wise paragraph, read
+                          literally, already includes the residual recompute, i.e. it
+                          is the default scheme): STAG_MIXED_RELIABLE replaces the
+                          inner residual by r = b - A (x + y) computed in fp64 but never
+                          folds y into x (the solution stays in fp32);
+                          STAG_MIXED_FOLD_ONLY folds y into x in fp64 (y = 0) but never
+                          recomputes r, and checks the true residual once, when the
+                          iterated one has met tol (ENOCONV if the true one misses it). */
     int small_lattice; /* 1 (default): tiny lattices solve each right-hand side inside
                           one workgroup, which loops over the iterations itself (no
                           kernel launch per stage): up to 128 sites per parity (4^4),
@@ -229,7 +237,7 @@ typedef struct stag_cg_params {
 #define STAG_MIXED_CARRY 0
 #define STAG_MIXED_RESTART 1
 #define STAG_MIXED_RELIABLE 2
-#define STAG_MIXED_GROUPWISE 3
+#define STAG_MIXED_FOLD_ONLY 3
 
 typedef struct stag_cg_stats {
     int iters;             /* CG iterations (inner iterations for mixed) */
@@ -277,7 +285,13 @@ int stag_cg_solve(stag_ctx* ctx, const stag_gauge* gauge, const double* mass,
  * blocks while other slots are mid-solve, and frees each slot when its
  * right-hand side has finished. Batches of different gauges run on separate
  * streams and overlap on the device. A right-hand side's result does not
- * depend on what else is being solved.
+ * depend on what else is being solved. An STAG_F16S request on a gauge that
+ * also holds F32 links hands a right-hand side whose fp16 inner iteration
+ * stalls (no halving of the true residual over 3 stall updates) over to the
+ * gauge's F32 batch, which continues from its current x without stall
+ * restarts, as stag_cg_solve escalates; its stats add up both passes and
+ * report inner_final = STAG_F32. Without an F32 copy such a right-hand side
+ * ends with STAG_ESTALL after max_stall (20) stall updates.
  *
  * stag_solver_submit: copies b_host (complex128 [nrhs][Vh][3], even sites)
  *   before returning; never waits for the GPU. mass > 0, 0 < tol < 1,

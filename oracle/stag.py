@@ -427,16 +427,19 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
 
     Convergence is declared only on the fp64 true residual.
     ``carry_direction=False`` restarts d = r at every update (ablation).
-    ``update`` selects the ablations of Sec.3.2's two update methods:
-    "reliable" only recomputes r = b - A (x + y) in fp64 at a trigger and
-    never folds y into x (the solution stays in fp32); "groupwise" only
-    folds y into x and never recomputes r, the direction continuing with
-    the iterated beta; when its iterated residual meets the tolerance the
-    true residual is computed once and decides ("inaccurate" if it misses).
+    ``update`` selects ablations that split the update into its two
+    ingredients (Sec.3.2's group-wise paragraph, read literally, already
+    contains the fp64 residual recompute and so equals "both"):
+    "reliable" only replaces the low-precision residual by r = b - A (x + y)
+    computed in fp64 at a trigger and never folds y into x (the solution
+    stays in fp32); "fold_only" only folds y into x in fp64 (y = 0) and
+    never recomputes r, the direction continuing with the iterated beta;
+    when its iterated residual meets the tolerance the true residual is
+    computed once and decides ("inaccurate" if it misses).
     ``Ulong``: the improved operator (U = fat links), in both precisions.
     Returns (x, stats).
     """
-    if update not in ("both", "reliable", "groupwise"):
+    if update not in ("both", "reliable", "fold_only"):
         raise ValueError(update)
     if stall_iters is None:
         stall_iters = 100 if prec == "f16s" else math.inf
@@ -487,7 +490,7 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
             since += 1
         upd = rn < delta * rmax or rr <= stop
         stall = (not upd) and since >= stall_iters
-        if (upd or stall) and update == "groupwise":
+        if (upd or stall) and update == "fold_only":
             # fold the correction into x; the iterated residual carries on
             x = x + y.astype(np.complex128)
             y[:] = 0

@@ -37,7 +37,7 @@ STAG_ENOTFOUND = -8
 
 F64, F32, F16S = 0, 1, 2
 PREC = {"f64": F64, "f32": F32, "f16s": F16S}
-MIXED_CARRY, MIXED_RESTART, MIXED_RELIABLE, MIXED_GROUPWISE = 0, 1, 2, 3
+MIXED_CARRY, MIXED_RESTART, MIXED_RELIABLE, MIXED_FOLD_ONLY = 0, 1, 2, 3
 GAUGE_R12 = 1 << 4
 TUNE_IMPROVED = 1 << 8
 MAX_RHS = 16
@@ -256,8 +256,10 @@ class Gauge:
         self.vh = Lx * Ly * Lz * Lt // 2
 
     def destroy(self):
+        """stag_gauge_destroy; raises StagError (EBUSY) while serving requests
+        on this gauge are uncollected (the gauge then stays valid)."""
         if self.h:
-            lib.stag_gauge_destroy(self.h)
+            self.ctx.check(lib.stag_gauge_destroy(self.h))
             self.h = None
 
 
@@ -321,7 +323,7 @@ def cg_params(tol=1e-8, inner="f64", max_iter=0, delta=0.1, stall_iters=0, max_s
     p.use_x0 = 1 if use_x0 else 0
     p.escalate = 1 if escalate else 0
     p.mixed_variant = {"carry": MIXED_CARRY, "restart": MIXED_RESTART, "reliable": MIXED_RELIABLE,
-                       "groupwise": MIXED_GROUPWISE}[mixed_variant]
+                       "fold_only": MIXED_FOLD_ONLY}[mixed_variant]
     p.small_lattice = 1 if small_lattice else 0
     return p
 

@@ -214,6 +214,7 @@ int stag_create(int device, size_t hbm_budget_bytes, stag_ctx** out) {
 }
 
 int stag_serve_shutdown_internal(stag_ctx* ctx);  // serve.cpp
+int stag_serve_release_gauge_internal(stag_ctx* ctx, const stag_gauge* g);  // serve.cpp
 
 int stag_destroy(stag_ctx* ctx) {
     if (!ctx) return STAG_OK;
@@ -398,6 +399,10 @@ int stag_gauge_destroy(stag_gauge* g) {
     if (!g) return STAG_OK;
     stag_ctx* ctx = g->ctx;
     DeviceGuard dg(ctx->device);
+    // serving requests still reference the gauge: refuse; else the serving
+    // batches on it are released (their in-flight blocks waited for)
+    int rc = stag_serve_release_gauge_internal(ctx, g);
+    if (rc) return rc;
     (void)hipStreamSynchronize(ctx->stream);
     std::vector<stag_engine*> drop;
     {
@@ -592,21 +597,10 @@ int stag_dslash(stag_ctx* ctx, const stag_gauge* g, const stag_field* in, stag_f
     return STAG_OK;
 }
 
-int stag_apply_A(stag_ctx* ctx, const stag_gauge* g, const double* mass, const stag_field* in,
-                 stag_field* out, void* stream) {
-    if (!ctx) return STAG_EINVAL;
-    int rc = check_pair(ctx, g, in, out, "stag_apply_A");
-    if (rc) return rc;
-    if (!mass) return set_error(ctx, STAG_EINVAL, "stag_apply_A: mass is NULL");
-    if (in->parity != 0 || out->parity != 0)
-        return set_error(ctx, STAG_EINVAL, "stag_apply_A: fields must be even (parity 0)");
-    for (int r = 0; r < in->nrhs; ++r)
-        if (!(mass[r] > 0.0) || !std::isfinite(mass[r]))
-            return set_error(ctx, STAG_EINVAL, "stag_apply_A: mass[%d] must be finite and > 0", r);
-    DeviceGuard dg(ctx->device);
-    hipStream_t s = pick_stream(ctx, stream);
-    void* t = nullptr;
-    HIPCK(ctx, hipMallocAsync(&t, in->rs * in->nrhs, s));
+// The two hop stages of A for every right-hand side of `in`, with the odd
+// intermediate D_oe in at t (in->nrhs right-hand sides of in->rs bytes).
+static int apply_A_stages(stag_ctx* ctx, const stag_gauge* g, const double* mass,
+                          const stag_field* in, stag_field* out, void* t, hipStream_t s) {
     int done = 0;
     while (done < in->nrhs) {
         int n = in->nrhs - done;
@@ -629,8 +623,34 @@ int stag_apply_A(stag_ctx* ctx, const stag_gauge* g, const double* mass, const s
                                in->rs, nullptr, 0, m2, nullptr, 0, nullptr, Issue{s}));
         done += Nk;
     }
-    HIPCK(ctx, hipFreeAsync(t, s));
     return STAG_OK;
+}
+
+static int check_apply_A(stag_ctx* ctx, const stag_gauge* g, const double* mass,
+                         const stag_field* in, const stag_field* out, const char* fn) {
+    int rc = check_pair(ctx, g, in, out, fn);
+    if (rc) return rc;
+    if (!mass) return set_error(ctx, STAG_EINVAL, "%s: mass is NULL", fn);
+    if (in->parity != 0 || out->parity != 0)
+        return set_error(ctx, STAG_EINVAL, "%s: fields must be even (parity 0)", fn);
+    for (int r = 0; r < in->nrhs; ++r)
+        if (!(mass[r] > 0.0) || !std::isfinite(mass[r]))
+            return set_error(ctx, STAG_EINVAL, "%s: mass[%d] must be finite and > 0", fn, r);
+    return STAG_OK;
+}
+
+int stag_apply_A(stag_ctx* ctx, const stag_gauge* g, const double* mass, const stag_field* in,
+                 stag_field* out, void* stream) {
+    if (!ctx) return STAG_EINVAL;
+    int rc = check_apply_A(ctx, g, mass, in, out, "stag_apply_A");
+    if (rc) return rc;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = pick_stream(ctx, stream);
+    void* t = nullptr;
+    HIPCK(ctx, hipMallocAsync(&t, in->rs * in->nrhs, s));
+    rc = apply_A_stages(ctx, g, mass, in, out, t, s);
+    HIPCK(ctx, hipFreeAsync(t, s));
+    return rc;
 }
 
 void stag_cg_params_default(stag_cg_params* p) {
@@ -650,10 +670,6 @@ void stag_cg_params_default(stag_cg_params* p) {
     p->small_lattice = 1;
 }
 
-// Stall restarts without a halving of the true residual after which an
-// escalating fp16 pass hands over to fp32.
-constexpr int kEscalateStalls = 3;
-
 int stag_cg_solve(stag_ctx* ctx, const stag_gauge* g, const double* mass, const stag_field* b,
                   stag_field* x, const stag_cg_params* params, stag_cg_stats* stats,
                   void* stream) {
@@ -671,7 +687,7 @@ int stag_cg_solve(stag_ctx* ctx, const stag_gauge* g, const double* mass, const 
         return set_error(ctx, STAG_EINVAL, "stag_cg_solve: tol must be in (0, 1)");
     if (p.inner_prec < 0 || p.inner_prec > 2)
         return set_error(ctx, STAG_EINVAL, "stag_cg_solve: inner precision %d", p.inner_prec);
-    if (p.mixed_variant < STAG_MIXED_CARRY || p.mixed_variant > STAG_MIXED_GROUPWISE)
+    if (p.mixed_variant < STAG_MIXED_CARRY || p.mixed_variant > STAG_MIXED_FOLD_ONLY)
         return set_error(ctx, STAG_EINVAL, "stag_cg_solve: mixed_variant %d", p.mixed_variant);
     if (!(g->mask & STAG_MASK_F64) || !(g->mask & (1 << p.inner_prec)))
         return set_error(ctx, STAG_EINVAL,

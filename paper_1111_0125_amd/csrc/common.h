@@ -186,9 +186,9 @@ enum StateFlag : unsigned {
     F_BADINPUT = 256u,   // |b|^2 not finite
     F_NEW = 512u,        // slot being started
     F_X0 = 1024u,        // slot being started from an initial guess x0
-    F_CHECK = 2048u,     // group-wise-only variant: iterated residual converged, true
+    F_CHECK = 2048u,     // fold-only ablation: iterated residual converged, true
                          // residual check pending
-    F_INACC = 4096u,     // group-wise-only variant: the true residual missed the tolerance
+    F_INACC = 4096u,     // fold-only ablation: the true residual missed the tolerance
 };
 
 struct RhsState {
@@ -226,7 +226,7 @@ enum MixedVariant : int {
     // ablations of the two update methods of Sec.3.2 (both are applied above)
     MIXED_RELIABLE = 2,   // reliable update only: r = b - A (x + y) in fp64, y is never
                           // folded into x (the solution stays in fp32)
-    MIXED_GROUPWISE = 3,  // group-wise update only: x += y in fp64, r never recomputed
+    MIXED_FOLD_ONLY = 3,  // solution folding only: x += y in fp64, y = 0, r never recomputed
 };
 
 // Finalisation applied to a reduced sum (by the one-block finalize kernel).
@@ -241,8 +241,8 @@ enum FinKind : int {
     FIN_CG_CHECK = 7,  // rr_true = sum, then accept or restart (plain CG)
     FIN_X0 = 8,        // |b - A x0|^2 = sum: residual state of a start from x0
     FIN_ACTIVATE = 9,  // a started slot begins iterating
-    FIN_GW = 10,       // group-wise-only variant: state after folding y into x
-    FIN_GW_CHECK = 11, // group-wise-only variant: rr_true = sum, accept or report
+    FIN_FOLD = 10,       // fold-only ablation: state after folding y into x
+    FIN_FOLD_CHECK = 11, // fold-only ablation: rr_true = sum, accept or report
     FIN_TRUE = 12,     // rr_true = sum
 };
 

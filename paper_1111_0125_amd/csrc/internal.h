@@ -150,6 +150,7 @@ struct SlotInit {
     double mass;
     stag_cg_params params;
     const void* x0 = nullptr;  // initial guess (fp64 internal layout, one RHS) or null: x = 0
+    bool x0_in_place = false;  // the slot's x64 block already holds the initial guess
 };
 
 void run_init(EngineRun& R, stag_engine* e, hipStream_t s, const void* b, size_t b_rs, int K,
@@ -161,14 +162,19 @@ void fill_stats(const RhsState& s, double secs, int inner_prec, stag_cg_stats* o
 bool flags_terminal(unsigned f);
 int status_of_flags(unsigned f);
 int default_graph_k(uint32_t Vh);
+// The buffers are cleared on init_stream, which is synchronised before return.
 int engine_create(stag_ctx* ctx, const stag_gauge* g, int prec, int N, bool serving,
-                  stag_engine** out);
+                  hipStream_t init_stream, stag_engine** out);
+// An fp16-storage solve that can hand over to fp32 gives up after this many
+// stall updates without halving the true residual (instead of max_stall).
+constexpr int kEscalateStalls = 3;
 
 }  // namespace stag
 
 namespace stag {
 
 int set_error(stag_ctx* ctx, int code, const char* fmt, ...);
+
 int dev_alloc(stag_ctx* ctx, size_t bytes, void** p);
 void dev_free(stag_ctx* ctx, void* p, size_t bytes);
 

@@ -432,7 +432,7 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
         case FIN_TRUE:
             s.rr_true = sum;
             break;
-        case FIN_GW: {
+        case FIN_FOLD: {
             // y has been folded into x; the iterated residual carries on (its
             // beta stays), after a stall from d = r
             const bool stall = (s.flags & F_STALL) != 0;
@@ -450,7 +450,7 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
             s.flags = F_ACTIVE;
             break;
         }
-        case FIN_GW_CHECK:
+        case FIN_FOLD_CHECK:
             s.rr_true = sum;
             s.flags = sum <= s.rr_stop ? F_DONE : ((s.flags & F_MAXIT) ? F_MAXIT : F_INACC);
             break;

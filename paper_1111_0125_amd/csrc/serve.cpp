@@ -20,10 +20,19 @@
 // A right-hand side's arithmetic does not depend on the other slots, the
 // kernel block size or when it started, so its result is the same bits alone
 // and in any mix.
+//
+// fp16-storage requests on a gauge that also holds fp32 links: a right-hand
+// side whose fp16 inner iteration stalls at its precision floor (ESTALL after
+// a few stall updates without progress) is handed over, as stag_cg_solve
+// does: it re-enters the queue ahead of new requests as a continuation that
+// starts from its current x in the gauge's fp32 batch (no stall restarts);
+// its statistics add up both passes and report inner_final = F32.
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <deque>
+#include <limits>
 #include <unordered_map>
 
 #include "internal.h"
@@ -41,6 +50,8 @@ struct Ticket {
     void* x_dev = nullptr;          // device result, canonical fp64 field layout
     size_t x_bytes = 0;
     std::vector<stag_cg_stats> stats;
+    std::vector<stag_cg_stats> first;  // per RHS: the fp16 pass of an escalated RHS
+    std::vector<char> escalated;       // per RHS: continued in fp32 from its x
     Clock::time_point t_submit, t_done;
     int remaining = 0;
     struct Batch* batch = nullptr;
@@ -48,6 +59,17 @@ struct Ticket {
     bool finishing = false;         // all slots harvested, waiting for done_ev
     bool done = false;
     bool cancelled = false;
+};
+
+// A unit of admission: right-hand sides `rhs` of ticket t to start in the
+// batch of (t->g, prec); a continuation starts them from the x held in the
+// ticket's result buffer.
+struct Work {
+    Ticket* t = nullptr;
+    int prec = 0;
+    std::vector<int> rhs;
+    bool cont = false;
+    hipEvent_t ready = nullptr;  // continuation: recorded after x was exported
 };
 
 struct Batch {
@@ -69,8 +91,13 @@ struct Serve {
     std::condition_variable cv;
     bool stop = false;
     bool started = false;
-    std::deque<Ticket*> queue;
+    std::deque<Work> queue;
     std::unordered_map<stag_ticket, Ticket*> tickets;
+    // uncollected tickets per gauge (stag_gauge_destroy refuses a gauge with any)
+    std::unordered_map<const stag_gauge*, int> gauge_refs;
+    // gauges whose batches the scheduler is asked to release (stag_gauge_destroy)
+    std::vector<const stag_gauge*> drop;
+    std::condition_variable drop_cv;
     stag_ticket next_id = 1;
     std::vector<Batch*> batches;  // scheduler thread only
     int slots = 16;
@@ -81,14 +108,17 @@ struct Serve {
 
 static int batch_create(Serve* S, const stag_gauge* g, int prec, Batch** out) {
     stag_ctx* ctx = S->ctx;
-    stag_engine* e = nullptr;
-    int rc = engine_create(ctx, g, prec, S->slots, true, &e);
-    if (rc) return rc;
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
-        engine_destroy(e);
         return set_error(ctx, STAG_EDEVICE, "serve: stream creation failed");
+    }
+    stag_engine* e = nullptr;
+    // cleared on the batch's own stream: other batches keep running meanwhile
+    int rc = engine_create(ctx, g, prec, S->slots, true, s, &e);
+    if (rc) {
+        (void)hipStreamDestroy(s);
+        return rc;
     }
     Batch* b = new Batch();
     b->e = e;
@@ -117,14 +147,18 @@ static void ticket_free(stag_ctx* ctx, Ticket* t) {
     delete t;
 }
 
-// Try to place ticket t into a batch. Returns STAG_OK when started,
+// Try to place work item w into a batch. Returns STAG_OK when started,
 // STAG_ENOMEM when it must wait, or another error that fails the ticket.
-static int admit(Serve* S, Ticket* t) {
+// Runs on the scheduler thread without S->mu: it touches only the batches
+// (scheduler-owned) and fields of a queued ticket that no other thread reads.
+static int admit(Serve* S, Work& w) {
     stag_ctx* ctx = S->ctx;
+    Ticket* t = w.t;
+    const int n = (int)w.rhs.size();
     Batch* bt = nullptr;
     for (Batch* b : S->batches) {
-        if (b->g != t->g || b->prec != t->prec) continue;
-        if ((int)b->slot_ticket.size() - b->busy >= t->nrhs) {
+        if (b->g != t->g || b->prec != w.prec) continue;
+        if ((int)b->slot_ticket.size() - b->busy >= n) {
             bt = b;
             break;
         }
@@ -137,7 +171,7 @@ static int admit(Serve* S, Ticket* t) {
         t->x_bytes = xb;
     }
     if (!bt) {
-        int rc = batch_create(S, t->g, t->prec, &bt);
+        int rc = batch_create(S, t->g, w.prec, &bt);
         if (rc == STAG_ENOMEM) {
             // release idle batches and retry once
             bool freed = false;
@@ -150,7 +184,7 @@ static int admit(Serve* S, Ticket* t) {
                     ++i;
                 }
             }
-            rc = freed ? batch_create(S, t->g, t->prec, &bt) : STAG_ENOMEM;
+            rc = freed ? batch_create(S, t->g, w.prec, &bt) : STAG_ENOMEM;
         }
         if (rc) return rc;
         S->batches.push_back(bt);
@@ -160,37 +194,66 @@ static int admit(Serve* S, Ticket* t) {
     stag_cg_params p;
     stag_cg_params_default(&p);
     p.tol = t->tol;
-    p.inner_prec = t->prec;
-    int r = 0;
-    for (int s = 0; s < (int)bt->slot_ticket.size() && r < t->nrhs; ++s) {
+    p.inner_prec = w.prec;
+    if (w.prec == P16S && (t->g->mask & STAG_MASK_F32))
+        p.max_stall = kEscalateStalls;  // somewhere to go: give up early
+    if (w.cont) {
+        // the fp32 continuation of a stalled fp16 pass: no stall restarts
+        p.use_x0 = 1;
+        p.stall_iters = std::numeric_limits<int>::max();
+    }
+    std::vector<int> taken;
+    auto release = [&]() {
+        for (int s : taken) bt->slot_ticket[s] = nullptr;
+    };
+    int k = 0;
+    for (int s = 0; s < (int)bt->slot_ticket.size() && k < n; ++s) {
         if (bt->slot_ticket[s]) continue;
+        const int r = w.rhs[k];
         bt->slot_ticket[s] = t;
         bt->slot_rhs[s] = r;
+        taken.push_back(s);
         // upload the canonical complex128 [Vh][3] vector into the slot's x64
-        // block (restarted from zero right after) and convert it into the
-        // engine's colour-major fp64 layout in b64
+        // block and convert it into the engine's colour-major fp64 layout in
+        // b64; x64 then starts from zero, or (continuation) from the ticket's
+        // current x, converted the same way
         const size_t off = (size_t)s * bt->e->rs64;
-        hipError_t err = hipMemcpyAsync((char*)bt->e->x64 + off, t->b.data() + (size_t)r * Vh * 6,
-                                        Vh * 48, hipMemcpyHostToDevice, bt->stream);
+        char* x64 = (char*)bt->e->x64 + off;
+        hipError_t err = hipMemcpyAsync(x64, t->b.data() + (size_t)r * Vh * 6, Vh * 48,
+                                        hipMemcpyHostToDevice, bt->stream);
         if (err == hipSuccess)
-            err = launch_import(P64, (char*)bt->e->x64 + off, (char*)bt->e->b64 + off, bt->e->rs64,
+            err = launch_import(P64, x64, (char*)bt->e->b64 + off, bt->e->rs64, (uint32_t)Vh, 1,
+                                bt->stream);
+        if (err == hipSuccess && w.cont && w.ready) err = hipStreamWaitEvent(bt->stream, w.ready, 0);
+        if (err == hipSuccess && w.cont)
+            err = launch_import(P64, (const char*)t->x_dev + (size_t)r * Vh * 48, x64, bt->e->rs64,
                                 (uint32_t)Vh, 1, bt->stream);
         if (err != hipSuccess) {
             (void)hipGetLastError();
+            release();
             return set_error(ctx, STAG_EDEVICE, "serve: right-hand side upload: %s",
                              hipGetErrorString(err));
         }
-        inits.push_back(SlotInit{s, t->mass, p});
-        ++r;
+        SlotInit si{s, t->mass, p};
+        si.x0_in_place = w.cont;
+        inits.push_back(si);
+        ++k;
     }
-    bt->busy += t->nrhs;
-    t->batch = bt;
-    t->remaining = t->nrhs;
     int hi = 0;
     for (int s = 0; s < (int)bt->slot_ticket.size(); ++s)
         if (bt->slot_ticket[s]) hi = s + 1;
+    const int hi_prev = bt->R.busy_hi;
     bt->R.busy_hi = std::max(bt->R.busy_hi, hi);
-    return run_start_slots(bt->R, inits);
+    int rc = run_start_slots(bt->R, inits);
+    if (rc) {
+        release();
+        bt->R.busy_hi = hi_prev;
+        return rc;
+    }
+    bt->busy += n;
+    t->batch = bt;
+    if (!w.cont) t->remaining = t->nrhs;
+    return STAG_OK;
 }
 
 // Harvest finished slots of a processed poll.
@@ -214,6 +277,34 @@ static void harvest(Serve* S, Batch* b, const RhsState* h) {
         }
         b->slot_ticket[s] = nullptr;
         b->busy -= 1;
+        if (t->escalated[r]) {
+            // the fp32 continuation ended: report both passes together
+            stag_cg_stats& a = t->stats[r];
+            const stag_cg_stats& f = t->first[r];
+            a.iters += f.iters;
+            a.reliable_updates += f.reliable_updates;
+            a.restarts += f.restarts;
+        } else if (b->prec == P16S && t->stats[r].status == STAG_ESTALL &&
+                   (t->g->mask & STAG_MASK_F32)) {
+            // fp16 storage hit its precision floor: continue in fp32 from x,
+            // which the export above has put into the result buffer; the
+            // continuation's upload runs on the fp32 batch's stream, so wait
+            // for the export before it is admitted
+            t->first[r] = t->stats[r];
+            t->escalated[r] = 1;
+            Work w;
+            w.t = t;
+            w.prec = P32;
+            w.rhs.push_back(r);
+            w.cont = true;
+            if (hipEventCreateWithFlags(&w.ready, hipEventDisableTiming) != hipSuccess ||
+                hipEventRecord(w.ready, b->stream) != hipSuccess) {
+                (void)hipGetLastError();
+                (void)hipStreamSynchronize(b->stream);
+            }
+            S->queue.push_front(w);
+            continue;
+        }
         t->remaining -= 1;
         if (t->remaining == 0) {
             if (!t->done_ev) (void)hipEventCreateWithFlags(&t->done_ev, hipEventDisableTiming);
@@ -228,37 +319,84 @@ static void harvest(Serve* S, Batch* b, const RhsState* h) {
     if (b->busy == 0) b->idle_since = Clock::now();
 }
 
+// Release the batches of the gauges stag_gauge_destroy asked for (under
+// S->mu; the gauge has no uncollected ticket, so its batches are idle apart
+// from blocks still in flight, which batch_destroy waits for).
+static void drop_batches(Serve* S) {
+    if (S->drop.empty()) return;
+    for (const stag_gauge* g : S->drop) {
+        for (size_t i = 0; i < S->batches.size();) {
+            if (S->batches[i]->g == g) {
+                batch_destroy(S->batches[i]);
+                S->batches.erase(S->batches.begin() + i);
+            } else {
+                ++i;
+            }
+        }
+    }
+    S->drop.clear();
+    S->drop_cv.notify_all();
+}
+
 static void scheduler(Serve* S) {
     stag_ctx* ctx = S->ctx;
     DeviceGuard dg(ctx->device);
-    std::vector<Ticket*> finishing;
     for (;;) {
         bool progress = false;
-        // ---- admission
+        // ---- admission: take the queue's current entries under the lock,
+        // admit them without it (batch creation clears device buffers and
+        // waits for that), then drop the admitted and failed ones. Only this
+        // thread removes entries or adds them at the front; submit appends.
+        std::vector<Work> cand;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             if (S->stop) break;
+            drop_batches(S);
             bool any_busy = false;
             for (Batch* b : S->batches) any_busy |= b->busy > 0;
-            if (S->queue.empty() && !any_busy && finishing.empty()) {
+            if (S->queue.empty() && !any_busy) {
                 S->cv.wait_for(lk, std::chrono::milliseconds(50));
                 if (S->stop) break;
+                drop_batches(S);
             }
-            for (size_t i = 0; i < S->queue.size();) {
-                Ticket* t = S->queue[i];
-                int rc = admit(S, t);
-                if (rc == STAG_OK) {
-                    S->queue.erase(S->queue.begin() + i);
+            cand.assign(S->queue.begin(), S->queue.end());
+        }
+        if (!cand.empty()) {
+            std::vector<int> rcs(cand.size());
+            for (size_t i = 0; i < cand.size(); ++i) rcs[i] = admit(S, cand[i]);
+            std::lock_guard<std::mutex> lk(S->mu);
+            std::deque<Work> keep;
+            for (size_t i = 0; i < cand.size(); ++i) {
+                Work& w = cand[i];
+                if (rcs[i] == STAG_ENOMEM) {
+                    keep.push_back(w);  // waits for memory
+                    continue;
+                }
+                if (w.ready) (void)hipEventDestroy(w.ready);
+                if (rcs[i] == STAG_OK) {
                     progress = true;
-                } else if (rc == STAG_ENOMEM) {
-                    ++i;  // waits for memory
                 } else {
-                    for (auto& st : t->stats) st.status = rc;
-                    t->done = true;
-                    t->t_done = Clock::now();
-                    S->queue.erase(S->queue.begin() + i);
+                    Ticket* t = w.t;
+                    for (int r : w.rhs) t->stats[r].status = rcs[i];
+                    if (w.cont) {
+                        // the other right-hand sides finish where they run; the
+                        // ticket completes when the last result copy has
+                        t->remaining -= 1;
+                        if (t->remaining == 0) {
+                            if (!t->done_ev)
+                                (void)hipEventCreateWithFlags(&t->done_ev, hipEventDisableTiming);
+                            (void)hipEventRecord(t->done_ev, t->batch ? t->batch->stream : nullptr);
+                            t->finishing = true;
+                        }
+                    } else {
+                        t->done = true;
+                        t->t_done = Clock::now();
+                    }
                 }
             }
+            // entries appended by submit meanwhile stay behind the kept ones
+            for (size_t i = cand.size(); i < S->queue.size(); ++i) keep.push_back(S->queue[i]);
+            S->queue.swap(keep);
         }
         // ---- device progress
         for (Batch* b : S->batches) {
@@ -340,7 +478,33 @@ int stag_serve_shutdown_internal(stag_ctx* ctx) {
     if (S->th.joinable()) S->th.join();
     for (Batch* b : S->batches) batch_destroy(b);
     for (auto& kv : S->tickets) ticket_free(ctx, kv.second);
+    for (Work& w : S->queue)
+        if (w.ready) (void)hipEventDestroy(w.ready);
     delete S;
+    return STAG_OK;
+}
+
+// stag_gauge_destroy: STAG_EBUSY while a serving ticket on g is uncollected;
+// otherwise the scheduler releases g's batches before this returns.
+int stag_serve_release_gauge_internal(stag_ctx* ctx, const stag_gauge* g) {
+    Serve* S = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        S = ctx->serve;
+    }
+    if (!S) return STAG_OK;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->gauge_refs.find(g);
+    if (it != S->gauge_refs.end() && it->second > 0)
+        return set_error(ctx, STAG_EBUSY,
+                         "stag_gauge_destroy: %d serving request(s) on this gauge not yet collected",
+                         it->second);
+    if (!S->started) return STAG_OK;
+    S->drop.push_back(g);
+    S->cv.notify_all();
+    S->drop_cv.wait(lk, [&]() {
+        return S->stop || std::find(S->drop.begin(), S->drop.end(), g) == S->drop.end();
+    });
     return STAG_OK;
 }
 
@@ -386,7 +550,13 @@ int stag_solver_submit(stag_ctx* ctx, const stag_gauge* g, double mass, int nrhs
         std::memset(&s, 0, sizeof(s));
         s.status = STAG_PENDING;
     }
+    t->first.resize(nrhs);
+    t->escalated.assign(nrhs, 0);
     t->t_submit = Clock::now();
+    Work w;
+    w.t = t;
+    w.prec = inner_prec;
+    for (int r = 0; r < nrhs; ++r) w.rhs.push_back(r);
     {
         std::lock_guard<std::mutex> lk(S->mu);
         if (S->queue.size() >= S->queue_cap) {
@@ -395,7 +565,8 @@ int stag_solver_submit(stag_ctx* ctx, const stag_gauge* g, double mass, int nrhs
         }
         t->id = S->next_id++;
         S->tickets[t->id] = t;
-        S->queue.push_back(t);
+        S->gauge_refs[g] += 1;
+        S->queue.push_back(w);
         if (!S->started) {
             S->started = true;
             S->th = std::thread(scheduler, S);
@@ -425,6 +596,7 @@ int stag_solver_poll(stag_ctx* ctx, stag_ticket ticket, double* x_host, stag_cg_
         t = it->second;
         if (!t->done) return STAG_PENDING;
         S->tickets.erase(it);
+        S->gauge_refs[t->g] -= 1;
     }
     DeviceGuard dg(ctx->device);
     int rc = STAG_OK;

@@ -51,7 +51,7 @@ void engine_destroy(stag_engine* e) {
 }
 
 int engine_create(stag_ctx* ctx, const stag_gauge* g, int prec, int N, bool serving,
-                  stag_engine** out) {
+                  hipStream_t init_stream, stag_engine** out) {
     stag_engine* e = new stag_engine();
     e->ctx = ctx;
     e->gauge = g;
@@ -118,15 +118,16 @@ int engine_create(stag_ctx* ctx, const stag_gauge* g, int prec, int N, bool serv
         return set_error(ctx, STAG_EDEVICE, "solver workspace: pinned staging");
     }
     // Every slot starts free, and the direction / y buffers must hold finite
-    // values (beta = 0 multiplies them). hipMemset runs on the null stream,
-    // which does not order against the non-blocking streams the solves use:
-    // wait for it here.
-    hipError_t err = hipMemset(e->st, 0, state_bytes(N));
-    if (err == hipSuccess) err = hipMemset(e->st1, 0, state_bytes(N));
-    if (err == hipSuccess && e->d64) err = hipMemset(e->d64, 0, N * e->rs64);
-    if (err == hipSuccess && e->d) err = hipMemset(e->d, 0, N * e->rsP);
-    if (err == hipSuccess && e->y32) err = hipMemset(e->y32, 0, N * e->rs32);
-    if (err == hipSuccess) err = hipDeviceSynchronize();
+    // values (beta = 0 multiplies them). Cleared on the given stream, which
+    // is then waited for (only it: other streams' work is not held up), so
+    // whatever stream the engine is used on later sees the cleared buffers.
+    hipStream_t s = init_stream;
+    hipError_t err = hipMemsetAsync(e->st, 0, state_bytes(N), s);
+    if (err == hipSuccess) err = hipMemsetAsync(e->st1, 0, state_bytes(N), s);
+    if (err == hipSuccess && e->d64) err = hipMemsetAsync(e->d64, 0, N * e->rs64, s);
+    if (err == hipSuccess && e->d) err = hipMemsetAsync(e->d, 0, N * e->rsP, s);
+    if (err == hipSuccess && e->y32) err = hipMemsetAsync(e->y32, 0, N * e->rs32, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
     if (err != hipSuccess) {
         (void)hipGetLastError();
         engine_destroy(e);
@@ -149,7 +150,7 @@ int engine_acquire(stag_ctx* ctx, const stag_gauge* g, int prec, int N, stag_eng
             }
     }
     stag_engine* e = nullptr;
-    int rc = engine_create(ctx, g, prec, N, false, &e);
+    int rc = engine_create(ctx, g, prec, N, false, ctx->stream, &e);
     if (rc) return rc;
     e->in_use = true;
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -427,22 +428,23 @@ hipError_t enqueue_check(const Ctx& c) {
 // stores x += y and y = 0 at its own site, forms r = b - A x with |r|^2 and
 // stores the inner residual q(r); the finalisation then finishes the slot
 // or carries the direction over (Eq.6), restarting it after a stall.
-// Ablations: the reliable update alone keeps y (r = b - A (x + y)); the
-// group-wise update alone folds y into x, leaves r as iterated and checks
-// the true residual only once the iterated one has met the tolerance.
+// Ablations splitting the update into its two ingredients: residual
+// replacement alone keeps y (r = b - A (x + y), the solution stays fp32);
+// folding alone (x += y, y = 0) leaves r as iterated and checks the true
+// residual only once the iterated one has met the tolerance.
 hipError_t enqueue_update(const Ctx& c) {
     stag_engine* e = c.e;
     const unsigned run = F_RU | F_STALL;
     hipError_t err;
-    if (c.variant == MIXED_GROUPWISE) {
+    if (c.variant == MIXED_FOLD_ONLY) {
         if ((err = vec(c, e->prec, OP_FOLD, {{e->x64, e->rs64}, {e->y32, e->rs32}}, FIN_STORE, run)))
             return err;
-        Reduce gw = make_red(e, FIN_GW);
+        Reduce gw = make_red(e, FIN_FOLD);
         gw.nparts = 0;  // a state transition: nothing to sum
         if ((err = timed_launch(c, KK_OTHER, [&]() { return launch_finalize(c.nk, gw, run, c.is); })))
             return err;
         if ((err = hop(c, P64, 1, EPI_PLAIN, e->x64, e->t64, nullptr, FIN_STORE, F_CHECK))) return err;
-        return hop(c, P64, 2, EPI_RESID, e->t64, e->r64, e->x64, FIN_GW_CHECK, F_CHECK);
+        return hop(c, P64, 2, EPI_RESID, e->t64, e->r64, e->x64, FIN_FOLD_CHECK, F_CHECK);
     }
     HopExtra x1;
     x1.lazy_y = e->y32;
@@ -608,13 +610,13 @@ int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots) {
     bool any_x0 = false;
     for (const SlotInit& si : slots) {
         RhsState& s = e->hstage[si.slot];
-        start_state(e, si.mass, si.params, si.x0 != nullptr, s);
+        const bool x0 = si.x0 != nullptr || si.x0_in_place;
+        start_state(e, si.mass, si.params, x0, s);
         RCK(hipMemcpyAsync(e->st + si.slot, &s, sizeof(RhsState), hipMemcpyHostToDevice, R.s));
-        if (si.x0) {
+        if (si.x0 && !si.x0_in_place)
             RCK(hipMemcpyAsync((char*)e->x64 + (size_t)si.slot * e->rs64, si.x0, e->rs64,
                                hipMemcpyDeviceToDevice, R.s));
-            any_x0 = true;
-        }
+        any_x0 |= x0;
         if (si.slot + 1 > R.busy_hi) R.busy_hi = si.slot + 1;
         // polls of blocks launched before this start show the slot's previous state
         R.start_after[si.slot] = R.launched - 1;

@@ -82,8 +82,8 @@ int main(void) {
     F(stag_cg_stats, seconds); F(stag_cg_stats, inner_final);
     F(stag_tune_cfg, S1); F(stag_tune_cfg, S2); F(stag_tune_cfg, nt); F(stag_tune_cfg, swizzle);
     printf("STAG_GAUGE_R12 %d STAG_MIXED_CARRY %d STAG_MIXED_RESTART %d STAG_MIXED_RELIABLE %d "
-           "STAG_MIXED_GROUPWISE %d STAG_TUNE_IMPROVED %d\n", STAG_GAUGE_R12, STAG_MIXED_CARRY,
-           STAG_MIXED_RESTART, STAG_MIXED_RELIABLE, STAG_MIXED_GROUPWISE, STAG_TUNE_IMPROVED);
+           "STAG_MIXED_FOLD_ONLY %d STAG_TUNE_IMPROVED %d\n", STAG_GAUGE_R12, STAG_MIXED_CARRY,
+           STAG_MIXED_RESTART, STAG_MIXED_RELIABLE, STAG_MIXED_FOLD_ONLY, STAG_TUNE_IMPROVED);
     return 0;
 }
 """
@@ -127,7 +127,7 @@ def test_binding_structs_match_the_header(tmp_path):
     assert consts == {"STAG_GAUGE_R12": s.GAUGE_R12, "STAG_MIXED_CARRY": s.MIXED_CARRY,
                       "STAG_MIXED_RESTART": s.MIXED_RESTART,
                       "STAG_MIXED_RELIABLE": s.MIXED_RELIABLE,
-                      "STAG_MIXED_GROUPWISE": s.MIXED_GROUPWISE,
+                      "STAG_MIXED_FOLD_ONLY": s.MIXED_FOLD_ONLY,
                       "STAG_TUNE_IMPROVED": s.TUNE_IMPROVED}
 
 

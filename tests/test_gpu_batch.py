@@ -20,7 +20,10 @@ def stag():
     return s
 
 
-def test_c4_block_solve_12_rhs(stag):
+@pytest.mark.parametrize("r12", [False, True])
+def test_c4_block_solve_12_rhs(stag, r12):
+    """With full links and with the 12-parameter f64 / f32 copies the
+    benchmark runs on; true residuals from the oracle's uncompressed A."""
     name = "c4_24x24x24x48"
     cfg = synth.CONFIGS[name]
     L, m, tol, n = cfg["L"], cfg["mass"], cfg["tol"], cfg["nrhs"]
@@ -29,7 +32,7 @@ def test_c4_block_solve_12_rhs(stag):
     b = synth.config_rhs(name)
     assert b.shape[0] == n == 12
     with stag.Context(0) as ctx:
-        g = ctx.gauge(L, U, precisions=("f64", "f32"))
+        g = ctx.gauge(L, U, precisions=("f64", "f32"), r12=r12)
         fb = ctx.field(g, 0, "f64", n).load(b)
         fx = ctx.field(g, 0, "f64", n)
         rc, st = stag.stag_cg_solve(ctx, g, [m] * n, fb, fx, stag.cg_params(tol=tol, inner="f32"))

@@ -30,16 +30,20 @@ def problem():
     return cfg, synth.config_links(NAME), synth.config_rhs(NAME)
 
 
-@pytest.mark.parametrize("inner", ["f16s", "f32", "f64"])
-def test_c3_solve_true_residual(stag, problem, inner):
+@pytest.mark.parametrize("inner,r12", [("f16s", False), ("f32", False), ("f64", False),
+                                       ("f16s", True), ("f32", True), ("f64", True)])
+def test_c3_solve_true_residual(stag, problem, inner, r12):
+    """With full links and with the 12-parameter f64 / f32 copies the
+    benchmark solves on (the fp16 copy is always full); the oracle's A uses
+    the uncompressed links."""
     cfg, U, b = problem
     L, m, tol = cfg["L"], cfg["mass"], cfg["tol"]
     with stag.Context(0) as ctx:
-        g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"))
+        g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"), r12=r12)
         fb = ctx.field(g, 0, "f64", 1).load(b)
         fx = ctx.field(g, 0, "f64", 1)
         rc, st = stag.stag_cg_solve(ctx, g, [m], fb, fx, stag.cg_params(tol=tol, inner=inner))
-        log(inner, rc, st[0])
+        log(inner, "r12" if r12 else "full", rc, st[0])
         assert rc == 0, st
         x = fx.store()
     r = b - oracle_apply_A(U, x, L, m)

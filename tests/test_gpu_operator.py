@@ -154,17 +154,21 @@ def test_block_operator_matches_single(stag, ctx, nrhs):
             assert rel_max(blk[r], so.store()[0]) <= (1e-14 if prec == "f64" else 1e-6)
 
 
+@pytest.mark.parametrize("r12", [False, True])
 @pytest.mark.parametrize("name", ["c4_24x24x24x48", "c3_32x32x32x64"])
-def test_apply_A_full_size(stag, ctx, name):
-    """A at the full benchmark lattices against the C oracle, all precisions."""
+def test_apply_A_full_size(stag, ctx, name, r12):
+    """A at the full benchmark lattices against the C oracle (which never
+    compresses links), every precision, with the links stored in full and in
+    the 12-parameter form the benchmark runs on (f64 / f32 copies)."""
     cfg = synth.CONFIGS[name]
     L = cfg["L"]
-    log("full-size A", name)
+    log("full-size A", name, "r12" if r12 else "full")
     U = synth.config_links(name)
-    g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"))
+    precs = ("f64", "f32") if r12 else ("f64", "f32", "f16s")
+    g = ctx.gauge(L, U, precisions=precs, r12=r12)
     v = synth.gaussian_rhs(L, 1, cfg["rhs_seed"])
     ref = oracle_apply_A(U, v, L, cfg["mass"])
-    for prec in ("f64", "f32", "f16s"):
+    for prec in precs:
         fi = ctx.field(g, 0, prec, 1).load(v)
         fo = ctx.field(g, 0, prec, 1)
         stag.stag_apply_A(ctx, g, [cfg["mass"]], fi, fo)

@@ -142,3 +142,72 @@ def test_destroy_with_pending_tickets(stag):
     for k in range(4):
         stag.stag_solver_submit(ctx, g, 0.01, synth.gaussian_rhs(L, 2, 400 + k), 1e-10, "f32")
     ctx.close()  # cancels whatever is pending; must return promptly
+
+
+def test_served_f16s_hard_request_hands_over_to_f32(stag):
+    """8^4 Haar links at m = 0.005, tol 1e-10: fp16 storage stalls at its
+    precision floor (the oracle's emulation does too: true residual ~0.5
+    after three stall updates). Served on a gauge that also holds fp32
+    links, each right-hand side hands over to the fp32 batch and reaches its
+    fp64 true residual (checked with the oracle's A), with the same bits and
+    iteration count as stag_cg_solve's own escalation of the same solve."""
+    L, m, tol = (8, 8, 8, 8), 0.005, 1e-10
+    U = synth.haar_links(L, 15)
+    b = synth.gaussian_rhs(L, 2, 1001)
+    with stag.Context(0) as ctx:
+        g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"))
+        tid = stag.stag_solver_submit(ctx, g, m, b, tol, "f16s")
+        res = wait_all(stag, ctx, {tid: (2, g.vh)})
+        rc, x, st, latency = res[tid]
+        log("served f16s", rc, st)
+        assert rc == 0, st
+        assert all(s["inner_final"] == stag.PREC["f32"] for s in st)
+        assert max(true_res(U, L, m, b, x)) <= tol
+        fb = ctx.field(g, 0, "f64", 2).load(b)
+        fx = ctx.field(g, 0, "f64", 2)
+        rc1, st1 = stag.stag_cg_solve(ctx, g, [m, m], fb, fx, stag.cg_params(tol=tol, inner="f16s"))
+        log("stag_cg_solve f16s", rc1, st1)
+        assert rc1 == 0 and all(s["inner_final"] == stag.PREC["f32"] for s in st1)
+        assert np.array_equal(fx.store(), x)
+        assert [s["iters"] for s in st1] == [s["iters"] for s in st]
+
+
+def test_served_f16s_without_f32_copy_reports_stall(stag):
+    """The same hard request on a gauge without fp32 links has nowhere to go:
+    it ends with ESTALL (and x is the last iterate), not a wrong success."""
+    L, m, tol = (8, 8, 8, 8), 0.005, 1e-10
+    U = synth.haar_links(L, 15)
+    b = synth.gaussian_rhs(L, 1, 1001)
+    with stag.Context(0) as ctx:
+        g = ctx.gauge(L, U, precisions=("f64", "f16s"))
+        tid = stag.stag_solver_submit(ctx, g, m, b, tol, "f16s")
+        rc, x, st, latency = wait_all(stag, ctx, {tid: (1, g.vh)}, timeout=300.0)[tid]
+        log("served f16s, no f32 copy", rc, st)
+        assert rc == stag.STAG_ESTALL and st[0]["status"] == stag.STAG_ESTALL
+        assert st[0]["inner_final"] == stag.PREC["f16s"]
+        assert st[0]["true_rel_res"] > tol
+
+
+def test_gauge_destroy_refused_while_requests_uncollected(stag):
+    """stag_gauge_destroy returns EBUSY while a serving request on the gauge
+    is uncollected, leaves the gauge usable, and succeeds once the ticket has
+    been polled (its serving batch released with it)."""
+    L, m, tol = (8, 8, 8, 8), 0.05, 1e-8
+    U = synth.haar_links(L, 17)
+    b = synth.gaussian_rhs(L, 1, 18)
+    with stag.Context(0) as ctx:
+        g = ctx.gauge(L, U, precisions=("f64", "f32"))
+        tid = stag.stag_solver_submit(ctx, g, m, b, tol, "f32")
+        with pytest.raises(stag.StagError) as ei:
+            g.destroy()
+        assert ei.value.code == stag.STAG_EBUSY and g.h is not None
+        rc, x, st, latency = wait_all(stag, ctx, {tid: (1, g.vh)})[tid]
+        assert rc == 0 and max(true_res(U, L, m, b, x)) <= tol
+        used = ctx.memory_used()
+        g.destroy()
+        assert g.h is None and ctx.memory_used() < used
+        # the context keeps serving other gauges
+        g2 = ctx.gauge(L, U, precisions=("f64", "f32"))
+        tid = stag.stag_solver_submit(ctx, g2, m, b, tol, "f32")
+        rc2, x2, st2, _ = wait_all(stag, ctx, {tid: (1, g2.vh)})[tid]
+        assert rc2 == 0 and np.array_equal(x2, x)

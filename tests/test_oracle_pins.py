@@ -312,7 +312,7 @@ def test_update_ablations_agree_when_well_conditioned():
     xd = np.linalg.solve(A, b.ravel()).reshape(-1, 3)
     ev = np.linalg.eigvalsh(A)
     iters = set()
-    for upd in ("both", "reliable", "groupwise"):
+    for upd in ("both", "reliable", "fold_only"):
         x, st = stag.mixed_cg(U, L, m, b, tol, prec="f32", update=upd)
         assert st["status"] == "ok", (upd, st)
         res = math.sqrt(stag.norm2(b - stag.apply_A(U, x, L, m)) / stag.norm2(b))
@@ -324,9 +324,10 @@ def test_update_ablations_agree_when_well_conditioned():
 
 def test_both_updates_are_needed():
     """Sec.3.2 applies the reliable and the group-wise update together: near a
-    tolerance fp32 cannot hold, the reliable update alone keeps the solution
-    in fp32 and stalls far above it, and the group-wise update alone lets the
-    iterated residual drift from the true one, which then misses it."""
+    tolerance fp32 cannot hold, replacing the residual alone (the reliable
+    update without folding y into x) keeps the solution in fp32 and stalls far
+    above it, and folding y into x alone (without the residual recompute)
+    lets the iterated residual drift from the true one, which then misses it."""
     L, m, tol = (4, 4, 4, 4), 0.1, 1e-10
     U = synth.haar_links(L, 11)
     b = synth.gaussian_rhs(L, 1, 111)[0]
@@ -337,7 +338,7 @@ def test_both_updates_are_needed():
     # the reported residual is that of the returned x = x + y
     res = math.sqrt(stag.norm2(b - stag.apply_A(U, x, L, m)) / stag.norm2(b))
     assert abs(res - rel["true_rel_res"]) <= 1e-12
-    x, gw = stag.mixed_cg(U, L, m, b, tol, prec="f32", update="groupwise")
+    x, gw = stag.mixed_cg(U, L, m, b, tol, prec="f32", update="fold_only")
     assert gw["status"] == "inaccurate" and gw["true_rel_res"] > 10 * tol
     assert abs(gw["iters"] - both["iters"]) <= 0.05 * both["iters"]
 
