@@ -190,6 +190,21 @@ int stag_dslash(stag_ctx* ctx, const stag_gauge* gauge, const stag_field* in, st
 int stag_apply_A(stag_ctx* ctx, const stag_gauge* gauge, const double* mass, const stag_field* in,
                  stag_field* out, void* stream);
 
+/* stag_apply_A_noalloc: stag_apply_A for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and the same bits as stag_apply_A, but
+ * the temporary odd-parity vector lives in a device scratch array of
+ * STAG_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends (its address is looked up by stag_create); the call
+ * allocates and frees nothing. The caller passes the fields as for
+ * stag_apply_A. Errors: as stag_apply_A, plus EINVAL when the intermediate
+ * (nrhs * Vh * 48 bytes for F64, * 24 for F32, * 16 for F16S) exceeds the
+ * scratch. Every call on one GPU shares that GPU's scratch: calls whose work
+ * overlaps on the device (on different streams, or from several contexts on
+ * the same GPU) race; calls on one stream are ordered and safe. */
+#define STAG_NOALLOC_SCRATCH_BYTES ((size_t)48 << 20)
+int stag_apply_A_noalloc(stag_ctx* ctx, const stag_gauge* gauge, const double* mass,
+                         const stag_field* in, stag_field* out, void* stream);
 
 /* ---------------------------------------------------------------- solver */
 typedef struct stag_cg_params {

@@ -33,6 +33,7 @@ STAG_ENOCONV = -4
 STAG_EBREAKDOWN = -5
 STAG_ESTALL = -6
 STAG_EBUSY = -7
+NOALLOC_SCRATCH_BYTES = 48 << 20  # STAG_NOALLOC_SCRATCH_BYTES
 STAG_ENOTFOUND = -8
 
 F64, F32, F16S = 0, 1, 2
@@ -123,6 +124,7 @@ def _load():
         "stag_field_destroy": ([vp], ip),
         "stag_dslash": ([vp, vp, vp, vp, vp], ip),
         "stag_apply_A": ([vp, vp, ctypes.POINTER(dp), vp, vp, vp], ip),
+        "stag_apply_A_noalloc": ([vp, vp, ctypes.POINTER(dp), vp, vp, vp], ip),
         "stag_cg_params_default": ([ctypes.POINTER(CgParams)], None),
         "stag_cg_solve": ([vp, vp, ctypes.POINTER(dp), vp, vp, ctypes.POINTER(CgParams),
                            ctypes.POINTER(CgStats), vp], ip),
@@ -305,6 +307,14 @@ def stag_apply_A(ctx: Context, gauge: Gauge, mass, fin: Field, fout: Field, stre
     m = np.broadcast_to(np.asarray(mass, dtype=np.float64), (fin.nrhs,)).copy()
     mp = m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return ctx.check(lib.stag_apply_A(ctx.h, gauge.h, mp, fin.h, fout.h, _stream(stream)))
+
+
+def stag_apply_A_noalloc(ctx: Context, gauge: Gauge, mass, fin: Field, fout: Field, stream=None):
+    """stag_apply_A with its intermediate in the library's device scratch
+    (allocates nothing; intermediates up to NOALLOC_SCRATCH_BYTES)."""
+    m = np.broadcast_to(np.asarray(mass, dtype=np.float64), (fin.nrhs,)).copy()
+    mp = m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return ctx.check(lib.stag_apply_A_noalloc(ctx.h, gauge.h, mp, fin.h, fout.h, _stream(stream)))
 
 
 def cg_params(tol=1e-8, inner="f64", max_iter=0, delta=0.1, stall_iters=0, max_stall=20,

@@ -39,6 +39,7 @@ UNITS = [
     ("blas.hip", "blas.o", []),
     ("layout.hip", "layout.o", []),
     ("tiny.hip", "tiny.o", []),
+    ("scratch.hip", "scratch.o", []),
     ("capi.cpp", "capi.o", []),
     ("solver.cpp", "solver.o", []),
     ("serve.cpp", "serve.o", []),

@@ -199,9 +199,18 @@ int stag_create(int device, size_t hbm_budget_bytes, stag_ctx** out) {
         (void)hipGetLastError();
         return set_error(nullptr, STAG_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
     }
+    void* scr = nullptr;
+    e = scratch_init(device, &scr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamDestroy(s);
+        return set_error(nullptr, STAG_EDEVICE, "stag_create: scratch address: %s",
+                         hipGetErrorString(e));
+    }
     stag_ctx* c = new stag_ctx();
     c->device = device;
     c->stream = s;
+    c->scratch = scr;
     if (hbm_budget_bytes == 0) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) == hipSuccess) c->budget = fr;
@@ -651,6 +660,24 @@ int stag_apply_A(stag_ctx* ctx, const stag_gauge* g, const double* mass, const s
     rc = apply_A_stages(ctx, g, mass, in, out, t, s);
     HIPCK(ctx, hipFreeAsync(t, s));
     return rc;
+}
+
+int stag_apply_A_noalloc(stag_ctx* ctx, const stag_gauge* g, const double* mass,
+                         const stag_field* in, stag_field* out, void* stream) {
+    if (!ctx) return STAG_EINVAL;
+    int rc = check_apply_A(ctx, g, mass, in, out, "stag_apply_A_noalloc");
+    if (rc) return rc;
+    const size_t need = in->rs * (size_t)in->nrhs;
+    if (need > kScratchBytes)
+        return set_error(ctx, STAG_EINVAL,
+                         "stag_apply_A_noalloc: the odd intermediate needs %zu bytes, more than "
+                         "the %zu-byte device scratch",
+                         need, kScratchBytes);
+    if (!ctx->scratch) return set_error(ctx, STAG_EDEVICE, "stag_apply_A_noalloc: no scratch");
+    DeviceGuard dg(ctx->device);
+    // every hop-stage-1 output site is written before stage 2 reads it, so
+    // nothing in the scratch needs clearing
+    return apply_A_stages(ctx, g, mass, in, out, ctx->scratch, pick_stream(ctx, stream));
 }
 
 void stag_cg_params_default(stag_cg_params* p) {

@@ -56,6 +56,7 @@ struct Timing {
 struct stag_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    void* scratch = nullptr;       // this device's copy of the scratch array (scratch.hip)
     size_t budget = 0;
     std::atomic<size_t> used{0};
     std::mutex mu;                 // guards the object lists and the workspace pool
@@ -175,6 +176,12 @@ namespace stag {
 
 int set_error(stag_ctx* ctx, int code, const char* fmt, ...);
 
+// The device scratch array of the allocation-free entry points (scratch.hip):
+// kScratchBytes per GPU, held until the process ends. scratch_init returns
+// its device address on `device`, which must be current (looked up once per
+// device and kept).
+constexpr size_t kScratchBytes = (size_t)48 << 20;
+hipError_t scratch_init(int device, void** out);
 int dev_alloc(stag_ctx* ctx, size_t bytes, void** p);
 void dev_free(stag_ctx* ctx, void* p, size_t bytes);
 

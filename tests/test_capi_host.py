@@ -43,6 +43,7 @@ def test_null_and_bad_arguments_rejected_on_host():
     assert lib.stag_field_import(None, None, 0, None) == s.STAG_EINVAL
     assert lib.stag_dslash(None, None, None, None, None) == s.STAG_EINVAL
     assert lib.stag_apply_A(None, None, None, None, None, None) == s.STAG_EINVAL
+    assert lib.stag_apply_A_noalloc(None, None, None, None, None, None) == s.STAG_EINVAL
     assert lib.stag_cg_solve(None, None, None, None, None, None, None, None) == s.STAG_EINVAL
     assert lib.stag_solver_submit(None, None, 0.1, 1, None, 1e-8, 1, None) == s.STAG_EINVAL
     assert lib.stag_solver_poll(None, 1, None, None, None) == s.STAG_EINVAL
