@@ -95,6 +95,85 @@ def measured_traffic(kernel, links):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
+A_SHAPES = [(S, nt, sw) for nt in (1, 0) for sw in (1, 0) for S in (1, 2, 4)]
+A_TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                 "a_apply_32x32x32x64_hbm_traffic.md")
+
+
+def summary_blob(path):
+    """The JSON block of a committed counter summary, or None."""
+    try:
+        with open(path) as f:
+            txt = f.read()
+        return json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+
+
+def a_leg_traffic(leg, shape):
+    """HBM bytes per A application of leg `leg` in launch shape `shape` from the
+    committed 32^3x64 counter summary, when it was taken on these sources; else None."""
+    blob = summary_blob(A_TRAFFIC_SUMMARY)
+    if not blob or blob.get("kernel_src_sha256") != csrc_digest():
+        return None
+    key = f"{leg} S={shape['S1']} nt={shape['nt']} swizzle={shape['swizzle']}"
+    v = blob.get("legs", {}).get(key)
+    return None if v is None else v.get("hbm_bytes_per_A")
+
+
+def a_apply_leg(stag, torch, costs, ctx, g, leg, prec, v, mass, reps, improved=False, r12=False,
+                sweep_reps=10, order=None):
+    """A on one gauge copy: every launch shape (lanes per site S for both stages,
+    non-temporal link loads, XCD-aware block order) timed over `sweep_reps`
+    back-to-back applications after 3 warm-ups, then the fastest over `reps`,
+    between torch events on the stream the library launches on. `order`
+    collects (leg, shape, applications) in launch order for the counter
+    summary."""
+    vh = g.vh
+    stream = torch.cuda.current_stream()
+    fi = ctx.field(g, 0, prec, 1).load(v)
+    fo = ctx.field(g, 0, prec, 1)
+
+    def run(shape, k):
+        S, nt, sw = shape
+        stag.stag_tune_set(ctx, prec, 1, vh, S1=S, S2=S, nt=nt, swizzle=sw, improved=improved)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        for _ in range(3):
+            stag.stag_apply_A(ctx, g, [mass], fi, fo, stream=stream)
+        e0.record(stream)
+        for _ in range(k):
+            stag.stag_apply_A(ctx, g, [mass], fi, fo, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if order is not None:
+            order.append({"leg": leg, "S": S, "nt": nt, "swizzle": sw, "applications": 3 + k})
+        return e0.elapsed_time(e1) / k
+
+    sweep = {f"S={S} nt={nt} swizzle={sw}": round(run((S, nt, sw), sweep_reps) * 1e3, 2)
+             for S, nt, sw in A_SHAPES}
+    best = min(A_SHAPES, key=lambda t: sweep[f"S={t[0]} nt={t[1]} swizzle={t[2]}"])
+    ms = run(best, reps)
+    fi.destroy()
+    fo.destroy()
+    byts = vh * costs.a_bytes_per_site(prec, r12=r12, improved=improved)
+    gbs = byts / (ms * 1e-3) / 1e9
+    paper_b = vh * costs.paper_a_bytes_per_site(prec, r12=r12 and prec != "f16s", improved=improved)
+    shape = {"S1": best[0], "S2": best[0], "nt": best[1], "swizzle": best[2]}
+    out = {"us_per_A": round(ms * 1e3, 2), "GB/s": round(gbs, 1),
+           "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
+           # every neighbour read counted, as the paper counts (Sec.2)
+           "paper_convention_GB/s": round(paper_b / (ms * 1e-3) / 1e9, 1),
+           "GFLOP/s": round(vh * costs.a_flops_per_site(improved=improved) / (ms * 1e-3) / 1e9, 1),
+           "bytes_per_A": byts, "shape": shape, "sweep_us_per_A": sweep}
+    t = a_leg_traffic(leg, shape)
+    out["traffic_bytes_per_A"] = t
+    out["traffic_ratio"] = None if t is None else round(t / byts, 4)
+    log("A-apply 32^3x64", leg, {k: out[k] for k in ("us_per_A", "GB/s", "frac_of_8TBs", "shape",
+                                                    "traffic_ratio")})
+    return out
+
+
 @functools.lru_cache(maxsize=1)
 def c3_inputs(synth):
     name = "c3_32x32x32x64"
@@ -102,12 +181,12 @@ def c3_inputs(synth):
     return synth.config_links(name), synth.config_rhs(name)
 
 
-def improved_32(stag, torch, costs, synth, reps=30, solves=True):
+def improved_32(stag, torch, costs, synth, reps=30, solves=True, order=None):
     """The improved operator (fat links + three-hop long links) on 32^3 x 64:
     fields from the Haar links of the 32^3 x 64 workload (fat = 9/8 U plus
     0.05 complex normal noise, long = -1/24 U U U), A-apply bandwidth per
-    precision and time to 1e-10 at m = 0.01, fp32-inner mixed CG against
-    plain fp64 CG."""
+    precision (each in its fastest launch shape) and time to 1e-10 at m = 0.01,
+    fp32-inner mixed CG against plain fp64 CG."""
     name = "c3_32x32x32x64"
     cfg = synth.CONFIGS[name]
     L, m, tol = cfg["L"], 0.01, 1e-10
@@ -120,34 +199,11 @@ def improved_32(stag, torch, costs, synth, reps=30, solves=True):
     with stag.Context(0) as ctx:
         g = ctx.gauge(L, fat, precisions=("f64", "f32", "f16s"), long=lng)
         del fat, lng
-        vh = g.vh
-        stream = torch.cuda.current_stream()
         for prec in ("f64", "f32", "f16s"):
-            cfgt, _ = stag.stag_tune(ctx, g, prec, 1)
-            fi = ctx.field(g, 0, prec, 1).load(v)
-            fo = ctx.field(g, 0, prec, 1)
-            for _ in range(5):
-                stag.stag_apply_A(ctx, g, [m], fi, fo, stream=stream)
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(reps):
-                stag.stag_apply_A(ctx, g, [m], fi, fo, stream=stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            byts = vh * costs.a_bytes_per_site(prec, improved=True)
-            gbs = byts / (ms * 1e-3) / 1e9
-            paper_b = vh * costs.paper_a_bytes_per_site(prec, improved=True)
-            out["A_" + prec] = {"us_per_A": round(ms * 1e3, 2), "GB/s": round(gbs, 1),
-                                "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
-                                "paper_convention_GB/s": round(paper_b / (ms * 1e-3) / 1e9, 1),
-                                "GFLOP/s": round(vh * costs.a_flops_per_site(improved=True)
-                                                 / (ms * 1e-3) / 1e9, 1),
-                                "bytes_per_A": byts, "tune": cfgt}
-            log("improved A-apply", prec, out["A_" + prec])
-            fi.destroy()
-            fo.destroy()
+            out["A_" + prec] = a_apply_leg(stag, torch, costs, ctx, g, "improved_" + prec, prec, v,
+                                           m, reps, improved=True, order=order)
+        for prec in (("f32", "f64") if solves else ()):
+            stag.stag_tune(ctx, g, prec, 1)  # the solver's iteration kernels
         fb = ctx.field(g, 0, "f64", 1).load(b)
         fx = ctx.field(g, 0, "f64", 1)
         for inner in (("f32", "f64") if solves else ()):
@@ -201,10 +257,10 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
     return round(gbs, 1)
 
 
-def a_apply_bandwidth(stag, torch, costs, synth, reps=50):
+def a_apply_bandwidth(stag, torch, costs, synth, reps=50, order=None):
     """GB/s of A = both hop stages on the 32^3 x 64 lattice, per precision,
-    full and 12-parameter links, timed with torch events on the stream the
-    library launches on."""
+    full and 12-parameter links, each in its fastest launch shape, timed with
+    torch events on the stream the library launches on."""
     name = "c3_32x32x32x64"
     cfg = synth.CONFIGS[name]
     L = cfg["L"]
@@ -213,36 +269,12 @@ def a_apply_bandwidth(stag, torch, costs, synth, reps=50):
     out = {}
     for r12 in (False, True):
         with stag.Context(0) as ctx:
-            g = ctx.gauge(L, U, precisions=("f64", "f32") if r12 else ("f64", "f32", "f16s"), r12=r12)
-            vh = g.vh
-            stream = torch.cuda.current_stream()
-            for prec in (("f64", "f32") if r12 else ("f64", "f32", "f16s")):
-                cfgt, _ = stag.stag_tune(ctx, g, prec, 1)
-                fi = ctx.field(g, 0, prec, 1).load(v)
-                fo = ctx.field(g, 0, prec, 1)
-                for _ in range(5):
-                    stag.stag_apply_A(ctx, g, [cfg["mass"]], fi, fo, stream=stream)
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                for _ in range(reps):
-                    stag.stag_apply_A(ctx, g, [cfg["mass"]], fi, fo, stream=stream)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                ms = e0.elapsed_time(e1) / reps
-                byts = vh * costs.a_bytes_per_site(prec, r12=r12)
-                gbs = byts / (ms * 1e-3) / 1e9
+            precs = ("f64", "f32") if r12 else ("f64", "f32", "f16s")
+            g = ctx.gauge(L, U, precisions=precs, r12=r12)
+            for prec in precs:
                 key = prec + ("_r12" if r12 else "")
-                paper_b = vh * costs.paper_a_bytes_per_site(prec, r12=r12 and prec != "f16s")
-                out[key] = {"us_per_A": round(ms * 1e3, 2), "GB/s": round(gbs, 1),
-                            "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
-                            # every neighbour read counted, as the paper counts (Sec.2)
-                            "paper_convention_GB/s": round(paper_b / (ms * 1e-3) / 1e9, 1),
-                            "GFLOP/s": round(vh * costs.a_flops_per_site() / (ms * 1e-3) / 1e9, 1),
-                            "bytes_per_A": byts, "tune": cfgt}
-                log("A-apply 32^3x64", key, out[key])
-                fi.destroy()
-                fo.destroy()
+                out[key] = a_apply_leg(stag, torch, costs, ctx, g, key, prec, v, cfg["mass"], reps,
+                                       r12=r12, order=order)
     return out
 
 
@@ -321,13 +353,50 @@ def batched_c4(stag, torch, synth):
     return out
 
 
+def c1_gpu(stag, torch, synth, solves=20):
+    """The 4^4 workload (Haar links, m = 0.1, 1e-10) on the GPU: the
+    one-workgroup solver in fp64 (Fig.1) and with fp32 inner iterations
+    (Sec.3.2), median over `solves` solves from b resident in HBM."""
+    import statistics
+    name = "c1_4x4x4x4"
+    cfg = synth.CONFIGS[name]
+    L, m, tol = cfg["L"], cfg["mass"], cfg["tol"]
+    U, b = synth.config_links(name), synth.config_rhs(name)
+    out = {"lattice": list(L), "mass": m, "tol": tol, "solver": "one workgroup per right-hand side"}
+    with stag.Context(0) as ctx:
+        g = ctx.gauge(L, U, precisions=("f64", "f32"))
+        fb = ctx.field(g, 0, "f64", 1).load(b)
+        fx = ctx.field(g, 0, "f64", 1)
+        for inner in ("f64", "f32"):
+            p = stag.cg_params(tol=tol, inner=inner)
+            stag.stag_cg_solve(ctx, g, [m], fb, fx, p)
+            ts = []
+            for _ in range(solves):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc, st = stag.stag_cg_solve(ctx, g, [m], fb, fx, p)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            out[inner] = {"time_to_1e-10_ms": round(statistics.median(ts) * 1e3, 3), "status": rc,
+                          "iters": st[0]["iters"], "true_rel_res": st[0]["true_rel_res"]}
+    log("c1 4^4", out)
+    return out
+
+
+# Requests per second the full serving stream below drains at when offered
+# more than it can take (80 requests at 2/s on one MI355X, fp32 inner):
+# the capacity its default arrival rate is set against.
+SERVE_CAPACITY_RPS = 1.27
+
+
 def serving(stag, synth, n_requests=40, rate=None, full=False, seed=2011):
     """A Poisson stream of solve requests over resident gauge fields,
     continuously batched per gauge; solves/s and submit-to-finish latency.
-    Default: a light stream over 8^4 and 16^3x32 with smooth links. full:
-    the four resident Haar fields 8^4, 16^3x32, 24^3x48, 32^3x64 (gauge
-    seeds 15-18), masses {0.005, 0.01, 0.05, 0.1} (long: 32^3x64 at
-    m = 0.005 takes seconds per solve)."""
+    full (the benchmark's default): the four resident Haar fields 8^4,
+    16^3x32, 24^3x48, 32^3x64 (gauge seeds 15-18), masses {0.005, 0.01,
+    0.05, 0.1}, tolerances {1e-6, 1e-8, 1e-10}, 1-8 right-hand sides, at
+    half the stream's measured capacity unless `rate` is given. Otherwise a
+    light stream over 8^4 and 16^3x32 with smooth links."""
     import numpy as np
     if full:
         sizes = [(8, 8, 8, 8), (16, 16, 16, 32), (24, 24, 24, 48), (32, 32, 32, 64)]
@@ -341,7 +410,7 @@ def serving(stag, synth, n_requests=40, rate=None, full=False, seed=2011):
         # the same smooth-link recipe as the 16^3 x 32 workload (exp(i 0.3 H))
         links = [synth.exp_ih_links(L, 15 + i, 0.3) for i, L in enumerate(sizes)]
     tols = [1e-6, 1e-8, 1e-10]
-    rate = rate or (50.0 if not full else 2.0)
+    rate = rate or (50.0 if not full else 0.5 * SERVE_CAPACITY_RPS)
     reqs = synth.request_stream(seed, n_requests, rate, sizes, masses, tols, max_nrhs=8)
     lat, nrhs_done = [], 0
     lat_by = {i: [] for i in range(len(sizes))}
@@ -383,6 +452,8 @@ def serving(stag, synth, n_requests=40, rate=None, full=False, seed=2011):
            "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
            "arrival_rate_per_s": rate,
+           "rho_vs_capacity": (round(rate / SERVE_CAPACITY_RPS, 3) if full else None),
+           "capacity_requests_per_s": SERVE_CAPACITY_RPS if full else None,
            "lattices": ["x".join(map(str, L)) for L in sizes],
            "links": "Haar" if full else "exp(i 0.3 H)",
            "p50_p99_by_lattice_s": {"x".join(map(str, sizes[i])): [
@@ -464,11 +535,13 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the fp64 / f16s comparison solves and the 32^3x64 A-apply")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--serve-full", action="store_true",
-                    help="serving stream over all four lattice sizes (long)")
-    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-light", action="store_true",
+                    help="light serving stream (8^4 and 16^3x32, smooth links) instead of the "
+                         "stream over all four Haar lattices")
+    ap.add_argument("--serve-requests", type=int, default=80)
     ap.add_argument("--serve-rate", type=float, default=0.0,
-                    help="request arrival rate per second (default: 50 light, 2 full)")
+                    help="request arrival rate per second (default: half the measured capacity "
+                         "of the full stream; 50 light)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only tune and launch the iteration kernels (as timed for the roofline), "
                          "then a 256 MiB copy kernel: the program that hardware-counter runs profile")
@@ -486,6 +559,11 @@ def main():
         sys.exit(2)
 
     import numpy as np  # noqa: F401
+    import tempfile
+
+    # persistent launch-shape table (stag_tune reads it before timing shapes)
+    os.environ.setdefault("STAG_TUNE_CACHE", os.path.join(tempfile.gettempdir(),
+                                                          "stag_tune_cache.txt"))
     import torch
 
     import paper_1111_0125_amd as stag
@@ -494,9 +572,16 @@ def main():
 
     if args.a_apply_only:
         torch.cuda.init()
-        out = {"a_apply_32x32x32x64": a_apply_bandwidth(stag, torch, costs, synth),
-               "improved_32x32x32x64": improved_32(stag, torch, costs, synth, solves=False),
-               "copy_kernel_GB/s": copy_bandwidth(torch)}
+        order = []
+        out = {"a_apply_32x32x32x64": a_apply_bandwidth(stag, torch, costs, synth, order=order),
+               "improved_32x32x32x64": improved_32(stag, torch, costs, synth, solves=False,
+                                                   order=order),
+               "copy_kernel_GB/s": copy_bandwidth(torch),
+               # what the counter summary needs to attribute dispatches: every
+               # (leg, shape) in launch order, each application two hop kernels,
+               # then the 1 GiB copy kernel (3 + 20 launches)
+               "launch_order": order, "copy_bytes_each_way": 1 << 30,
+               "kernel_src_sha256": csrc_digest()}
         print(json.dumps(out), flush=True)
         return
 
@@ -506,12 +591,16 @@ def main():
     U = synth.config_links(WORKLOAD)
     b = synth.config_rhs(WORKLOAD)
     torch.cuda.init()
+    if args.kernels_only:
+        # the counter runs time every launch shape: no shapes from a table
+        os.environ.pop("STAG_TUNE_CACHE", None)
     ctx = stag.Context(0)
     r12 = not args.full_links
     g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"), r12=r12)
     vh = g.vh
     tunes = {p: stag.stag_tune(ctx, g, p, 1)[0] for p in ("f64", "f32", "f16s")}
-    log("tuned", tunes)
+    loaded, measured = stag.stag_tune_counts(ctx)
+    log("tuned", tunes, "loaded from the table:", loaded, "measured:", measured)
     inner = args.inner
     if args.kernels_only:
         us = stag.stag_time_kernels(ctx, g, inner, 1, reps=20)
@@ -523,6 +612,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"kernels_only": True, "tune": tunes[inner], "us": us,
                           "kernel_names": kernel_names(tunes[inner], inner),
+                          "inner": inner, "links": "r12" if r12 else "full", "vh": vh,
                           "copy_bytes_read": n * 4, "copy_bytes_written": n * 4,
                           "kernel_src_sha256": csrc_digest()}), flush=True)
         return
@@ -591,6 +681,8 @@ def main():
                       inner, True, r12=r12 and inner != "f16s") * vh},
         "kernels": kinds,
         "tune": tunes,
+        "tune_table": {"path": os.environ.get("STAG_TUNE_CACHE"), "loaded": loaded,
+                       "measured": measured},
     }
 
     fp64_iters = None
@@ -647,8 +739,9 @@ def main():
         result["improved_32x32x32x64"] = improved_32(stag, torch, costs, synth)
         c3_inputs.cache_clear()
         result["batched_24x24x24x48_12rhs"] = batched_c4(stag, torch, synth)
+        result["c1_4x4x4x4_gpu"] = c1_gpu(stag, torch, synth)
         result["serving"] = serving(stag, synth, n_requests=args.serve_requests,
-                                    rate=args.serve_rate or None, full=args.serve_full)
+                                    rate=args.serve_rate or None, full=not args.serve_light)
 
     if not args.no_cpu:
         if fp64_iters is None:
@@ -660,6 +753,10 @@ def main():
                 fp64_iters = st[0]["iters"]
         result["cpu_baseline"] = cpu_baseline(synth, L, U, b[0], mass, fp64_iters, args.cpu_seconds)
         result["cpu_baseline"]["a_apply_fp64"] = cpu_a_apply(synth, costs)
+        c1 = result.get("c1_4x4x4x4_gpu")
+        if c1:
+            c1["cpu_oracle_fp64_cg_ms"] = result["cpu_baseline"]["a_apply_fp64"]["c1_4x4x4x4"].get(
+                "cg_to_tol_ms")
     print(json.dumps(result), flush=True)
 
 

@@ -354,6 +354,15 @@ int stag_tune_get(stag_ctx* ctx, int prec, int nrhs, int64_t vh, stag_tune_cfg* 
 int stag_tune_set(stag_ctx* ctx, int prec, int nrhs, int64_t vh, const stag_tune_cfg* cfg);
 int stag_tune(stag_ctx* ctx, const stag_gauge* gauge, int prec, int nrhs, stag_tune_cfg* best,
               double* best_ms);
+/* Persistent tune table: when the environment variable STAG_TUNE_CACHE names
+ * a file, stag_tune first looks the shape up there, keyed by (device
+ * architecture, operator, link form, sites per parity, precision, kernel
+ * right-hand-side count), and times the shapes only on a miss, appending the
+ * result (one text line per entry; the last entry of a key wins; an
+ * unreadable or unwritable file only means measuring). stag_tune_counts:
+ * how many stag_tune calls on ctx were answered from the file (loaded) and
+ * how many timed the shapes (measured). Errors: EINVAL (null argument). */
+int stag_tune_counts(const stag_ctx* ctx, int* loaded, int* measured);
 
 /* ---------------------------------------------------------------- timing
  * While enabled, stag_cg_solve launches its kernels eagerly (no graph) and

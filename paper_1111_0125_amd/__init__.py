@@ -131,6 +131,7 @@ def _load():
         "stag_tune_get": ([vp, ip, ip, ctypes.c_int64, ctypes.POINTER(TuneCfg)], ip),
         "stag_tune_set": ([vp, ip, ip, ctypes.c_int64, ctypes.POINTER(TuneCfg)], ip),
         "stag_tune": ([vp, vp, ip, ip, ctypes.POINTER(TuneCfg), ctypes.POINTER(dp)], ip),
+        "stag_tune_counts": ([vp, ctypes.POINTER(ip), ctypes.POINTER(ip)], ip),
         "stag_solver_submit": ([vp, vp, dp, ip, vp, dp, ip, ctypes.POINTER(ctypes.c_int64)], ip),
         "stag_solver_poll": ([vp, ctypes.c_int64, vp, ctypes.POINTER(CgStats),
                               ctypes.POINTER(dp)], ip),
@@ -358,6 +359,13 @@ def stag_tune(ctx: Context, gauge: Gauge, prec="f32", nrhs=1):
     ctx.check(lib.stag_tune(ctx.h, gauge.h, PREC[prec] if isinstance(prec, str) else prec,
                             int(nrhs), ctypes.byref(cfg), ctypes.byref(ms)))
     return cfg.as_dict(), ms.value
+
+
+def stag_tune_counts(ctx: Context):
+    """(loaded, measured): stag_tune calls answered from STAG_TUNE_CACHE / timed."""
+    a, b = ctypes.c_int(), ctypes.c_int()
+    ctx.check(lib.stag_tune_counts(ctx.h, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def _tune_prec(prec, improved):

@@ -67,6 +67,8 @@ struct stag_ctx {
     std::vector<struct stag_engine*> engines;
     std::map<long long, stag::HopTune> tune;  // key: (prec, N, Vh bucket)
     std::mutex tune_mu;
+    std::atomic<int> tune_loaded{0};    // stag_tune calls answered from STAG_TUNE_CACHE
+    std::atomic<int> tune_measured{0};  // stag_tune calls that timed the shapes
     stag::Serve* serve = nullptr;
     stag::Timing timing;
 };

@@ -7,11 +7,72 @@
 // the reduction order do not depend on the shape), so tuning never changes
 // a solve's iterates.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 
 #include "internal.h"
 
 namespace stag {
+
+// ------------------------------------------------------------------ persistent table
+//
+// With the environment variable STAG_TUNE_CACHE naming a file, stag_tune
+// first looks its shape up there and measures only on a miss, appending the
+// shape it found. One line per entry:
+//   <arch> <hop pairs> <r12> <sites per parity> <precision> <kernel RHS> : S1 S2 nt swizzle ms
+// The key holds everything the kernels' speed depends on: the device
+// architecture, the operator (4 hop pairs for Eq.5, 8 for the improved one),
+// the link form, the lattice size, the storage precision and the block size.
+
+static std::string tune_cache_key(int device, const stag_gauge* g, int prec, int N) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t c = arch.find(':');
+        if (c != std::string::npos) arch.resize(c);
+    } else {
+        (void)hipGetLastError();
+    }
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s %d %d %u %d %d", arch.c_str(), g->npairs,
+             g->r12 && prec != P16S ? 1 : 0, g->g.Vh, prec, N);
+    return buf;
+}
+
+static bool tune_cache_lookup(const char* path, const std::string& key, HopTune* t, double* ms) {
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        const char* colon = strchr(line, ':');
+        if (!colon) continue;
+        std::string k(line, (size_t)(colon - line));
+        while (!k.empty() && k.back() == ' ') k.pop_back();
+        if (k != key) continue;
+        HopTune v;
+        double m = 0;
+        if (sscanf(colon + 1, "%d %d %d %d %lf", &v.S1, &v.S2, &v.nt, &v.swizzle, &m) == 5 &&
+            (v.S1 == 1 || v.S1 == 2 || v.S1 == 4) && (v.S2 == 1 || v.S2 == 2 || v.S2 == 4)) {
+            *t = v;  // the last entry for a key wins
+            *ms = m;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+static void tune_cache_append(const char* path, const std::string& key, const HopTune& t,
+                              double ms) {
+    FILE* f = fopen(path, "a");
+    if (!f) return;  // an unwritable cache only costs re-tuning
+    fprintf(f, "%s : %d %d %d %d %.9g\n", key.c_str(), t.S1, t.S2, t.nt, t.swizzle, ms);
+    fclose(f);
+}
 
 hipError_t timing_begin(stag_ctx* ctx, hipStream_t s, hipEvent_t* ev) {
     Timing& T = ctx->timing;
@@ -103,6 +164,13 @@ int stag_timing_read(stag_ctx* ctx, int kind, int64_t* count, double* total_ms) 
     return STAG_OK;
 }
 
+int stag_tune_counts(const stag_ctx* ctx, int* loaded, int* measured) {
+    if (!ctx || !loaded || !measured) return STAG_EINVAL;
+    *loaded = ctx->tune_loaded.load();
+    *measured = ctx->tune_measured.load();
+    return STAG_OK;
+}
+
 int stag_tune_get(stag_ctx* ctx, int prec, int nrhs, int64_t vh, stag_tune_cfg* out) {
     const int npairs = (prec & STAG_TUNE_IMPROVED) ? 8 : 4;
     prec &= ~STAG_TUNE_IMPROVED;
@@ -154,6 +222,25 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, stag_tune_
     DeviceGuard dg(ctx->device);
     const int N = pick_n(nrhs);
     const uint32_t Vh = g->g.Vh;
+    const char* cache = getenv("STAG_TUNE_CACHE");
+    const std::string key = cache && *cache ? tune_cache_key(ctx->device, g, prec, N) : std::string();
+    if (!key.empty()) {
+        HopTune t;
+        double ms = 0;
+        if (tune_cache_lookup(cache, key, &t, &ms)) {
+            set_tune(ctx, prec, N, Vh, g->npairs, t);
+            apply_tune_to_engines(ctx);
+            ctx->tune_loaded.fetch_add(1);
+            if (best) {
+                best->S1 = t.S1;
+                best->S2 = t.S2;
+                best->nt = t.nt;
+                best->swizzle = t.swizzle;
+            }
+            if (best_ms) *best_ms = ms;
+            return STAG_OK;
+        }
+    }
     // time the solver's own iteration kernels (deferred direction update,
     // finalisations at kernel start) on a solver workspace of this shape
     stag_engine* e = nullptr;
@@ -214,6 +301,8 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, stag_tune_
     if (rc) return rc;
     set_tune(ctx, prec, N, Vh, g->npairs, bestT);
     apply_tune_to_engines(ctx);
+    ctx->tune_measured.fetch_add(1);
+    if (!key.empty()) tune_cache_append(cache, key, bestT, (best1 + best2) * 1e-3);
     if (best) {
         best->S1 = bestT.S1;
         best->S2 = bestT.S2;
