@@ -184,8 +184,9 @@ int stag_dslash(stag_ctx* ctx, const stag_gauge* gauge, const stag_field* in, st
 /* stag_apply_A (Sec.2, Eq.2-3): out_j = m_j^2 in_j - D_eo D_oe in_j on even
  * fields, right-hand side j using mass[j] (host array of in->nrhs finite
  * masses > 0). Asynchronous on `stream`; uses a temporary odd-parity vector
- * allocated stream-ordered. Errors: EINVAL (parity 1, mismatch, mass <= 0 or
- * not finite), ENOMEM, EDEVICE.
+ * allocated stream-ordered from a memory pool of the context, which keeps
+ * freed memory for the next call until stag_destroy. Errors: EINVAL (parity
+ * 1, mismatch, mass <= 0 or not finite), ENOMEM, EDEVICE.
  */
 int stag_apply_A(stag_ctx* ctx, const stag_gauge* gauge, const double* mass, const stag_field* in,
                  stag_field* out, void* stream);
@@ -222,9 +223,12 @@ typedef struct stag_cg_params {
     int use_graph;     /* 1: replay each K-iteration block as one hipGraph */
     int use_x0;        /* 1: x holds the initial guess on entry; 0: start from x = 0 */
     int escalate;      /* F16S inner, gauge with an F32 copy: when the fp16-storage inner
-                          iteration stalls at its precision floor (ESTALL, here after at most
-                          3 stall updates without progress), continue from the current x
-                          with F32 inner iterations (no stall restarts); default 1 */
+                          iteration cannot refine the system, continue from the current x
+                          with F32 inner iterations (no stall restarts); default 1. The
+                          fp16 pass ends (ESTALL) after 3 stall updates without progress,
+                          or at the first refinement cycle that reduces the true residual
+                          norm by less than half (a working inner solve reduces it by
+                          about delta) */
     int mixed_variant; /* mixed: what an update does with the search direction.
                           STAG_MIXED_CARRY (default): keep it, d = r + beta d with
                           beta = |r_true|^2 / |r_prev|^2 (Sec.3.2, Eq.6); the inner cycle
@@ -302,7 +306,8 @@ int stag_cg_solve(stag_ctx* ctx, const stag_gauge* gauge, const double* mass,
  * streams and overlap on the device. A right-hand side's result does not
  * depend on what else is being solved. An STAG_F16S request on a gauge that
  * also holds F32 links hands a right-hand side whose fp16 inner iteration
- * stalls (no halving of the true residual over 3 stall updates) over to the
+ * cannot refine its system (no halving of the true residual over 3 stall
+ * updates, or a refinement cycle that does not halve it) over to the
  * gauge's F32 batch, which continues from its current x without stall
  * restarts, as stag_cg_solve escalates; its stats add up both passes and
  * report inner_final = STAG_F32. Without an F32 copy such a right-hand side

@@ -405,7 +405,8 @@ def refinement_cg(U, L, m, b, tol, prec="f32", eps_in=0.1, max_iter=None, Ulong=
 # --------------------------------------------------------------------------
 
 def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
-             max_iter=None, max_stall=20, carry_direction=True, update="both", Ulong=None):
+             max_iter=None, max_stall=20, carry_direction=True, update="both", Ulong=None,
+             slow_ratio=None):
     """Corrected mixed-precision CG of Sec.3.2, emulated on the CPU.
 
     Inner iterations run on stored low-precision vectors (fp32 arithmetic,
@@ -437,6 +438,13 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
     when its iterated residual meets the tolerance the true residual is
     computed once and decides ("inaccurate" if it misses).
     ``Ulong``: the improved operator (U = fat links), in both precisions.
+    ``slow_ratio``: end with status "stall" at the first (non-stall) update
+    whose true residual norm fell by less than this factor since the previous
+    update: iterative refinement contracts the true residual by about the inner
+    reduction ``delta`` per cycle when the inner precision can resolve the
+    system, so a cycle that does not even halve it means the low precision
+    cannot refine it (the setting a solver that can hand over to a higher
+    inner precision uses).
     Returns (x, stats).
     """
     if update not in ("both", "reliable", "fold_only"):
@@ -514,9 +522,12 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
             else:  # reliable only: y stays, r from x + y
                 r64 = b - A64(x + y.astype(np.complex128))
             rr = norm2(r64)
-            true_rr = rr
+            prev_true, true_rr = true_rr, rr
             stats["updates"] += 1
             if rr <= stop:
+                break
+            if slow_ratio and not stall and rr > slow_ratio * slow_ratio * prev_true:
+                stats["status"] = "stall"
                 break
             rs = q(r64)
             rmax = rmin = math.sqrt(rr)

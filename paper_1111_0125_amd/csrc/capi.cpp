@@ -207,10 +207,32 @@ int stag_create(int device, size_t hbm_budget_bytes, stag_ctx** out) {
         return set_error(nullptr, STAG_EDEVICE, "stag_create: scratch address: %s",
                          hipGetErrorString(e));
     }
+    // Temporaries of the asynchronous calls (A's odd intermediate, host
+    // import / export staging) come from a pool of the context that keeps
+    // freed memory for reuse: the device's default pool returns it at every
+    // synchronisation, and a fresh physical allocation in a loop of A
+    // applications can take longer than the kernels.
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = device;
+    hipMemPool_t pool = nullptr;
+    e = hipMemPoolCreate(&pool, &props);
+    if (e == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (pool) (void)hipMemPoolDestroy(pool);
+        (void)hipStreamDestroy(s);
+        return set_error(nullptr, STAG_EDEVICE, "stag_create: memory pool: %s", hipGetErrorString(e));
+    }
     stag_ctx* c = new stag_ctx();
     c->device = device;
     c->stream = s;
     c->scratch = scr;
+    c->pool = pool;
     if (hbm_budget_bytes == 0) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) == hipSuccess) c->budget = fr;
@@ -251,6 +273,7 @@ int stag_destroy(stag_ctx* ctx) {
         delete g;
     }
     (void)hipStreamDestroy(ctx->stream);
+    if (ctx->pool) (void)hipMemPoolDestroy(ctx->pool);
     delete ctx;
     return STAG_OK;
 }
@@ -520,7 +543,7 @@ int stag_field_import(stag_field* f, const double* src, int src_on_device, void*
     const void* dsrc = src;
     void* tmp = nullptr;
     if (!src_on_device) {
-        HIPCK(ctx, hipMallocAsync(&tmp, bytes, s));
+        HIPCK(ctx, hipMallocFromPoolAsync(&tmp, bytes, ctx->pool, s));
         HIPCK(ctx, hipMemcpyAsync(tmp, src, bytes, hipMemcpyHostToDevice, s));
         dsrc = tmp;
     }
@@ -543,7 +566,7 @@ int stag_field_export(const stag_field* f, double* dst, int dst_on_device, void*
     void* ddst = dst;
     void* tmp = nullptr;
     if (!dst_on_device) {
-        HIPCK(ctx, hipMallocAsync(&tmp, bytes, s));
+        HIPCK(ctx, hipMallocFromPoolAsync(&tmp, bytes, ctx->pool, s));
         ddst = tmp;
     }
     HIPCK(ctx, launch_export(f->prec, f->data, f->rs, ddst, (uint32_t)Vh, f->nrhs, s));
@@ -656,7 +679,7 @@ int stag_apply_A(stag_ctx* ctx, const stag_gauge* g, const double* mass, const s
     DeviceGuard dg(ctx->device);
     hipStream_t s = pick_stream(ctx, stream);
     void* t = nullptr;
-    HIPCK(ctx, hipMallocAsync(&t, in->rs * in->nrhs, s));
+    HIPCK(ctx, hipMallocFromPoolAsync(&t, in->rs * in->nrhs, ctx->pool, s));
     rc = apply_A_stages(ctx, g, mass, in, out, t, s);
     HIPCK(ctx, hipFreeAsync(t, s));
     return rc;
@@ -735,7 +758,7 @@ int stag_cg_solve(stag_ctx* ctx, const stag_gauge* g, const double* mass, const 
     stag_engine* e = nullptr;
     int rc = engine_acquire(ctx, g, p.inner_prec, pick_n(n), &e);
     if (rc) return rc;
-    rc = engine_solve(e, n, mass, b->data, b->rs, x->data, x->rs, p1, st1.data(), s);
+    rc = engine_solve(e, n, mass, b->data, b->rs, x->data, x->rs, p1, st1.data(), s, can_escalate);
     engine_release(e);
     bool stalled = false;
     for (const auto& t : st1) stalled |= t.status == STAG_ESTALL;

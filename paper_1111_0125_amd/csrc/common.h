@@ -205,6 +205,10 @@ struct RhsState {
     double tol2;      // tol^2
     double m2;        // mass^2
     double rstart;    // |r| when the current inner cycle started (last update)
+    double slow_ratio;  // > 0: a non-stall update whose true |r| fell by less than this
+                        // factor since the previous update ends the pass (F_ESTALL): the
+                        // inner precision cannot refine this system (fp16 storage that
+                        // can hand over to fp32); 0: off
     int since;        // iterations since the last new residual minimum
     int stall_iters;
     int stall_count;

@@ -57,6 +57,7 @@ struct stag_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     void* scratch = nullptr;       // this device's copy of the scratch array (scratch.hip)
+    hipMemPool_t pool = nullptr;   // stream-ordered temporaries; keeps freed memory for reuse
     size_t budget = 0;
     std::atomic<size_t> used{0};
     std::mutex mu;                 // guards the object lists and the workspace pool
@@ -154,6 +155,7 @@ struct SlotInit {
     stag_cg_params params;
     const void* x0 = nullptr;  // initial guess (fp64 internal layout, one RHS) or null: x = 0
     bool x0_in_place = false;  // the slot's x64 block already holds the initial guess
+    bool escalating = false;   // fp16 storage that can hand over to fp32 (slow-cycle exit)
 };
 
 void run_init(EngineRun& R, stag_engine* e, hipStream_t s, const void* b, size_t b_rs, int K,
@@ -171,6 +173,10 @@ int engine_create(stag_ctx* ctx, const stag_gauge* g, int prec, int N, bool serv
 // An fp16-storage solve that can hand over to fp32 gives up after this many
 // stall updates without halving the true residual (instead of max_stall).
 constexpr int kEscalateStalls = 3;
+// ... and ends at the first refinement cycle that does not reduce the true
+// residual norm by this factor (a working inner solve reduces it by about the
+// update threshold delta = 0.1).
+constexpr double kSlowCycleRatio = 0.5;
 
 }  // namespace stag
 
@@ -219,9 +225,12 @@ void engine_drop_graphs(stag_engine* e);
 
 // One whole solve of n <= N right-hand sides held in canonical device
 // buffers b_dev / x_dev (complex128 [n][Vh][3]) or fields.
+// escalating: an fp16-storage solve whose caller hands stalled right-hand
+// sides over to fp32 (the pass also ends at a refinement cycle that fails to
+// halve the true residual).
 int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, size_t b_rs,
                  void* x64_out, size_t x_rs, const stag_cg_params& p, stag_cg_stats* stats,
-                 hipStream_t stream);
+                 hipStream_t stream, bool escalating = false);
 
 // Event timing helpers (no-ops when timing is off).
 hipError_t timing_begin(stag_ctx* ctx, hipStream_t s, hipEvent_t* ev);

@@ -456,6 +456,7 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
             break;
         case FIN_RU_END: {
             const double rt = sum;
+            const double rt_prev = s.rr_true;  // true |r|^2 at the previous update (or start)
             s.rr_true = rt;
             const bool stall = (s.flags & F_STALL) != 0;
             s.updates += 1;
@@ -471,6 +472,15 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
             if (s.flags & F_MAXIT) {
                 s.rr = rt;
                 s.flags = F_MAXIT;
+                break;
+            }
+            // a refinement cycle reduces the true residual by about the inner
+            // reduction (delta) when the inner precision suffices; one that
+            // does not even reach slow_ratio shows the inner iteration cannot
+            // refine this system: end the pass so the caller can hand over
+            if (!stall && s.slow_ratio > 0.0 && rt > s.slow_ratio * s.slow_ratio * rt_prev) {
+                s.rr = rt;
+                s.flags = F_ESTALL;
                 break;
             }
             // Eq.6: the next direction is r + beta d with beta = |r_true|^2 / |r_prev|^2;

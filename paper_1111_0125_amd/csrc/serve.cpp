@@ -236,6 +236,7 @@ static int admit(Serve* S, Work& w) {
         }
         SlotInit si{s, t->mass, p};
         si.x0_in_place = w.cont;
+        si.escalating = w.prec == P16S && (t->g->mask & STAG_MASK_F32);
         inits.push_back(si);
         ++k;
     }

@@ -589,7 +589,7 @@ int default_graph_k(uint32_t Vh) { return Vh >= 262144 ? 16 : (Vh >= 32768 ? 32 
 // at once (FIN_INIT: F_DONE), a non-finite b with F_BADINPUT.
 // The state of a slot about to start (before FIN_INIT).
 static void start_state(const stag_engine* e, double mass, const stag_cg_params& p, bool x0,
-                        RhsState& s) {
+                        bool escalating, RhsState& s) {
     const uint64_t n_unknowns = 3ull * e->Vh;
     std::memset(&s, 0, sizeof(s));
     s.tol2 = p.tol * p.tol;
@@ -602,6 +602,9 @@ static void start_state(const stag_engine* e, double mass, const stag_cg_params&
     s.max_iter = p.max_iter > 0 ? p.max_iter : (int)std::min<uint64_t>(10 * n_unknowns, 1000000);
     s.flags = F_NEW | (x0 ? F_X0 : 0u);
     s.variant = p.mixed_variant;
+    // an fp16-storage pass with somewhere to go hands over as soon as a
+    // refinement cycle fails to halve the true residual
+    s.slow_ratio = escalating && e->prec == P16S ? kSlowCycleRatio : 0.0;
 }
 
 int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots) {
@@ -611,7 +614,7 @@ int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots) {
     for (const SlotInit& si : slots) {
         RhsState& s = e->hstage[si.slot];
         const bool x0 = si.x0 != nullptr || si.x0_in_place;
-        start_state(e, si.mass, si.params, x0, s);
+        start_state(e, si.mass, si.params, x0, si.escalating, s);
         RCK(hipMemcpyAsync(e->st + si.slot, &s, sizeof(RhsState), hipMemcpyHostToDevice, R.s));
         if (si.x0 && !si.x0_in_place)
             RCK(hipMemcpyAsync((char*)e->x64 + (size_t)si.slot * e->rs64, si.x0, e->rs64,
@@ -760,12 +763,12 @@ static bool tiny_solve_eligible(const stag_engine* e, int n, const stag_cg_param
 // One-workgroup solves of the n right-hand sides already in e->b64; the final
 // states are copied to fin.
 static int tiny_solve(stag_engine* e, int n, const double* mass, const stag_cg_params& p,
-                      hipStream_t stream, std::vector<RhsState>& fin) {
+                      bool escalating, hipStream_t stream, std::vector<RhsState>& fin) {
     const stag_gauge* g = e->gauge;
     const int P = e->prec;
     int max_iter = 0;
     for (int r = 0; r < n; ++r) {
-        start_state(e, mass[r], p, false, e->hstage[r]);
+        start_state(e, mass[r], p, false, escalating, e->hstage[r]);
         max_iter = std::max(max_iter, e->hstage[r].max_iter);
     }
     RCK(hipMemcpyAsync(e->st, e->hstage, sizeof(RhsState) * n, hipMemcpyHostToDevice, stream));
@@ -835,13 +838,13 @@ static int engine_solve_finish(stag_engine* e, int n, void* x_out, size_t x_rs,
 
 int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, size_t b_rs,
                  void* x_out, size_t x_rs, const stag_cg_params& p, stag_cg_stats* stats,
-                 hipStream_t stream) {
+                 hipStream_t stream, bool escalating) {
     const auto t0 = std::chrono::steady_clock::now();
     const int K = p.graph_k > 0 ? p.graph_k : default_graph_k(e->Vh);
     RCK(hipMemcpy2DAsync(e->b64, e->rs64, b64, b_rs, e->rs64, n, hipMemcpyDeviceToDevice, stream));
     std::vector<RhsState> fin(n);
     if (tiny_solve_eligible(e, n, p)) {
-        int rc = tiny_solve(e, n, mass, p, stream, fin);
+        int rc = tiny_solve(e, n, mass, p, escalating, stream, fin);
         if (rc) return rc;
         return engine_solve_finish(e, n, x_out, x_rs, stats, stream, fin, t0);
     }
@@ -852,6 +855,7 @@ int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, siz
     for (int r = 0; r < n; ++r) {
         slots[r] = SlotInit{r, mass[r], p};
         if (p.use_x0) slots[r].x0 = (const char*)x_out + (size_t)r * x_rs;
+        slots[r].escalating = escalating;
     }
     int rc = run_start_slots(R, slots);
     if (rc) return rc;

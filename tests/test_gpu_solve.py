@@ -336,3 +336,24 @@ def _c2_oracle_iters():
     with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_counts.json")) as f:
         c = json.load(f)["c2_16x16x16x32"]
     return {"f64": c["fig1_fp64_cg"]["iters"], "f32": c["sec32_fp32_mixed"]["iters"]}
+
+
+def test_f16s_hands_over_at_first_slow_cycle(stag, ctx):
+    """8^4 Haar, m = 0.01, 1e-10: fp16 storage cannot refine this system well
+    (the oracle's emulation ends its pass at the first update, whose true
+    residual has not halved; plain fp16 refinement takes over 13 000
+    iterations). With fp32 links on the gauge the solve hands over there and
+    finishes in fp32 to the requested fp64 true residual, in far fewer
+    iterations than the fp16 iteration alone needs."""
+    L, m, tol = (8, 8, 8, 8), 0.01, 1e-10
+    U = synth.haar_links(L, 15)
+    b = synth.gaussian_rhs(L, 1, 1001)
+    _, est = ostag.mixed_cg(U, L, m, b[0], tol, prec="f16s", max_stall=3, slow_ratio=0.5)
+    assert est["status"] == "stall" and est["updates"] == 1
+    rc, st, x = solve(stag, ctx, L, U, b, [m], tol, inner="f16s", precisions=("f64", "f32", "f16s"))
+    log("f16s with hand-over", rc, st[0], "oracle fp16 pass", est)
+    assert rc == 0 and st[0]["inner_final"] == stag.PREC["f32"]
+    assert true_res(U, L, [m], b, x)[0] <= tol
+    rc32, st32, _ = solve(stag, ctx, L, U, b, [m], tol, inner="f32")
+    # the fp16 pass ends near where the oracle's does; the rest is about an fp32 solve
+    assert st[0]["iters"] <= st32[0]["iters"] + 1.25 * est["iters"] + 50

@@ -343,6 +343,30 @@ def test_both_updates_are_needed():
     assert abs(gw["iters"] - both["iters"]) <= 0.05 * both["iters"]
 
 
+def test_slow_refinement_cycle_ends_the_fp16_pass():
+    """With fp16 storage on a system it cannot refine well (8^4 Haar,
+    m = 0.01: kappa u16 >> 1) the first refinement cycle reduces the iterated
+    residual tenfold but the true residual by less than half, so slow_ratio
+    ends the pass there (without it the same iteration runs on past the cap,
+    where plain fp16 refinement needs over 13 000 iterations); on a system fp16
+    does refine, slow_ratio changes nothing."""
+    L, m, tol = (8, 8, 8, 8), 0.01, 1e-10
+    U = synth.haar_links(L, 15)
+    b = synth.gaussian_rhs(L, 1, 1001)[0]
+    _, slow = stag.mixed_cg(U, L, m, b, tol, prec="f16s", max_stall=3, slow_ratio=0.5)
+    assert slow["status"] == "stall" and slow["updates"] == 1 and slow["restarts"] == 0
+    assert 0.5 < slow["true_rel_res"] < 1.0
+    _, capped = stag.mixed_cg(U, L, m, b, tol, prec="f16s", max_stall=3,
+                              max_iter=slow["iters"] + 50)
+    assert capped["status"] == "noconv" and capped["updates"] >= 1
+    L, m, tol = (4, 4, 4, 4), 0.5, 1e-8
+    U = synth.haar_links(L, 11)
+    b = synth.gaussian_rhs(L, 1, 111)[0]
+    x1, a = stag.mixed_cg(U, L, m, b, tol, prec="f16s", slow_ratio=0.5)
+    x2, c = stag.mixed_cg(U, L, m, b, tol, prec="f16s")
+    assert a == c and a["status"] == "ok" and np.array_equal(x1, x2)
+
+
 def test_paper_cost_model_golden():
     g = json.load(open(os.path.join(GOLDEN, "paper_cost_model.json")))
     reals = 8 * 18 + 8 * 6 + 6
@@ -486,9 +510,33 @@ def test_improved_low_operator_error():
     e16 = rel(stag.LowOperator(fat, L, m, "f16s", lng)(v), ref)
     assert 1e-9 < e32 < 1e-6
     assert 1e-5 < e16 < 1e-3
-    # the fp16 scale covers the long links: entries of N never exceed it
+    # one fp16 scale per site covers its fat and its long links
+    def amax(W):  # over the links stored at each site, after rounding to fp32
+        W = W.astype(np.complex64)
+        return np.maximum(np.abs(W.real), np.abs(W.imag)).max(axis=(-1, -2, -3))
     s = stag.f16s_link_scale(fat, L, lng)
-    assert np.all(s >= np.maximum(np.abs(lng.real), np.abs(lng.imag)).max(axis=(-1, -2, -3)))
+    assert np.all(s >= amax(lng)) and np.all(s >= amax(fat))
+
+
+def test_shared_fp16_scale_keeps_long_links_significands():
+    """The long links are about 27 times smaller than the fat links sharing
+    their site scale, but fp16 is a floating format: N / s sits far above the
+    fp16 normal range's lower end (6.1e-5), so it keeps its 11-bit significand
+    and a scale of its own would lower its rounding error by far less than a
+    factor 2 (not the 2^5 a fixed-point format would lose)."""
+    L = (4, 4, 4, 6)
+    fat, lng = synth.naik_links(synth.haar_links(L, 251), fat_noise=0.05, seed=252)
+    shared = stag.f16s_link_scale(fat, L, lng)
+    own = stag.f16s_link_scale(lng, L)  # long links alone (their own maximum)
+    ratio = (own / shared).astype(np.float64)
+    assert 0.02 < ratio.min() and ratio.max() < 0.06
+    nmu = lng[..., 0, :, :]
+    q = lambda s_: stag._q_link_f16(nmu.astype(np.complex64), s_)
+    small = np.abs(nmu) > 1e-3 * np.abs(nmu).max()
+    rel_shared = (np.abs(q(shared) - nmu) / np.abs(nmu))[small].max()
+    rel_own = (np.abs(q(own) - nmu) / np.abs(nmu))[small].max()
+    assert rel_shared < 2.0 ** -10 and rel_own < 2.0 ** -10
+    assert rel_shared < 2.0 * rel_own
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16s"])
