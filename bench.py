@@ -552,6 +552,10 @@ def main():
                     help="only the 32^3x64 A applications (Eq.5 full and 12-parameter links, and "
                          "the improved operator), autotuned: the program the A-apply kernel "
                          "profiles trace")
+    ap.add_argument("--block-kernels-only", action="store_true",
+                    help="only tune and time the block iteration kernels of the 24^3x48 workload "
+                         "for 4, 8 and 12 right-hand sides, then a 256 MiB copy kernel: the program "
+                         "the block-kernel profiles run")
     ap.add_argument("--full-links", action="store_true",
                     help="store the gauge copies in full (18 reals per link) instead of 12 parameters")
     args = ap.parse_args()
@@ -585,6 +589,29 @@ def main():
                # then the 1 GiB copy kernel (3 + 20 launches)
                "launch_order": order, "copy_bytes_each_way": 1 << 30,
                "kernel_src_sha256": csrc_digest()}
+        print(json.dumps(out), flush=True)
+        return
+
+    if args.block_kernels_only:
+        torch.cuda.init()
+        os.environ.pop("STAG_TUNE_CACHE", None)  # every shape is timed (and counted)
+        name = "c4_24x24x24x48"
+        c4 = synth.CONFIGS[name]
+        with stag.Context(0) as ctx:
+            g = ctx.gauge(c4["L"], synth.config_links(name), precisions=("f64", "f32"), r12=True)
+            out = {"block_kernels_only": True, "workload": name, "inner": "f32", "links": "r12",
+                   "vh": g.vh, "tune": {}, "us": {}, "kernel_src_sha256": csrc_digest()}
+            for n in (4, 8, 12):
+                out["tune"][n], _ = stag.stag_tune(ctx, g, "f32", n)
+                out["us"][n] = stag.stag_time_kernels(ctx, g, "f32", n, reps=20)
+                log("block kernels", n, out["tune"][n], out["us"][n])
+        nf = COPY_FLOATS
+        xs = torch.ones(nf, device="cuda")
+        ys = torch.empty_like(xs)
+        for _ in range(3):
+            torch.mul(xs, 2.0, out=ys)
+        torch.cuda.synchronize()
+        out.update({"copy_bytes_read": nf * 4, "copy_bytes_written": nf * 4})
         print(json.dumps(out), flush=True)
         return
 

@@ -338,8 +338,12 @@ int stag_solver_config(stag_ctx* ctx, int slots_per_batch, int graph_k, int queu
 /* ---------------------------------------------------------------- tuning
  * Launch shape of the two hop stages of A: S1 / S2 = lanes per output site
  * (1, 2 or 4) for stage 1 (D_oe) and stage 2 (D_eo with the m^2 update),
- * nt = non-temporal link loads, swizzle = XCD-aware block order. Every
- * shape computes bit-identical results; only speed differs.
+ * nt = non-temporal link loads, swizzle = block order: 0 plain, 1 each XCD
+ * on a contiguous eighth of the blocks, 2 / 3 / 4 that and then the blocks
+ * in groups of 2 / 4 / 8 consecutive t-slices with t running fastest (keeps a
+ * site's t-neighbours close in launch order; used where the lattice has
+ * whole blocks per t-slice, else as 1). Every shape computes bit-identical
+ * results; only speed differs.
  * stag_tune_get / stag_tune_set: the shape used for (prec, nrhs, vh) by
  * gauges of Eq.5's operator, or with STAG_TUNE_IMPROVED or-ed into prec by
  * gauges of the improved operator. stag_tune: time the solver's own iteration

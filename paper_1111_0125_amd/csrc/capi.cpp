@@ -135,6 +135,14 @@ hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, con
     a.run_mask = run_mask;
     a.p_out = p_out;
     a.swizzle = t.swizzle;
+    a.tile_bps = 0;
+    if (t.swizzle >= 2) {
+        // t-grouped block order: needs whole blocks per t-slice and groups
+        // that divide Lt; otherwise the XCD order alone
+        const uint64_t slice = (uint64_t)g->g.st * (uint64_t)S;  // lanes per t-slice
+        const uint32_t tb = 1u << (t.swizzle - 1);
+        if (slice % kBlock == 0 && g->g.L[3] % (int)tb == 0) a.tile_bps = (uint32_t)(slice / kBlock);
+    }
     a.g = g->g;
     if (red) a.red = *red;
     if (fin) a.fin = *fin;

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
     constexpr int LOGB = B >= 8 ? 3 : B >= 4 ? 2 : B >= 2 ? 1 : 0;
     static_assert(B >= 1 && (1 << LOGB) == B, "pairs per lane must be a power of two");
     using T = typename Real<P>::T;
-    const uint32_t blk = logical_block(a.swizzle);
+    const uint32_t blk = logical_block(a.swizzle, a.tile_bps);
     const uint32_t gt = blk * kBlock + threadIdx.x;
     const uint32_t s = gt / S;
     const int j = (int)(gt % S);

@@ -22,7 +22,9 @@ struct Serve;  // serving loop (serve.cpp)
 struct HopTune {
     int S1 = 1, S2 = 1;  // lanes per site of stage 1 (D_oe) and stage 2 (D_eo + xpay)
     int nt = 1;          // non-temporal link loads
-    int swizzle = 1;     // XCD-aware block order
+    int swizzle = 1;     // block order: 0 plain, 1 XCD-aware, 2-4 XCD-aware in groups of
+                         // 2, 4 or 8 t-slices with t fastest (hop kernels; vector kernels
+                         // take any value >= 1 as XCD-aware)
 };
 
 }  // namespace stag

@@ -328,14 +328,36 @@ __device__ __forceinline__ void matvec_acc(const T (&lr)[18], const T (&li)[18],
 
 // ------------------------------------------------------------------ launch geometry
 
-// Map the hardware block index to a logical tile so that each of the eight
-// XCDs (which receive blocks round-robin) works on one contiguous eighth of
-// the sites; neighbouring tiles then share that XCD's L2.
-__device__ __forceinline__ uint32_t logical_block(int swizzle) {
+// Map the hardware block index to the block of sites it handles (a block
+// always handles one contiguous range of sites, so the work, the rounding and
+// the reduction chunks do not depend on the mapping).
+// swizzle >= 1: each of the eight XCDs (which receive blocks round-robin)
+// works on one contiguous eighth of the blocks; neighbouring blocks then
+// share that XCD's L2.
+// swizzle >= 2 with bps (blocks per t-slice, i.e. per Lx Ly Lz / 2 sites)
+// set: those blocks are then taken in groups of TB = 2^(swizzle - 1)
+// consecutive t-slices, and within a group t runs fastest. A site's
+// t-neighbours are then TB blocks or fewer away in launch order instead of a
+// whole slice, so the direction vectors a hop stage gathers there are still
+// in L2 (with several right-hand sides a slice's links, inputs and outputs
+// overflow the XCD's 4 MB L2, and every input is otherwise fetched again for
+// each of its two t-neighbours). The caller sets bps only when the grid is
+// Lt x bps blocks and TB divides Lt.
+__device__ __forceinline__ uint32_t logical_block(int swizzle, uint32_t bps = 0) {
     const uint32_t k = blockIdx.x, nb = gridDim.x;
-    if (!swizzle || nb < 16) return k;
-    const uint32_t q = nb >> 3, rem = nb & 7, x = k & 7, i = k >> 3;
-    return x * q + (x < rem ? x : rem) + i;
+    uint32_t v = k;
+    if (swizzle && nb >= 16) {
+        const uint32_t q = nb >> 3, rem = nb & 7, x = k & 7, i = k >> 3;
+        v = x * q + (x < rem ? x : rem) + i;
+    }
+    if (swizzle >= 2 && bps) {
+        const uint32_t tb = 1u << (swizzle - 1);
+        const uint32_t grp = tb * bps;  // blocks per group of tb slices
+        const uint32_t tg = v / grp, rem = v - tg * grp;
+        const uint32_t j = rem / tb, tt = rem - j * tb;
+        v = (tg * tb + tt) * bps + j;
+    }
+    return v;
 }
 
 // ------------------------------------------------------------------ reductions

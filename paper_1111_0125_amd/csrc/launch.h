@@ -48,7 +48,8 @@ struct HopArgs {
     RhsState* st;          // null: every RHS is processed
     unsigned run_mask;     // process RHS r iff st[r].flags & run_mask
     int p_out;
-    int swizzle;
+    int swizzle;           // block order (logical_block)
+    uint32_t tile_bps;     // blocks per t-slice for the t-grouped orders (0: off)
     int r12;               // links in 12-parameter form (P64 / P32)
     int npairs;            // hop pairs per site: 4 (Eq.5) or 8 (improved operator)
     Geom g;

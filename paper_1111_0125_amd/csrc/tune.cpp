@@ -1,9 +1,10 @@
 // Launch-shape autotuner and kernel event timing.
 //
 // The autotuner times the two hop stages of A on the actual gauge field for
-// every launch shape (lanes per site S, non-temporal link loads, XCD-aware
-// block order) and keeps the fastest per stage for (precision, RHS block,
-// lattice size). All shapes compute bit-identical results (the hop sum and
+// every launch shape (lanes per site S, non-temporal link loads, block order:
+// plain, XCD-aware, and for blocks of several right-hand sides XCD-aware in
+// groups of t-slices) and keeps the fastest per stage for (precision, RHS
+// block, lattice size). All shapes compute bit-identical results (the hop sum and
 // the reduction order do not depend on the shape), so tuning never changes
 // a solve's iterates.
 #include <algorithm>
@@ -207,7 +208,9 @@ int stag_tune_set(stag_ctx* ctx, int prec, int nrhs, int64_t vh, const stag_tune
     t.S1 = cfg->S1;
     t.S2 = cfg->S2;
     t.nt = cfg->nt ? 1 : 0;
-    t.swizzle = cfg->swizzle ? 1 : 0;
+    if (cfg->swizzle < 0 || cfg->swizzle > 4)
+        return set_error(ctx, STAG_EINVAL, "stag_tune_set: swizzle must be 0..4");
+    t.swizzle = cfg->swizzle;
     set_tune(ctx, prec, pick_n(nrhs), (uint32_t)vh, npairs, t);
     apply_tune_to_engines(ctx);
     return STAG_OK;
@@ -261,8 +264,11 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, stag_tune_
     rc = time_cfg(bestT, us0);
     double best1 = us0[0], best2 = us0[1], best3 = us0[2];
     const int Ss[] = {1, 2, 4};
+    // block orders: plain and XCD-aware; blocks of several right-hand sides
+    // also the t-grouped orders (their neighbour gathers are what overflows L2)
+    const int max_sw = N > 1 ? 4 : 1;
     for (int nt = 0; nt <= 1 && rc == STAG_OK; ++nt)
-        for (int sw = 0; sw <= 1 && rc == STAG_OK; ++sw)
+        for (int sw = 0; sw <= max_sw && rc == STAG_OK; ++sw)
             for (int S : Ss) {
                 if (N > 1 && nt == 0) break;  // several RHS always load links non-temporally
                 HopTune tu;

@@ -280,37 +280,44 @@ def cmd_iteration(a):
         if h:
             prec = PREC_NAME[h["prec"]]
             r12p = links == "r12" and prec != "f16s"
+            n = h["N"]
+            # blocks of 8 or more right-hand sides, and of several on lattices of
+            # 131072 sites per parity or more, form the direction in a pass of
+            # their own: their hop stages read d as stored
+            lazy = n == 1 or (n < 8 and vh < 131072)
             if h["epi"] == 0:
-                alg = vh * costs.hop_bytes_per_site(prec, 1, lazy=True, r12=r12p)
+                alg = vh * costs.hop_bytes_per_site(prec, 1, n, lazy=lazy, r12=r12p)
             elif h["epi"] == 2:
-                alg = vh * costs.hop_bytes_per_site(prec, 2, lazy=True, r12=r12p)
+                alg = vh * costs.hop_bytes_per_site(prec, 2, n, lazy=lazy, r12=r12p)
             else:
                 continue
         else:
             m = VEC.search(name)
-            if not m or int(m.group(2)) != 1 or int(m.group(3)) not in (2, 3):
+            if not m or int(m.group(3)) not in (2, 3):
                 continue
             prec = PREC_NAME[int(m.group(1))]
-            alg = vh * costs.update_bytes_per_site(prec, int(m.group(3)) == 3)
+            alg = vh * int(m.group(2)) * costs.update_bytes_per_site(prec, int(m.group(3)) == 3)
         F, W = statistics.mean(d["fetch"]), statistics.mean(d["write"])
         b = F * 1024 * fs + W * 1024 * ws
         out[name] = {"fetch_kib": round(F, 1), "write_kib": round(W, 1),
                      "dispatches": [len(d["fetch"]), len(d["write"])],
                      "hbm_bytes_per_launch": int(round(b)), "algorithmic_bytes_per_launch": alg,
                      "ratio": round(b / alg, 4)}
-    blob = {"workload": "16^3x32 exp(i 0.3 H) links, the CG iteration kernels of every precision "
-                        "(f64: plain CG; f32, f16s: mixed), one RHS",
+    blob = {"workload": a.workload,
             "links": links, "kernel_src_sha256": run["kernel_src_sha256"],
             "fetch_scale": round(fs, 5), "write_scale": round(ws, 5), "kernels": out}
-    lines = ["# HBM traffic of the 16^3x32 iteration kernels (rocprofv3 FETCH_SIZE / WRITE_SIZE)", "",
+    lines = [f"# HBM traffic of the iteration kernels: {a.workload} (rocprofv3 FETCH_SIZE / WRITE_SIZE)", "",
              "Commands (from the repository root on one MI355X; `<repo>` is that root), one counter "
              "per run:", ""]
     lines += ["    " + c for c in a.cmd]
-    lines += ["", "`bench.py --kernels-only` builds the 16^3x32 workload, runs the autotuner over "
-              "every launch shape of the three iteration kernels (no shapes from a table), launches "
-              "them 20 more times as `stag_time_kernels` does, then a 256 MiB elementwise copy "
-              "(`torch.mul`, 3 launches). Counter values are KiB per dispatch, averaged over all "
-              "dispatches of each kernel symbol (the same work every launch).", "",
+    lines += ["", a.program, "Counter values are KiB per dispatch, averaged over all "
+              "dispatches of each kernel symbol (the same work every launch). Template arguments: "
+              "`k_hop<prec, S, N, epilogue, nt, pairs>` (prec 0 = f64, 1 = f32, 2 = f16s; S lanes "
+              "per site; N right-hand sides; epilogue 0 = stage 1, 2 = stage 2 with <d, A d>), "
+              "`k_vec<prec, N, op>` (op 3 = mixed update, 2 = fp64 CG update). Compulsory bytes: "
+              "`paper_1111_0125_amd/costs.py` (blocks of several right-hand sides on this many "
+              "sites read the direction as stored; one right-hand side forms it in the hop "
+              "stages from r and the previous d).", "",
               f"Calibration on the copy kernel (`{cname}`): FETCH_SIZE reads {fkib:.1f} KiB per "
               f"dispatch (scale {fs:.5f}), WRITE_SIZE {wkib:.1f} KiB (scale {ws:.5f}).", "",
               "| kernel | dispatches (fetch / write run) | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM MB per "
@@ -394,6 +401,12 @@ def main(argv=None):
     p.add_argument("--out", required=True)
     p = sub.add_parser("iteration")
     p.add_argument("--json", required=True)
+    p.add_argument("--workload", default="16^3x32 exp(i 0.3 H) links, the CG iteration kernels "
+                   "of every precision (f64: plain CG; f32, f16s: mixed), one RHS")
+    p.add_argument("--program", default="`bench.py --kernels-only` builds the 16^3x32 workload, "
+                   "runs the autotuner over every launch shape of the three iteration kernels (no "
+                   "shapes from a table), launches them 20 more times as `stag_time_kernels` does, "
+                   "then a 256 MiB elementwise copy (`torch.mul`, 3 launches).")
     p.add_argument("--fetch", required=True)
     p.add_argument("--write", required=True)
     p.add_argument("--cmd", action="append", default=[])

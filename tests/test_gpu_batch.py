@@ -51,3 +51,56 @@ def test_c4_block_solve_12_rhs(stag, r12):
         rc1, st1 = stag.stag_cg_solve(ctx, g, [m], f1, x1, stag.cg_params(tol=tol, inner="f32"))
         assert rc1 == 0 and st1[0]["iters"] == st[j]["iters"]
         assert np.array_equal(x1.store()[0], x[j])
+
+
+@pytest.mark.parametrize("nrhs", [2, 4, 8, 12])
+def test_block_orders_bitwise_identical(stag, nrhs):
+    """Every block order (plain, XCD-aware, and XCD-aware in groups of 2, 4
+    or 8 t-slices with t fastest) and lane count gives the same bits for a
+    block A, on a lattice whose t-slices are whole blocks for every lane count
+    (8^4: 256 sites per slice and parity), and meets the oracle."""
+    L = (8, 8, 8, 8)
+    U = synth.haar_links(L, 41)
+    v = synth.gaussian_rhs(L, nrhs, 42)
+    masses = [0.05 + 0.01 * r for r in range(nrhs)]
+    with stag.Context(0) as ctx:
+        g = ctx.gauge(L, U, precisions=("f32",), r12=True)
+        fi = ctx.field(g, 0, "f32", nrhs).load(v)
+        fo = ctx.field(g, 0, "f32", nrhs)
+        outs = {}
+        for S in (1, 2, 4):
+            for sw in range(5):
+                stag.stag_tune_set(ctx, "f32", nrhs, g.vh, S, S, 1, sw)
+                stag.stag_apply_A(ctx, g, masses, fi, fo)
+                outs[(S, sw)] = fo.store()
+        ref = outs[(1, 0)]
+        for k, o in outs.items():
+            assert np.array_equal(o, ref), k
+        Ax = oracle_apply_A(U, v, L, np.array(masses))
+        assert float(np.abs(ref - Ax).max() / np.abs(Ax).max()) <= 1e-6
+
+
+def test_block_solve_bitwise_across_block_orders(stag):
+    """An 8-RHS mixed block solve (direction pass of its own, block hop
+    stages, fp64 fix-ups) gives the same iterations and bits in every block
+    order, and each right-hand side meets the oracle's true residual."""
+    L, m, tol, n = (8, 8, 8, 8), 0.05, 1e-9, 8
+    U = synth.haar_links(L, 43)
+    b = synth.gaussian_rhs(L, n, 44)
+    res = []
+    with stag.Context(0) as ctx:
+        g = ctx.gauge(L, U, precisions=("f64", "f32"), r12=True)
+        fb = ctx.field(g, 0, "f64", n).load(b)
+        fx = ctx.field(g, 0, "f64", n)
+        for sw in range(5):
+            for p in ("f64", "f32"):
+                stag.stag_tune_set(ctx, p, n, g.vh, 1, 1, 1, sw)
+            rc, st = stag.stag_cg_solve(ctx, g, [m] * n, fb, fx,
+                                        stag.cg_params(tol=tol, inner="f32", small_lattice=False))
+            assert rc == 0, st
+            res.append(([s["iters"] for s in st], fx.store()))
+    for it, x in res[1:]:
+        assert it == res[0][0] and np.array_equal(x, res[0][1])
+    Ax = oracle_apply_A(U, res[0][1], L, m)
+    r = [math.sqrt(ostag.norm2(b[k] - Ax[k]) / ostag.norm2(b[k])) for k in range(n)]
+    assert max(r) <= tol

@@ -99,7 +99,7 @@ def _shapes(nrhs):
     for S1 in (1, 2, 4):
         for S2 in (1, 2, 4):
             for nt in ((0, 1) if nrhs == 1 else (1,)):
-                for sw in (0, 1):
+                for sw in ((0, 1) if nrhs == 1 else (0, 1, 2, 3, 4)):
                     yield S1, S2, nt, sw
 
 
