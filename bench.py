@@ -658,6 +658,15 @@ def main():
     sec, last = timed_solves(stag, torch, ctx, g, mass, fb, fx, params, args.steps)
     log("timed", args.steps, "solves:", round(sec * 1e3, 3), "ms each;", last)
 
+    # the same kernels inside a solve: one more solve with its kernels launched
+    # eagerly, events recorded at each kernel's start and end (the graph
+    # replays of the timed region cannot be bracketed kernel by kernel)
+    stag.stag_timing_enable(ctx, True)
+    stag.stag_cg_solve(ctx, g, [mass], fb, fx, params)
+    in_solve = {name: stag.stag_timing_read(ctx, kk) for name, kk in
+                (("hop_stage1", stag.K_HOP1), ("hop_stage2", stag.K_HOP2), ("update", stag.K_UPDATE))}
+    stag.stag_timing_enable(ctx, False)
+
     # ---- the iteration's kernels, launched exactly as in the solve, timed
     # back to back between HIP events on the library's stream
     us = stag.stag_time_kernels(ctx, g, inner, 1, reps=200)
@@ -678,6 +687,14 @@ def main():
                            f"nt={tunes[inner]['nt']} swizzle={tunes[inner]['swizzle']})"),
                 "avg_us": d["avg_us"],
                 "bytes_per_launch": d["bytes_per_launch"]}
+    n_in, ms_in = in_solve[dom]
+    in_us = ms_in * 1e3 / max(n_in, 1)
+    roofline["in_solve"] = {"launches": n_in, "avg_us": round(in_us, 3),
+                            "GB/s": round(d["bytes_per_launch"] / (in_us * 1e-6) / 1e9, 1),
+                            "frac": round(d["bytes_per_launch"] / (in_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                            "how": "one solve with its kernels launched eagerly (no graph), "
+                                   "events recorded at each kernel's start and end; mean over all "
+                                   "of its launches of the kernel (inactive-slot launches included)"}
     iters = last["iters"]
     per_iter_us = sec * 1e6 / max(iters, 1)
     log("kernels", kinds, "per-iteration wall", round(per_iter_us, 2), "us")

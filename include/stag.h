@@ -374,8 +374,9 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* gauge, int prec, int nrhs, stag_t
 int stag_tune_counts(const stag_ctx* ctx, int* loaded, int* measured);
 
 /* ---------------------------------------------------------------- timing
- * While enabled, stag_cg_solve launches its kernels eagerly (no graph) and
- * brackets each with HIP events on the launch stream; stag_timing_read
+ * While enabled, stag_cg_solve launches its kernels eagerly (no graph) with
+ * HIP events recorded at each kernel's start and end (hipExtLaunchKernel, on
+ * the launch stream); stag_timing_read
  * returns the number of launches and their summed duration per kind.
  * stag_timing_enable waits for the device and resets the counters.
  */

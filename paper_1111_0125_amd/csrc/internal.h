@@ -235,8 +235,8 @@ int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, siz
                  hipStream_t stream, bool escalating = false);
 
 // Event timing helpers (no-ops when timing is off).
-hipError_t timing_begin(stag_ctx* ctx, hipStream_t s, hipEvent_t* ev);
-hipError_t timing_end(stag_ctx* ctx, hipStream_t s, int kind, hipEvent_t start);
+hipError_t timing_events(stag_ctx* ctx, hipEvent_t* a, hipEvent_t* b);  // two pooled events
+void timing_push(stag_ctx* ctx, int kind, hipEvent_t a, hipEvent_t b);   // record a bracketed launch
 void timing_collect(stag_ctx* ctx);  // accumulate every completed record
 
 // Fields of HopArgs used only by the fp64 stages of a reliable update.

@@ -196,16 +196,22 @@ struct Ctx {
     int variant;  // mixed CG variant of the run (MixedVariant)
 };
 
-// Launch `fn` bracketed by timing events when the run is timed.
+// Launch `fn` (one kernel) with timing events recorded at the kernel's
+// start and end (hipExtLaunchKernel) when the run is timed.
 template <typename F>
 hipError_t timed_launch(const Ctx& c, int kind, F&& fn) {
     if (!c.timed) return fn();
-    hipEvent_t a = nullptr;
-    hipError_t err = timing_begin(c.e->ctx, c.is.stream, &a);
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t err = timing_events(c.e->ctx, &a, &b);
     if (err != hipSuccess) return err;
+    Issue& is = const_cast<Issue&>(c.is);  // eager launches only: no graph is being built
+    is.ev_start = a;
+    is.ev_stop = b;
     err = fn();
+    is.ev_start = is.ev_stop = nullptr;
     if (err != hipSuccess) return err;
-    return timing_end(c.e->ctx, c.is.stream, kind, a);
+    timing_push(c.e->ctx, kind, a, b);
+    return hipSuccess;
 }
 
 Reduce make_red(stag_engine* e, int kind, double* partials = nullptr) {

@@ -75,42 +75,37 @@ static void tune_cache_append(const char* path, const std::string& key, const Ho
     fclose(f);
 }
 
-hipError_t timing_begin(stag_ctx* ctx, hipStream_t s, hipEvent_t* ev) {
+// Two events from the context's pool (created when it is empty).
+hipError_t timing_events(stag_ctx* ctx, hipEvent_t* a, hipEvent_t* b) {
     Timing& T = ctx->timing;
-    hipEvent_t a = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
     {
         std::lock_guard<std::mutex> lk(T.mu);
-        if (!T.pool.empty()) {
-            a = T.pool.back();
+        for (int i = 0; i < 2 && !T.pool.empty(); ++i) {
+            ev[i] = T.pool.back();
             T.pool.pop_back();
         }
     }
-    if (!a) {
-        hipError_t e = hipEventCreate(&a);
-        if (e != hipSuccess) return e;
+    for (int i = 0; i < 2; ++i) {
+        if (ev[i]) continue;
+        hipError_t e = hipEventCreate(&ev[i]);
+        if (e != hipSuccess) {
+            std::lock_guard<std::mutex> lk(T.mu);
+            for (int k = 0; k < i; ++k) T.pool.push_back(ev[k]);
+            return e;
+        }
     }
-    *ev = a;
-    return hipEventRecord(a, s);
+    *a = ev[0];
+    *b = ev[1];
+    return hipSuccess;
 }
 
-hipError_t timing_end(stag_ctx* ctx, hipStream_t s, int kind, hipEvent_t start) {
+// A launch bracketed by events a and b: its duration is read at the next
+// timing_collect.
+void timing_push(stag_ctx* ctx, int kind, hipEvent_t a, hipEvent_t b) {
     Timing& T = ctx->timing;
-    hipEvent_t b = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(T.mu);
-        if (!T.pool.empty()) {
-            b = T.pool.back();
-            T.pool.pop_back();
-        }
-    }
-    if (!b) {
-        hipError_t e = hipEventCreate(&b);
-        if (e != hipSuccess) return e;
-    }
-    hipError_t e = hipEventRecord(b, s);
     std::lock_guard<std::mutex> lk(T.mu);
-    T.pending.push_back({kind, start, b});
-    return e;
+    T.pending.push_back({kind, a, b});
 }
 
 void timing_collect(stag_ctx* ctx) {

@@ -266,6 +266,10 @@ def cmd_iteration(a):
     fs, fkib, cname = calibration(fetch, copy_bytes, 3)
     ws, wkib, _ = calibration(write, run["copy_bytes_written"], 3)
     inner, links = run.get("inner", "f32"), run.get("links", "r12")
+    traced = {}
+    if a.trace:
+        for _, name, us in read_trace(a.trace):
+            traced.setdefault(name, []).append(us)
     vh = run["vh"]
     kern = {}
     for rows, key in ((fetch, "fetch"), (write, "write")):
@@ -303,6 +307,10 @@ def cmd_iteration(a):
                      "dispatches": [len(d["fetch"]), len(d["write"])],
                      "hbm_bytes_per_launch": int(round(b)), "algorithmic_bytes_per_launch": alg,
                      "ratio": round(b / alg, 4)}
+        if traced.get(name):
+            t = statistics.mean(traced[name])
+            out[name]["traced_us"] = round(t, 3)
+            out[name]["compulsory_GB/s_traced"] = round(alg / (t * 1e-6) / 1e9, 1)
     blob = {"workload": a.workload,
             "links": links, "kernel_src_sha256": run["kernel_src_sha256"],
             "fetch_scale": round(fs, 5), "write_scale": round(ws, 5), "kernels": out}
@@ -320,12 +328,17 @@ def cmd_iteration(a):
               "stages from r and the previous d).", "",
               f"Calibration on the copy kernel (`{cname}`): FETCH_SIZE reads {fkib:.1f} KiB per "
               f"dispatch (scale {fs:.5f}), WRITE_SIZE {wkib:.1f} KiB (scale {ws:.5f}).", "",
+              "HBM MB counts the bytes between L2 and the memory fabric (MALL or HBM); "
+              "traced us is the mean kernel duration over every dispatch of the symbol in the "
+              "`--kernel-trace` run of the same program (when given).", "",
               "| kernel | dispatches (fetch / write run) | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM MB per "
-              "launch | compulsory MB | ratio |", "|---|---:|---:|---:|---:|---:|---:|"]
+              "launch | compulsory MB | ratio | traced us | compulsory GB/s |",
+              "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
     for name, e in out.items():
         lines.append(f"| `{name}` | {e['dispatches'][0]} / {e['dispatches'][1]} | {e['fetch_kib']} | "
                      f"{e['write_kib']} | {e['hbm_bytes_per_launch'] / 1e6:.2f} | "
-                     f"{e['algorithmic_bytes_per_launch'] / 1e6:.2f} | {e['ratio']:.3f} |")
+                     f"{e['algorithmic_bytes_per_launch'] / 1e6:.2f} | {e['ratio']:.3f} | "
+                     f"{e.get('traced_us', '')} | {e.get('compulsory_GB/s_traced', '')} |")
     lines += ["", "`bench.py` reads the block below to fill `roofline.traffic` for its dominant "
               "kernel, only while `kernel_src_sha256` matches the current device-code sources and "
               "the links match.", "", "```json", json.dumps(blob, indent=1), "```", ""]
@@ -346,7 +359,7 @@ def cmd_headline(a):
     ev = bench["roofline"]["avg_us"]
     byts = bench["roofline"]["bytes_per_launch"]
     rows = [("timing loop (`stag_time_kernels`, last %d launches)" % a.reps, loop),
-            ("the solves' launches (warm-up and timed solves, HIP graphs)", solves),
+            ("the solves' launches (warm-up and timed solves, HIP graphs; the eager solve)", solves),
             (f"the solves' launches longer than {a.idle_us} us (active slot)", active)]
     lines = [f"# rocprofv3 kernel trace: the dominant kernel of the {bench['config']['workload']}", "",
              "Commands (from the repository root on one MI355X; `<repo>` is that root), the "
@@ -356,8 +369,9 @@ def cmd_headline(a):
     lines += ["", f"Kernel: `{sym}` ({bench['roofline']['kernel']}), {byts} compulsory bytes per "
               "launch. In the trace its launches are the warm-up and timed solves' (graph "
               "replays; a launch whose slot is inactive, after a flag until its segment's fix-up "
-              "or after convergence, reads the state and exits) followed by the 3 + 200 launches "
-              "of `stag_time_kernels` that `roofline` is computed from.", "",
+              "or after convergence, reads the state and exits), one more solve's launched "
+              "eagerly (`roofline.in_solve`), and last the 3 + 200 launches of "
+              "`stag_time_kernels` that `roofline` is computed from.", "",
               "| launches | count | mean us | median us | GB/s at the mean | frac of 8 TB/s |",
               "|---|---:|---:|---:|---:|---:|"]
     for label, d in rows:
@@ -366,6 +380,10 @@ def cmd_headline(a):
         m = statistics.mean(d)
         lines.append(f"| {label} | {len(d)} | {m:.3f} | {statistics.median(d):.3f} | "
                      f"{byts / (m * 1e-6) / 1e9:.1f} | {byts / (m * 1e-6) / 8e12:.4f} |")
+    ins = bench["roofline"].get("in_solve")
+    if ins:
+        lines += ["", f"The unprofiled run's eager solve (`roofline.in_solve`): {ins['avg_us']} us per "
+                  f"launch over {ins['launches']} launches, {ins['frac']} of 8 TB/s."]
     lines += ["", f"The unprofiled run's `roofline`: {ev} us per launch (events at the kernel's start "
               f"and end around each of the 200 launches), {bench['roofline']['achieved']} GB/s = "
               f"{bench['roofline']['frac']} of 8 TB/s; its solve took "
@@ -401,6 +419,7 @@ def main(argv=None):
     p.add_argument("--out", required=True)
     p = sub.add_parser("iteration")
     p.add_argument("--json", required=True)
+    p.add_argument("--trace")
     p.add_argument("--workload", default="16^3x32 exp(i 0.3 H) links, the CG iteration kernels "
                    "of every precision (f64: plain CG; f32, f16s: mixed), one RHS")
     p.add_argument("--program", default="`bench.py --kernels-only` builds the 16^3x32 workload, "

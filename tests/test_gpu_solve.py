@@ -357,3 +357,36 @@ def test_f16s_hands_over_at_first_slow_cycle(stag, ctx):
     rc32, st32, _ = solve(stag, ctx, L, U, b, [m], tol, inner="f32")
     # the fp16 pass ends near where the oracle's does; the rest is about an fp32 solve
     assert st[0]["iters"] <= st32[0]["iters"] + 1.25 * est["iters"] + 50
+
+
+def test_timing_mode_counts_launches_and_keeps_results(stag, ctx):
+    """With kernel timing on, a solve runs eagerly with events at each
+    kernel's start and end: the same iterations and bits as the graph solve,
+    one stage-1, stage-2 and update launch per iteration (plus the launches
+    of flagged slots idling to the end of their segment, and up to two
+    blocks of K = 64 iterations enqueued behind the poll that sees
+    convergence), and plausible per-launch durations."""
+    L, m, tol = (8, 8, 8, 8), 0.05, 1e-8
+    U = links(L, "haar", 45)
+    b = synth.gaussian_rhs(L, 1, 46)
+    g = ctx.gauge(L, U, precisions=("f64", "f32"))
+    fb = ctx.field(g, 0, "f64", 1).load(b)
+    fx = ctx.field(g, 0, "f64", 1)
+    p = stag.cg_params(tol=tol, inner="f32")
+    rc, st = stag.stag_cg_solve(ctx, g, [m], fb, fx, p)
+    x_ref = fx.store()
+    stag.stag_timing_enable(ctx, True)
+    try:
+        rc2, st2 = stag.stag_cg_solve(ctx, g, [m], fb, fx, p)
+        counts = {k: stag.stag_timing_read(ctx, k) for k in (stag.K_HOP1, stag.K_HOP2, stag.K_UPDATE)}
+    finally:
+        stag.stag_timing_enable(ctx, False)
+    log("timed solve", st2[0], counts)
+    assert rc == rc2 == 0 and st2[0]["iters"] == st[0]["iters"]
+    assert np.array_equal(fx.store(), x_ref)
+    n1, n2, nu = (counts[k][0] for k in (stag.K_HOP1, stag.K_HOP2, stag.K_UPDATE))
+    assert n1 == n2 == nu and st[0]["iters"] <= n1 <= st[0]["iters"] + 3 * 64
+    for n, ms in counts.values():
+        assert 0.5 <= ms * 1e3 / n <= 1000.0
+    for o in (fb, fx, g):
+        o.destroy()
