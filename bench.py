@@ -307,6 +307,24 @@ def c3_solves(stag, torch, synth, costs):
                           "true_rel_res": s0["true_rel_res"], "inner_final": s0["inner_final"],
                           "us_per_iteration": round(dt * 1e6 / max(s0["iters"], 1), 2)}
             log("c3", inner, out[inner])
+        # the same links at m = 0.1 and 1e-8, a system fp16 storage can refine
+        # (kappa u16 near 1): where its lower traffic per iteration pays
+        wc = {"mass": 0.1, "tol": 1e-8}
+        for inner in ("f16s", "f32", "f64"):
+            p = stag.cg_params(tol=1e-8, inner=inner)
+            stag.stag_cg_solve(ctx, g, [0.1], fb, fx, p)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st = stag.stag_cg_solve(ctx, g, [0.1], fb, fx, p)
+            torch.cuda.synchronize()
+            wc[inner] = {"time_to_tol_s": round(time.perf_counter() - t0, 4), "status": rc,
+                         "iters": st[0]["iters"], "inner_final": st[0]["inner_final"],
+                         "true_rel_res": st[0]["true_rel_res"]}
+        if all(wc[k]["status"] == 0 for k in ("f16s", "f32", "f64")):
+            wc["speedup_f16s_vs_f32"] = round(wc["f32"]["time_to_tol_s"] / wc["f16s"]["time_to_tol_s"], 3)
+            wc["speedup_f16s_vs_f64"] = round(wc["f64"]["time_to_tol_s"] / wc["f16s"]["time_to_tol_s"], 3)
+        out["m0.1_tol1e-8"] = wc
+        log("c3 links at m = 0.1", wc)
     if out["f64"]["status"] == 0:
         for inner in ("f16s", "f32"):
             if out[inner]["status"] == 0:
