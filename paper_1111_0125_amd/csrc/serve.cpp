@@ -54,9 +54,11 @@ struct Ticket {
     std::vector<char> escalated;       // per RHS: continued in fp32 from its x
     Clock::time_point t_submit, t_done;
     int remaining = 0;
-    struct Batch* batch = nullptr;
-    hipEvent_t done_ev = nullptr;   // recorded after the last result copy
-    bool finishing = false;         // all slots harvested, waiting for done_ev
+    // one event per harvested right-hand side, recorded on its batch's stream
+    // after its result copy (an escalated right-hand side finishes in another
+    // batch than the others, on another stream)
+    std::vector<hipEvent_t> copy_evs;
+    bool finishing = false;         // all slots harvested, waiting for copy_evs
     bool done = false;
     bool cancelled = false;
 };
@@ -143,8 +145,20 @@ static void batch_destroy(Batch* b) {
 
 static void ticket_free(stag_ctx* ctx, Ticket* t) {
     if (t->x_dev) dev_free(ctx, t->x_dev, t->x_bytes);
-    if (t->done_ev) (void)hipEventDestroy(t->done_ev);
+    for (hipEvent_t e : t->copy_evs) (void)hipEventDestroy(e);
     delete t;
+}
+
+// Whether every result copy of ticket t has completed.
+static bool copies_done(Ticket* t) {
+    for (hipEvent_t e : t->copy_evs) {
+        hipError_t q = hipEventQuery(e);
+        if (q != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+    }
+    return true;
 }
 
 // Try to place work item w into a batch. Returns STAG_OK when started,
@@ -252,7 +266,6 @@ static int admit(Serve* S, Work& w) {
         return rc;
     }
     bt->busy += n;
-    t->batch = bt;
     if (!w.cont) t->remaining = t->nrhs;
     return STAG_OK;
 }
@@ -272,9 +285,14 @@ static void harvest(Serve* S, Batch* b, const RhsState* h) {
         hipError_t err = launch_export(P64, (char*)b->e->x64 + (size_t)s * b->e->rs64, b->e->rs64,
                                        (char*)t->x_dev + (size_t)r * Vh * 48, (uint32_t)Vh, 1,
                                        b->stream);
+        hipEvent_t ev = nullptr;
+        if (err == hipSuccess) err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (err == hipSuccess) err = hipEventRecord(ev, b->stream);
+        if (ev) t->copy_evs.push_back(ev);
         if (err != hipSuccess) {
             (void)hipGetLastError();
             t->stats[r].status = STAG_EDEVICE;
+            (void)hipStreamSynchronize(b->stream);  // the copy is then waited for here
         }
         b->slot_ticket[s] = nullptr;
         b->busy -= 1;
@@ -307,11 +325,7 @@ static void harvest(Serve* S, Batch* b, const RhsState* h) {
             continue;
         }
         t->remaining -= 1;
-        if (t->remaining == 0) {
-            if (!t->done_ev) (void)hipEventCreateWithFlags(&t->done_ev, hipEventDisableTiming);
-            (void)hipEventRecord(t->done_ev, b->stream);
-            t->finishing = true;
-        }
+        if (t->remaining == 0) t->finishing = true;
     }
     int hi = 0;
     for (int s = 0; s < (int)b->slot_ticket.size(); ++s)
@@ -381,14 +395,9 @@ static void scheduler(Serve* S) {
                     for (int r : w.rhs) t->stats[r].status = rcs[i];
                     if (w.cont) {
                         // the other right-hand sides finish where they run; the
-                        // ticket completes when the last result copy has
+                        // ticket completes when their result copies have
                         t->remaining -= 1;
-                        if (t->remaining == 0) {
-                            if (!t->done_ev)
-                                (void)hipEventCreateWithFlags(&t->done_ev, hipEventDisableTiming);
-                            (void)hipEventRecord(t->done_ev, t->batch ? t->batch->stream : nullptr);
-                            t->finishing = true;
-                        }
+                        if (t->remaining == 0) t->finishing = true;
                     } else {
                         t->done = true;
                         t->t_done = Clock::now();
@@ -420,15 +429,10 @@ static void scheduler(Serve* S) {
             std::lock_guard<std::mutex> lk(S->mu);
             for (auto& kv : S->tickets) {
                 Ticket* t = kv.second;
-                if (t->finishing && !t->done) {
-                    hipError_t q = hipEventQuery(t->done_ev);
-                    if (q == hipSuccess) {
-                        t->done = true;
-                        t->t_done = Clock::now();
-                        progress = true;
-                    } else {
-                        (void)hipGetLastError();
-                    }
+                if (t->finishing && !t->done && copies_done(t)) {
+                    t->done = true;
+                    t->t_done = Clock::now();
+                    progress = true;
                 }
             }
             // release batches idle for a while
