@@ -307,6 +307,20 @@ def _q_link_f16(u32, s):
             + 1j * (im.astype(np.float32) * safe).astype(np.float32)).astype(np.complex64)
 
 
+def su3_third_row(W):
+    """The link with its third row replaced by the conjugated cross product
+    of its first two, computed in W's precision (Sec.3.3, link compression:
+    for a special unitary 3x3 matrix the third row follows from the other
+    two, so only twelve real parameters need storing)."""
+    a, b = W[..., 0, :], W[..., 1, :]
+    c = np.conj(np.cross(a, b)).astype(W.dtype)
+    return np.concatenate([W[..., :2, :], c[..., None, :]], axis=-2)
+
+
+def _dag(W):
+    return np.conj(np.swapaxes(W, -1, -2))
+
+
 class LowOperator:
     """A in the inner solver's precision: fp32 arithmetic on stored operands.
 
@@ -314,10 +328,16 @@ class LowOperator:
     ``prec`` = "f16s": links stored as fp16 with the per-site scale of
     ``f16s_link_scale``; the intermediate odd-site vector and the result are
     stored with ``q_f16s``. Arithmetic is fp32 in both cases.
+    ``r12``: twelve-parameter links (SU(3) only): each hop stores the first
+    two rows of the matrix it multiplies by, W_mu(x) forward and
+    W_mu(x - mu)^+ backward, in the storage precision, and the third row is
+    rebuilt from the stored rows in fp32 (``su3_third_row``).
     ``Ulong``: the improved operator (three-hop terms, U = fat links).
     """
 
-    def __init__(self, U, L, m, prec, Ulong=None):
+    def __init__(self, U, L, m, prec, Ulong=None, r12=False):
+        if r12 and Ulong is not None:
+            raise ValueError("twelve-parameter links need SU(3) links")
         self.L = extents(L)
         self.m2 = np.float32(m * m)
         self.prec = prec
@@ -336,6 +356,9 @@ class LowOperator:
                 if prec == "f16s":
                     u = _q_link_f16(u, s)
                     ub = _q_link_f16(ub, s)
+                if r12:
+                    u = su3_third_row(u)
+                    ub = _dag(su3_third_row(_dag(ub)))
                 fwd = (e[mu][..., None, None] * u).astype(np.complex64)
                 bwd = (np.roll(e[mu], dist, axis=ax)[..., None, None] * ub).astype(np.complex64)
                 self.hops.append((dist, ax, fwd, bwd))
@@ -360,12 +383,13 @@ class LowOperator:
 # Fig.2 iterative refinement (outer fp64, fresh low-precision inner CG)
 # --------------------------------------------------------------------------
 
-def refinement_cg(U, L, m, b, tol, prec="f32", eps_in=0.1, max_iter=None, Ulong=None):
+def refinement_cg(U, L, m, b, tol, prec="f32", eps_in=0.1, max_iter=None, Ulong=None, r12=False):
     """Mixed CG by iterative refinement, Fig.2: the inner solve starts from
     y = 0, r = r_k, d = r_k every outer step (no information carried over).
-    Ulong: the improved operator (U = fat links)."""
+    Ulong: the improved operator (U = fat links); r12: twelve-parameter
+    low-precision links (``LowOperator``)."""
     A64 = lambda v: apply_A(U, v, L, m, Ulong)
-    Alow = LowOperator(U, L, m, prec, Ulong)
+    Alow = LowOperator(U, L, m, prec, Ulong, r12)
     q = quantiser(prec)
     b = np.asarray(b, dtype=np.complex128)
     max_iter = default_max_iter(b.size) if not max_iter or max_iter <= 0 else max_iter
@@ -406,7 +430,7 @@ def refinement_cg(U, L, m, b, tol, prec="f32", eps_in=0.1, max_iter=None, Ulong=
 
 def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
              max_iter=None, max_stall=20, carry_direction=True, update="both", Ulong=None,
-             slow_ratio=None):
+             slow_ratio=None, r12=False):
     """Corrected mixed-precision CG of Sec.3.2, emulated on the CPU.
 
     Inner iterations run on stored low-precision vectors (fp32 arithmetic,
@@ -438,6 +462,7 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
     when its iterated residual meets the tolerance the true residual is
     computed once and decides ("inaccurate" if it misses).
     ``Ulong``: the improved operator (U = fat links), in both precisions.
+    ``r12``: twelve-parameter links in the low precision (``LowOperator``).
     ``slow_ratio``: end with status "stall" at the first (non-stall) update
     whose true residual norm fell by less than this factor since the previous
     update: iterative refinement contracts the true residual by about the inner
@@ -452,7 +477,7 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
     if stall_iters is None:
         stall_iters = 100 if prec == "f16s" else math.inf
     A64 = lambda v: apply_A(U, v, L, m, Ulong)
-    Alow = LowOperator(U, L, m, prec, Ulong)
+    Alow = LowOperator(U, L, m, prec, Ulong, r12)
     q = quantiser(prec)
     b = np.asarray(b, dtype=np.complex128)
     max_iter = default_max_iter(b.size) if not max_iter or max_iter <= 0 else max_iter

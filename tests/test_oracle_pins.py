@@ -256,6 +256,35 @@ def test_f32_low_operator_error():
     assert 1e-5 < e16 < 1e-3
 
 
+def test_third_row_of_special_unitary_links():
+    # for det U = 1 and U U^+ = 1 the third row is the conjugated cross
+    # product of the first two (Sec.3.3); Haar links are phase-fixed to det 1
+    U = synth.haar_links((4, 4, 4, 4), 75)
+    assert np.abs(stag.su3_third_row(U) - U).max() < 1e-14
+    # a unitary link with det e^{i phi} gets a third row off by e^{-i phi}
+    W = U[0, 0, 0, 0, 0] * np.exp(0.2j)
+    r = stag.su3_third_row(W)
+    assert np.allclose(r[:2], W[:2], rtol=0, atol=0)
+    assert np.allclose(r[2], W[2] * np.exp(-0.6j), atol=1e-14)
+
+
+@pytest.mark.parametrize("prec,lo,hi", [("f32", 1e-9, 1e-6), ("f16s", 1e-5, 1e-3)])
+def test_twelve_parameter_low_operator_error(prec, lo, hi):
+    # rebuilding the third row from stored rows adds an error of the order of
+    # the storage rounding and no more: within the full-storage bounds and at
+    # most twice the full-storage error on the same links and vector
+    L, m = (6, 4, 4, 8), 0.1
+    U = synth.haar_links(L, 73)
+    v = synth.gaussian_rhs(L, 1, 74)[0]
+    ref = stag.apply_A(U, v, L, m)
+    full = rel(stag.LowOperator(U, L, m, prec)(v), ref)
+    r12 = rel(stag.LowOperator(U, L, m, prec, r12=True)(v), ref)
+    assert lo < r12 < hi
+    assert r12 < 2 * full
+    with pytest.raises(ValueError):
+        stag.LowOperator(U, L, m, prec, Ulong=U, r12=True)
+
+
 # ---------------------------------------------------------------- mixed CG (Sec.3)
 
 @pytest.fixture(scope="module")
