@@ -43,7 +43,6 @@ KERNEL_NAMES = ("hop_stage1", "hop_stage2", "update")
 
 def kernel_bytes(which, inner, vh, costs, r12):
     """Algorithmic bytes of one launch of a CG-iteration kernel (as the solver runs it)."""
-    r12 = r12 and inner != "f16s"
     if which == 0:
         return vh * costs.hop_bytes_per_site(inner, 1, lazy=True, r12=r12)
     if which == 1:
@@ -160,7 +159,7 @@ def a_apply_leg(stag, torch, costs, ctx, g, leg, prec, v, mass, reps, improved=F
     fo.destroy()
     byts = vh * costs.a_bytes_per_site(prec, r12=r12, improved=improved)
     gbs = byts / (ms * 1e-3) / 1e9
-    paper_b = vh * costs.paper_a_bytes_per_site(prec, r12=r12 and prec != "f16s", improved=improved)
+    paper_b = vh * costs.paper_a_bytes_per_site(prec, r12=r12, improved=improved)
     shape = {"S1": best[0], "S2": best[0], "nt": best[1], "swizzle": best[2]}
     out = {"us_per_A": round(ms * 1e3, 2), "trials_us_per_A": [round(t * 1e3, 2) for t in trials],
            "GB/s": round(gbs, 1),
@@ -272,7 +271,7 @@ def a_apply_bandwidth(stag, torch, costs, synth, reps=50, order=None):
     out = {}
     for r12 in (False, True):
         with stag.Context(0) as ctx:
-            precs = ("f64", "f32") if r12 else ("f64", "f32", "f16s")
+            precs = ("f64", "f32", "f16s")
             g = ctx.gauge(L, U, precisions=precs, r12=r12)
             for prec in precs:
                 key = prec + ("_r12" if r12 else "")
@@ -288,7 +287,7 @@ def c3_solves(stag, torch, synth, costs):
     cfg = synth.CONFIGS[name]
     L, m, tol = cfg["L"], cfg["mass"], cfg["tol"]
     U, b = c3_inputs(synth)
-    out = {"lattice": list(L), "mass": m, "tol": tol, "links": "12-parameter f64/f32, full f16s"}
+    out = {"lattice": list(L), "mass": m, "tol": tol, "links": "12-parameter"}
     with stag.Context(0) as ctx:
         g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"), r12=True)
         fb = ctx.field(g, 0, "f64", 1).load(b)
@@ -700,7 +699,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(d["GB/s"] / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel_symbol": dom_name,
-                "kernel": (f"{dom} ({inner}, 16^3x32, {'12-parameter' if r12 and inner != 'f16s' else 'full'}"
+                "kernel": (f"{dom} ({inner}, 16^3x32, {'12-parameter' if r12 else 'full'}"
                            f" links, S1={tunes[inner]['S1']} S2={tunes[inner]['S2']} "
                            f"nt={tunes[inner]['nt']} swizzle={tunes[inner]['swizzle']})"),
                 "avg_us": d["avg_us"],
@@ -735,7 +734,7 @@ def main():
                          f"m={mass}, 1 complex Gaussian RHS (seed {cfg['rhs_seed']}), "
                          f"true residual {tol:g}, {inner}-inner CG + fp64 reliable updates"),
             "lattice": list(L), "mass": mass, "tol": tol, "inner": inner, "nrhs": 1,
-            "links": "12-parameter f64/f32 (third row rebuilt), full f16s" if r12 else "full",
+            "links": "12-parameter (third row rebuilt)" if r12 else "full",
         },
         "roofline": roofline,
         "solve": {"iters": iters, "reliable_updates": last["reliable_updates"],
@@ -743,7 +742,7 @@ def main():
                   "us_per_iteration": round(per_iter_us, 3),
                   "kernel_us_per_iteration": round(sum(us), 3),
                   "bytes_per_iteration": costs.cg_iteration_bytes_per_site(
-                      inner, True, r12=r12 and inner != "f16s") * vh},
+                      inner, True, r12=r12) * vh},
         "kernels": kinds,
         "tune": tunes,
         "tune_table": {"path": os.environ.get("STAG_TUNE_CACHE"), "loaded": loaded,

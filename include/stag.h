@@ -77,12 +77,14 @@ extern "C" {
 #define STAG_MASK_F64 (1 << STAG_F64)
 #define STAG_MASK_F32 (1 << STAG_F32)
 #define STAG_MASK_F16S (1 << STAG_F16S)
-/* Gauge option (or-ed into prec_mask): store the F64 and F32 copies with 12
- * real parameters per link (two rows; the kernels rebuild the third as the
- * conjugated cross product of the first two and apply the staggered phase
- * from the site's coordinates), cutting link traffic by a third. Needs
- * SU(3) links: stag_gauge_create checks |U U^+ - 1| and |det U - 1| <= 1e-10
- * on every link and fails with EINVAL otherwise. F16S copies stay full. */
+/* Gauge option (or-ed into prec_mask): store every copy with 12 real
+ * parameters per link (two rows; the kernels rebuild the third as the
+ * conjugated cross product of the first two, in the copy's arithmetic
+ * precision, and apply the staggered phase from the site's coordinates),
+ * cutting link traffic by a third (Sec.3.3). F16S copies keep their per-site
+ * scale, taken over the full links. Needs SU(3) links: stag_gauge_create
+ * checks |U U^+ - 1| and |det U - 1| <= 1e-10 on every link and fails with
+ * EINVAL otherwise. */
 #define STAG_GAUGE_R12 (1 << 4)
 
 #define STAG_MAX_RHS 16 /* right-hand sides per field / per solve call */
@@ -121,7 +123,7 @@ int stag_memory_used(const stag_ctx* ctx, size_t* bytes);
  *               context's device otherwise. Copied; the caller keeps ownership.
  *   prec_mask   which stored copies to build (STAG_MASK_*); solves need
  *               STAG_MASK_F64 plus the mask of their inner precision. May
- *               include STAG_GAUGE_R12 (12-parameter F64 / F32 copies).
+ *               include STAG_GAUGE_R12 (12-parameter copies).
  * The library folds the phases eta_mu into the links (or, with
  * STAG_GAUGE_R12, applies them from the coordinates), splits them by parity
  * and stores, per output site, its eight hop links in a site-coalesced

@@ -229,8 +229,8 @@ class Context:
 
 
 class Gauge:
-    """A resident gauge field (stag_gauge_create); r12: 12-parameter F64 / F32
-    copies (SU(3) links only). With ``long`` (stag_gauge_create_improved) the
+    """A resident gauge field (stag_gauge_create); r12: 12-parameter copies
+    (SU(3) links only). With ``long`` (stag_gauge_create_improved) the
     improved operator: U holds the fat links, ``long`` the long links, both
     host arrays or both device tensors."""
 

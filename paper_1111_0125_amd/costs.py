@@ -13,7 +13,8 @@ compulsory one.
 Bytes per stored link matrix / colour vector:
   f64  144 / 48   (12-parameter storage: 96 per link)
   f32   72 / 24   (12-parameter storage: 48 per link)
-  f16s  36 (+ one 4-byte scale per site shared by its 8 links) / 16
+  f16s  36 (12-parameter: 24; + one 4-byte scale per site shared by its
+        8 links) / 16
 
 The improved operator (``improved=True``: fat links plus three-hop long
 links) reads sixteen links per output site and does sixteen hops, so its
@@ -22,8 +23,8 @@ neighbours are again the caches' job).
 """
 
 LINK_BYTES = {"f64": 144, "f32": 72, "f16s": 36}
-# 12-parameter storage (two rows per SU(3) link), f64 and f32 copies only
-LINK_BYTES_R12 = {"f64": 96, "f32": 48, "f16s": 36}
+# 12-parameter storage (two rows per SU(3) link)
+LINK_BYTES_R12 = {"f64": 96, "f32": 48, "f16s": 24}
 SPINOR_BYTES = {"f64": 48, "f32": 24, "f16s": 16}
 SITE_SCALE_BYTES = {"f64": 0, "f32": 0, "f16s": 4}
 

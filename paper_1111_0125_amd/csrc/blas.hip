@@ -255,9 +255,9 @@ hipError_t launch_vec(int prec, int N, int op, const VecArgs& a, const Issue& is
 // ------------------------------------------------------------------ reduction finalisation
 
 template <int N>
-__global__ __launch_bounds__(kBlock) void k_finalize(Reduce R, unsigned run_mask) {
+__global__ __launch_bounds__(64 * N) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_finalize(Reduce R, unsigned run_mask) {
     __shared__ RhsState ls[N];
-    finalize_block<N>(R, run_mask, ls);
+    finalize_wide<N>(R, run_mask, ls);
 }
 
 template <int N>
@@ -265,7 +265,7 @@ static hipError_t issue_finalize(const Reduce& R, unsigned run_mask, const Issue
     Reduce r = R;
     unsigned m = run_mask;
     void* args[] = {&r, &m};
-    return issue_kernel(is, reinterpret_cast<const void*>(&k_finalize<N>), 1, kBlock, args);
+    return issue_kernel(is, reinterpret_cast<const void*>(&k_finalize<N>), 1, 64 * N, args);
 }
 
 hipError_t launch_finalize(int N, const Reduce& R, unsigned run_mask, const Issue& is) {

@@ -120,7 +120,7 @@ hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, con
     a.lazy_r_rs = lazy_r_rs;
     a.gauge = g->G[prec][p_out];
     a.gscale = prec == P16S ? g->gscale[p_out] : nullptr;
-    a.r12 = g->r12 && prec != P16S;
+    a.r12 = g->r12;
     a.npairs = g->npairs;
     a.in = in;
     a.in_rs = in_rs;
@@ -133,6 +133,11 @@ hipError_t enqueue_hop(const stag_gauge* g, int prec, int S, int N, int epi, con
     for (int r = 0; r < kMaxN; ++r) a.m2[r] = m2 ? m2[r] : 0.0;
     a.st = st;
     a.run_mask = run_mask;
+    // a predicated fp64 launch of one right-hand side (fix-ups and checks,
+    // their slot flagged only now and then) looks at the flags before
+    // requesting operands; the iteration's own launches request them first,
+    // the state's latency overlapping theirs
+    a.gate = prec == P64 && N == 1 && st && !fin && run_mask != F_ACTIVE;
     a.p_out = p_out;
     a.swizzle = t.swizzle;
     a.tile_bps = 0;

@@ -143,10 +143,11 @@ inline size_t spinor_rhs_bytes(int prec, size_t Vh) {
 // Hop pair mu (hops 2mu, 2mu+1) is 18 complex = words 18mu.. (P64) or 9mu..
 // (P32, P16S).
 // ---------------------------------------------------------------------------
-// 12-parameter storage (P64 / P32, SU(3) links): per output site and hop
-// pair mu, the first two rows of U_mu(x) then of U_mu(x - mu)^dagger (12
-// complex, no phases): P64 48 words of double2, P32 24 words of float4 at
-// [w][Vh]; pair mu is words 12mu.. (P64) or 6mu.. (P32). The kernels rebuild
+// 12-parameter storage (SU(3) links): per output site and hop pair mu, the
+// first two rows of U_mu(x) then of U_mu(x - mu)^dagger (12 complex, no
+// phases): P64 48 words of double2, P32 24 words of float4, P16S 24 words of
+// uint2 at [w][Vh] plus the site scale of the full form; pair mu is words
+// 12mu.. (P64) or 6mu.. (P32, P16S). The kernels rebuild
 // each third row as the conjugated cross product of the first two and apply
 // +eta_mu(x) to the forward and -eta_mu(x) to the backward link
 // (eta_mu(x - mu) = eta_mu(x): the phase depends on the coordinates before mu).
@@ -163,7 +164,7 @@ inline size_t link_bytes(int prec, size_t Vh, bool r12 = false, int npairs = 4) 
     const size_t k = (size_t)npairs / 4;
     if (prec == P64) return k * Vh * (r12 ? 48 : 72) * 16;
     if (prec == P32) return k * Vh * (r12 ? 24 : 36) * 16;
-    return k * Vh * 36 * 8;
+    return k * Vh * (r12 ? 24 : 36) * 8;
 }
 inline size_t gauge_parity_bytes(int prec, size_t Vh, bool r12 = false, int npairs = 4) {
     return link_bytes(prec, Vh, r12, npairs) + (prec == P16S ? Vh * 4 : 0);

@@ -113,6 +113,8 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
     const bool valid = s < Vh;
     // stage 1 forms the deferred direction at the neighbours it gathers
     const bool lazy_nb = EPI == EPI_PLAIN && a.lazy_r != nullptr;
+    // the improved operator's fat and long links are always stored full
+    const int r12 = NP == 4 ? a.r12 : 0;
 
     // Per-RHS state, finalised here from the previous reduction's partials
     // when a.fin is set. One RHS: each wavefront keeps it in registers (no
@@ -134,6 +136,17 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
     [[maybe_unused]] PairRaw<P> pl[PB];
     [[maybe_unused]] Raw<P> pwf[PB], pwb[PB], pown;
     if constexpr (N == 1) {
+        if constexpr (P == P64) {
+            // gated launches (the fp64 fix-ups and checks): an unflagged slot
+            // has nothing to do, no operand read and no partials (the
+            // reduction's consumer skips unflagged slots). Its own load and
+            // branch, so the others need not wait for the flags before
+            // their operand loads; the inner-precision kernels, never gated,
+            // carry no branch at all.
+            if (a.gate) {
+                if (!(a.st->flags & a.run_mask)) return;
+            }
+        }
         s1 = *(a.st ? a.st : &kNoState);
         if (a.st && !(s1.flags & a.run_mask)) act = 0;
         if (valid) {
@@ -148,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
             }
             static_for<0, PB>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
-                load_pair_raw<P, NT>(a.gauge, a.gscale, Vh, s, j * B + k, a.r12, pl[k]);
+                load_pair_raw<P, NT>(a.gauge, a.gscale, Vh, s, j * B + k, r12, pl[k]);
             });
         }
         if (a.st && a.fin.partials) {
@@ -210,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
             if constexpr (N == 1 && k < PB) {
                 nf = pnf[k];
                 nb = pnb[k];
-                finish_pair<P>(a.r12, eta_sign(mu & 3, x, y, z), pl[k], lr, li);
+                finish_pair<P>(r12, eta_sign(mu & 3, x, y, z), pl[k], lr, li);
             } else {
                 pair_neighbours<NP>(a.g, s, x, y, z, t, mu, nf, nb);
                 if constexpr (N == 1) {
@@ -218,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                     load_raw<P>(a, (const char*)a.in, 0, nf, lazy_nb, wfk);
                     load_raw<P>(a, (const char*)a.in, 0, nb, lazy_nb, wbk);
                 }
-                load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, a.r12, eta_sign(mu & 3, x, y, z), lr, li);
+                load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, r12, eta_sign(mu & 3, x, y, z), lr, li);
             }
 #pragma unroll
             for (int r = 0; r < N; ++r) {

@@ -83,7 +83,7 @@ struct stag_gauge {
     int mask = 0;
     void* G[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
     float* gscale[2] = {nullptr, nullptr};  // P16S
-    bool r12 = false;                       // P64 / P32 copies in 12-parameter form
+    bool r12 = false;                       // every copy in 12-parameter form
     int npairs = 4;                         // hop pairs per site: 8 for the improved operator
     size_t bytes = 0;
 };

@@ -190,7 +190,7 @@ struct PairRaw<P32> {
 };
 template <>
 struct PairRaw<P16S> {
-    u2v v[9];
+    u2v v[9];   // two entries each, as P32
     float sc;
 };
 
@@ -214,10 +214,14 @@ __device__ __forceinline__ void load_pair_raw(const void* G, const float* gscale
             for (int e = 6; e < 9; ++e) w.v[e] = ldg<NT>(g + (size_t)e * Vh);
         }
     } else {
-        const u2v* g = (const u2v*)G + (size_t)(9 * mu) * Vh + s;
+        const u2v* g = (const u2v*)G + (size_t)((r12 ? 6 : 9) * mu) * Vh + s;
         w.sc = gscale[s];
 #pragma unroll
-        for (int e = 0; e < 9; ++e) w.v[e] = ldg<NT>(g + (size_t)e * Vh);
+        for (int e = 0; e < 6; ++e) w.v[e] = ldg<NT>(g + (size_t)e * Vh);
+        if (!r12) {
+#pragma unroll
+            for (int e = 6; e < 9; ++e) w.v[e] = ldg<NT>(g + (size_t)e * Vh);
+        }
     }
 }
 
@@ -230,64 +234,65 @@ __device__ __forceinline__ void finish_pair(int r12, int eta, const PairRaw<P>& 
                                             typename Real<P>::T (&lr)[18],
                                             typename Real<P>::T (&li)[18]) {
     using T = typename Real<P>::T;
-    if constexpr (P == P16S) {
+    T fr[18], fi[18], cr[18], ci[18];  // full, compressed
+    if constexpr (P == P64) {
 #pragma unroll
-        for (int e = 0; e < 9; ++e) {
-            lr[2 * e] = h2f_lo(w.v[e].x) * w.sc;
-            li[2 * e] = h2f_hi(w.v[e].x) * w.sc;
-            lr[2 * e + 1] = h2f_lo(w.v[e].y) * w.sc;
-            li[2 * e + 1] = h2f_hi(w.v[e].y) * w.sc;
+        for (int e = 0; e < 18; ++e) {
+            fr[e] = w.v[e].x;
+            fi[e] = w.v[e].y;
+        }
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            cr[e] = w.v[e].x;
+            ci[e] = w.v[e].y;
+            cr[9 + e] = w.v[6 + e].x;
+            ci[9 + e] = w.v[6 + e].y;
         }
     } else {
-        T fr[18], fi[18], cr[18], ci[18];  // full, compressed
-        if constexpr (P == P64) {
-#pragma unroll
-            for (int e = 0; e < 18; ++e) {
-                fr[e] = w.v[e].x;
-                fi[e] = w.v[e].y;
-            }
-#pragma unroll
-            for (int e = 0; e < 6; ++e) {
-                cr[e] = w.v[e].x;
-                ci[e] = w.v[e].y;
-                cr[9 + e] = w.v[6 + e].x;
-                ci[9 + e] = w.v[6 + e].y;
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < 9; ++e) {
-                fr[2 * e] = w.v[e].x;
-                fi[2 * e] = w.v[e].y;
-                fr[2 * e + 1] = w.v[e].z;
-                fi[2 * e + 1] = w.v[e].w;
-            }
-#pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                cr[2 * e] = w.v[e].x;
-                ci[2 * e] = w.v[e].y;
-                cr[2 * e + 1] = w.v[e].z;
-                ci[2 * e + 1] = w.v[e].w;
-                cr[9 + 2 * e] = w.v[3 + e].x;
-                ci[9 + 2 * e] = w.v[3 + e].y;
-                cr[9 + 2 * e + 1] = w.v[3 + e].z;
-                ci[9 + 2 * e + 1] = w.v[3 + e].w;
-            }
-        }
-        third_row(cr, ci, 0);
-        third_row(cr, ci, 9);
-        const T sf = (T)eta, sb = -(T)eta;
+        // word e holds entries 2e and 2e + 1 (P32 as floats, P16S as
+        // fp16 pairs times the site scale)
+        T wr[18], wi[18];
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
-            cr[e] *= sf;
-            ci[e] *= sf;
-            cr[9 + e] *= sb;
-            ci[9 + e] *= sb;
+            if constexpr (P == P32) {
+                wr[2 * e] = w.v[e].x;
+                wi[2 * e] = w.v[e].y;
+                wr[2 * e + 1] = w.v[e].z;
+                wi[2 * e + 1] = w.v[e].w;
+            } else {
+                wr[2 * e] = h2f_lo(w.v[e].x) * w.sc;
+                wi[2 * e] = h2f_hi(w.v[e].x) * w.sc;
+                wr[2 * e + 1] = h2f_lo(w.v[e].y) * w.sc;
+                wi[2 * e + 1] = h2f_hi(w.v[e].y) * w.sc;
+            }
         }
 #pragma unroll
         for (int e = 0; e < 18; ++e) {
-            lr[e] = r12 ? cr[e] : fr[e];
-            li[e] = r12 ? ci[e] : fi[e];
+            fr[e] = wr[e];
+            fi[e] = wi[e];
         }
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            cr[e] = wr[e];
+            ci[e] = wi[e];
+            cr[9 + e] = wr[6 + e];
+            ci[9 + e] = wi[6 + e];
+        }
+    }
+    third_row(cr, ci, 0);
+    third_row(cr, ci, 9);
+    const T sf = (T)eta, sb = -(T)eta;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        cr[e] *= sf;
+        ci[e] *= sf;
+        cr[9 + e] *= sb;
+        ci[9 + e] *= sb;
+    }
+#pragma unroll
+    for (int e = 0; e < 18; ++e) {
+        lr[e] = r12 ? cr[e] : fr[e];
+        li[e] = r12 ? ci[e] : fi[e];
     }
 }
 
@@ -607,11 +612,29 @@ __device__ __forceinline__ void block_chunk_partials(double (&v)[N], const Reduc
 // wavefront: lane l accumulates partials l, l + 64, l + 128, ... into four
 // interleaved running sums, combined as (s0 + s1) + (s2 + s3) and then
 // across the wave by a butterfly. Every lane returns the same value (each
-// exchange adds the same two numbers on both partners).
+// exchange adds the same two numbers on both partners). U only sets how
+// many rounds of four loads a lane has in flight before it adds them (the
+// sum is bound by memory latency when the partials are many); the order of
+// the additions, and so the result, is the same for every U.
+template <int U = 4>
 __device__ __forceinline__ double wave_sum_partials(const double* pp, int nparts) {
     const int lane = threadIdx.x & 63;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int i = lane;
+    if constexpr (U > 4) {
+        for (; i + (256 * U - 64) < nparts; i += 256 * U) {
+            double v[4 * U];
+#pragma unroll
+            for (int u = 0; u < 4 * U; ++u) v[u] = pp[i + 64 * u];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                s0 += v[4 * u];
+                s1 += v[4 * u + 1];
+                s2 += v[4 * u + 2];
+                s3 += v[4 * u + 3];
+            }
+        }
+    }
 #pragma unroll 4
     for (; i + 192 < nparts; i += 256) {
         s0 += pp[i];
@@ -638,6 +661,27 @@ __device__ __forceinline__ void load_state(const RhsState* st, RhsState* ls) {
     unsigned long long* dst = (unsigned long long*)ls;
     for (int i = threadIdx.x; i < N * kStateWords; i += blockDim.x) dst[i] = src[i];
     __syncthreads();
+}
+
+// Finalise reduction R as a one-block kernel of 64 N threads (the result of
+// finalize_block, bit for bit): wave r sums RHS r's partials with many
+// loads in flight, before the states are read, so the two latencies
+// overlap; the sums of RHS not flagged in run_mask are discarded.
+template <int N>
+__device__ __forceinline__ void finalize_wide(const Reduce& R, unsigned run_mask, RhsState* ls) {
+    constexpr int U = N <= 8 ? 16 : 8;  // loads in flight within the register budget
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double sum = wave_sum_partials<U>(R.partials + (size_t)wave * R.nparts, R.nparts);
+    if (!R.st) {
+        if (lane == 0 && R.out) R.out[wave] = sum;
+        return;
+    }
+    load_state<N>(R.st, ls);
+    if (lane == 0 && (ls[wave].flags & run_mask)) finalize_one(R.kind, ls + wave, sum, R.out ? R.out + wave : nullptr);
+    __syncthreads();
+    unsigned long long* dst = (unsigned long long*)(R.st_out ? R.st_out : R.st);
+    const unsigned long long* src = (const unsigned long long*)ls;
+    for (int i = threadIdx.x; i < N * kStateWords; i += blockDim.x) dst[i] = src[i];
 }
 
 // Finalise reduction R for the first N right-hand sides, block-wide: the

@@ -47,10 +47,11 @@ struct HopArgs {
     double m2[16];         // mass^2 per right-hand side (used when st is null)
     RhsState* st;          // null: every RHS is processed
     unsigned run_mask;     // process RHS r iff st[r].flags & run_mask
+    int gate;              // P64, one RHS: read the flags before any operand, leave if unflagged
     int p_out;
     int swizzle;           // block order (logical_block)
     uint32_t tile_bps;     // blocks per t-slice for the t-grouped orders (0: off)
-    int r12;               // links in 12-parameter form (P64 / P32)
+    int r12;               // links in 12-parameter form
     int npairs;            // hop pairs per site: 4 (Eq.5) or 8 (improved operator)
     Geom g;
     Reduce red;            // XPAY_DOT / RESID: where the chunk partials go
@@ -114,7 +115,7 @@ hipError_t launch_vec(int prec, int N, int op, const VecArgs& a, const Issue& is
 hipError_t launch_finalize(int N, const Reduce& R, unsigned run_mask, const Issue& is);
 
 // Layout conversion kernels (canonical complex128 <-> internal storage).
-// r12: 12-parameter layout (P64 / P32 only; P16S is always full).
+// r12: 12-parameter layout.
 // Ulong_dev: long links of the improved operator (U_dev then holds the fat
 // links), or null; never together with r12.
 hipError_t launch_gauge_pack(int prec, const void* U_dev, const void* Ulong_dev, void* G,

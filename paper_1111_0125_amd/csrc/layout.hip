@@ -120,11 +120,13 @@ __global__ __launch_bounds__(kBlock) void k_gauge_pack(const d2v* __restrict__ U
     }
 }
 
-// 12-parameter packing (P64 / P32): the first two rows of U_mu(x) and of
+// 12-parameter packing: the first two rows of U_mu(x) and of
 // U_mu(x - mu)^dagger per hop pair, without phases (layout in common.h).
+// P16S divides by the site scale of the full packing (the largest |Re| or
+// |Im| over all 144 reals of the site's eight links, third rows included).
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_gauge_pack12(const d2v* __restrict__ U, void* G, Geom g,
-                                                         int p_out) {
+__global__ __launch_bounds__(kBlock) void k_gauge_pack12(const d2v* __restrict__ U, void* G,
+                                                         float* gscale, Geom g, int p_out) {
     const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= g.Vh) return;
     int c[4];
@@ -134,6 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_gauge_pack12(const d2v* __restrict__
         return (size_t)q[0] + (size_t)Lx * ((size_t)q[1] + (size_t)Ly * ((size_t)q[2] + (size_t)Lz * q[3]));
     };
     double lr[48], li[48];
+    float sc = 0.f;
     const size_t lex = lex_of(c);
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
@@ -141,6 +144,14 @@ __global__ __launch_bounds__(kBlock) void k_gauge_pack12(const d2v* __restrict__
         b[mu] = (b[mu] == 0) ? g.L[mu] - 1 : b[mu] - 1;
         const d2v* uf = U + (lex * 4 + mu) * 9;
         const d2v* ub = U + (lex_of(b) * 4 + mu) * 9;
+        if constexpr (P == P16S) {
+#pragma unroll
+            for (int e = 0; e < 9; ++e) {
+                const d2v f = uf[e], v = ub[e];
+                sc = fmaxf(sc, fmaxf(fabsf((float)f.x), fabsf((float)f.y)));
+                sc = fmaxf(sc, fmaxf(fabsf((float)v.x), fabsf((float)v.y)));
+            }
+        }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -164,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_gauge_pack12(const d2v* __restrict__
             v.y = li[e];
             o[(size_t)e * Vh + s] = v;
         }
-    } else {
+    } else if constexpr (P == P32) {
         f4v* o = (f4v*)G;
 #pragma unroll
         for (int w = 0; w < 24; ++w) {
@@ -173,6 +184,20 @@ __global__ __launch_bounds__(kBlock) void k_gauge_pack12(const d2v* __restrict__
             v.y = (float)li[2 * w];
             v.z = (float)lr[2 * w + 1];
             v.w = (float)li[2 * w + 1];
+            o[(size_t)w * Vh + s] = v;
+        }
+    } else {
+        gscale[s] = sc;
+        u2v* o = (u2v*)G;
+#pragma unroll
+        for (int w = 0; w < 24; ++w) {
+            u2v v;
+            if (sc == 0.f) {
+                v.x = v.y = 0u;
+            } else {
+                v.x = f2h_pair(__fdiv_rn((float)lr[2 * w], sc), __fdiv_rn((float)li[2 * w], sc));
+                v.y = f2h_pair(__fdiv_rn((float)lr[2 * w + 1], sc), __fdiv_rn((float)li[2 * w + 1], sc));
+            }
             o[(size_t)w * Vh + s] = v;
         }
     }
@@ -237,13 +262,15 @@ hipError_t launch_su3_check(const void* U_dev, uint64_t nlinks, double tol, int*
 hipError_t launch_gauge_pack(int prec, const void* U_dev, const void* Ulong_dev, void* G,
                              float* gscale, const Geom& g, int p_out, bool r12, hipStream_t st) {
     if (r12 && Ulong_dev) return hipErrorInvalidValue;
-    if (r12 && prec != P16S) {
+    if (r12) {
         const dim3 grid((g.Vh + kBlock - 1) / kBlock), block(kBlock);
         const d2v* U = (const d2v*)U_dev;
-        if (prec == P64)
-            hipLaunchKernelGGL((k_gauge_pack12<P64>), grid, block, 0, st, U, G, g, p_out);
-        else
-            hipLaunchKernelGGL((k_gauge_pack12<P32>), grid, block, 0, st, U, G, g, p_out);
+        switch (prec) {
+            case P64: hipLaunchKernelGGL((k_gauge_pack12<P64>), grid, block, 0, st, U, G, gscale, g, p_out); break;
+            case P32: hipLaunchKernelGGL((k_gauge_pack12<P32>), grid, block, 0, st, U, G, gscale, g, p_out); break;
+            case P16S: hipLaunchKernelGGL((k_gauge_pack12<P16S>), grid, block, 0, st, U, G, gscale, g, p_out); break;
+            default: return hipErrorInvalidValue;
+        }
         return hipGetLastError();
     }
     const dim3 grid((g.Vh + kBlock - 1) / kBlock), block(kBlock);

@@ -784,7 +784,7 @@ static int tiny_solve(stag_engine* e, int n, const double* mass, const stag_cg_p
         a.gscale[q] = P == P16S ? g->gscale[q] : nullptr;
         a.G64[q] = g->G[P64][q];
     }
-    a.r12 = g->r12 && P != P16S;
+    a.r12 = g->r12;
     a.r12_64 = g->r12;
     a.g = g->g;
     a.b64 = e->b64;

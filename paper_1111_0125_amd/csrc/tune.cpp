@@ -39,7 +39,7 @@ static std::string tune_cache_key(int device, const stag_gauge* g, int prec, int
     }
     char buf[160];
     snprintf(buf, sizeof buf, "%s %d %d %u %d %d", arch.c_str(), g->npairs,
-             g->r12 && prec != P16S ? 1 : 0, g->g.Vh, prec, N);
+             g->r12 ? 1 : 0, g->g.Vh, prec, N);
     return buf;
 }
 

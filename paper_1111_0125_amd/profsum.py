@@ -283,7 +283,7 @@ def cmd_iteration(a):
         h = hop_parts(name)
         if h:
             prec = PREC_NAME[h["prec"]]
-            r12p = links == "r12" and prec != "f16s"
+            r12p = links == "r12"
             n = h["N"]
             # blocks of 8 or more right-hand sides, and of several on lattices of
             # 131072 sites per parity or more, form the direction in a pass of

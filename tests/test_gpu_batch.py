@@ -22,7 +22,7 @@ def stag():
 
 @pytest.mark.parametrize("r12", [False, True])
 def test_c4_block_solve_12_rhs(stag, r12):
-    """With full links and with the 12-parameter f64 / f32 copies the
+    """With full links and with the 12-parameter copies the
     benchmark runs on; true residuals from the oracle's uncompressed A."""
     name = "c4_24x24x24x48"
     cfg = synth.CONFIGS[name]

@@ -33,9 +33,8 @@ def problem():
 @pytest.mark.parametrize("inner,r12", [("f16s", False), ("f32", False), ("f64", False),
                                        ("f16s", True), ("f32", True), ("f64", True)])
 def test_c3_solve_true_residual(stag, problem, inner, r12):
-    """With full links and with the 12-parameter f64 / f32 copies the
-    benchmark solves on (the fp16 copy is always full); the oracle's A uses
-    the uncompressed links."""
+    """With full links and with the 12-parameter copies the benchmark
+    solves on; the oracle's A uses the uncompressed links."""
     cfg, U, b = problem
     L, m, tol = cfg["L"], cfg["mass"], cfg["tol"]
     with stag.Context(0) as ctx:

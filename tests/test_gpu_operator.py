@@ -159,12 +159,12 @@ def test_block_operator_matches_single(stag, ctx, nrhs):
 def test_apply_A_full_size(stag, ctx, name, r12):
     """A at the full benchmark lattices against the C oracle (which never
     compresses links), every precision, with the links stored in full and in
-    the 12-parameter form the benchmark runs on (f64 / f32 copies)."""
+    the 12-parameter form the benchmark runs on."""
     cfg = synth.CONFIGS[name]
     L = cfg["L"]
     log("full-size A", name, "r12" if r12 else "full")
     U = synth.config_links(name)
-    precs = ("f64", "f32") if r12 else ("f64", "f32", "f16s")
+    precs = ("f64", "f32", "f16s")
     g = ctx.gauge(L, U, precisions=precs, r12=r12)
     v = synth.gaussian_rhs(L, 1, cfg["rhs_seed"])
     ref = oracle_apply_A(U, v, L, cfg["mass"])

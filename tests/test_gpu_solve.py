@@ -303,7 +303,7 @@ def test_c2_time_to_1e8_fp64_and_mixed(stag, ctx, r12):
     """16^3 x 32, exp(i 0.3 H) links, m = 0.01: plain fp64 CG and fp32-inner
     CG with fp64 reliable updates both reach true residual 1e-8 (true residual
     checked by the C oracle, whose links are never compressed), with full
-    links and with the 12-parameter f64 / f32 copies the benchmark solves on.
+    links and with the 12-parameter copies the benchmark solves on.
     The fp64 and fp32-inner iteration counts agree with the oracle's Fig.1 CG
     and Sec.3.2 emulation on the same system."""
     name = "c2_16x16x16x32"
