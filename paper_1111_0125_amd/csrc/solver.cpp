@@ -175,10 +175,11 @@ void engine_release(stag_engine* e) {
 // is finalised by a one-block kernel and consumers read the state.
 constexpr size_t kFuseMaxPartials = 2048;
 
-// Blocks of several right-hand sides run the direction update as its own
-// pass from this many sites per parity on, and blocks of 8 on any lattice
-// (measured: at 16^3x32 with 8 RHS the hop stages gain 13 us for a ~7 us
-// pass; with 2 or 4 RHS the pass costs what it saves).
+// Kernels of any number of right-hand sides run the direction update as
+// its own pass from this many sites per parity on, and blocks of 8 on any
+// lattice (measured: at 16^3x32 with 8 RHS the hop stages gain 13 us for a
+// ~7 us pass, with 2 or 4 RHS the pass costs what it saves; at 32^3x64 with
+// one RHS an fp16+scale iteration takes 17 % less and an fp32 one 1 % less).
 constexpr uint32_t kXpayMinSites = 131072;
 constexpr int kXpayMinRhs = 8;
 
@@ -281,13 +282,16 @@ hipError_t vec(const Ctx& c, int prec, int op, std::initializer_list<std::pair<v
 
 constexpr int kKernelsPerIteration = 3;
 
-// Several right-hand sides on a large lattice: the direction update
-// d = q(r + beta d) as a pass of its own before stage 1, which then gathers
-// one field per neighbour and right-hand side instead of two (the gathers,
-// not the compulsory traffic, bound the block hop kernels there); stage 2
+// Large lattices, and blocks of 8 or more right-hand sides: the direction
+// update d = q(r + beta d) as a pass of its own before stage 1, which then
+// gathers one field per neighbour and right-hand side instead of two (the
+// gathers, not the compulsory traffic, bound the block hop kernels there)
+// and forms no direction (with fp16+scale storage every neighbour's d must
+// be re-encoded to the bits stage 2 stores: eight encodes per site, each
+// with six divisions, kept stage 1 far below its bandwidth bound); stage 2
 // reads d as stored. Four kernels per iteration, bitwise the same results.
 bool separate_xpay(const stag_engine* e, int nk) {
-    return nk >= kXpayMinRhs || (nk > 1 && e->Vh >= kXpayMinSites);
+    return nk >= kXpayMinRhs || e->Vh >= kXpayMinSites;
 }
 
 hipError_t enqueue_iterations_xpay(const Ctx& c, int K) {

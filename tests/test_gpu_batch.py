@@ -83,7 +83,9 @@ def test_block_orders_bitwise_identical(stag, nrhs):
 def test_block_solve_bitwise_across_block_orders(stag):
     """An 8-RHS mixed block solve (direction pass of its own, block hop
     stages, fp64 fix-ups) gives the same iterations and bits in every block
-    order, and each right-hand side meets the oracle's true residual."""
+    order, and the bits of a single-RHS solve on this small lattice (whose
+    stage 1 forms the direction at every neighbour); each right-hand side
+    meets the oracle's true residual."""
     L, m, tol, n = (8, 8, 8, 8), 0.05, 1e-9, 8
     U = synth.haar_links(L, 43)
     b = synth.gaussian_rhs(L, n, 44)
@@ -99,6 +101,12 @@ def test_block_solve_bitwise_across_block_orders(stag):
                                         stag.cg_params(tol=tol, inner="f32", small_lattice=False))
             assert rc == 0, st
             res.append(([s["iters"] for s in st], fx.store()))
+        f1 = ctx.field(g, 0, "f64", 1).load(b[3:4])
+        x1 = ctx.field(g, 0, "f64", 1)
+        rc1, st1 = stag.stag_cg_solve(ctx, g, [m], f1, x1,
+                                      stag.cg_params(tol=tol, inner="f32", small_lattice=False))
+        assert rc1 == 0 and st1[0]["iters"] == res[0][0][3]
+        assert np.array_equal(x1.store()[0], res[0][1][3])
     for it, x in res[1:]:
         assert it == res[0][0] and np.array_equal(x, res[0][1])
     Ax = oracle_apply_A(U, res[0][1], L, m)
