@@ -219,11 +219,12 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
             const int mu = j * B + k;  // hop pair index
             uint32_t nf, nb;
             T lr[18], li[18];
+            PairScale<T> ps;
             [[maybe_unused]] Raw<P> wfk, wbk;
             if constexpr (N == 1 && k < PB) {
                 nf = pnf[k];
                 nb = pnb[k];
-                finish_pair<P>(r12, eta_sign(mu & 3, x, y, z), pl[k], lr, li);
+                finish_pair<P>(r12, eta_sign(mu & 3, x, y, z), pl[k], lr, li, ps);
             } else {
                 pair_neighbours<NP>(a.g, s, x, y, z, t, mu, nf, nb);
                 if constexpr (N == 1) {
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                     load_raw<P>(a, (const char*)a.in, 0, nf, lazy_nb, wfk);
                     load_raw<P>(a, (const char*)a.in, 0, nb, lazy_nb, wbk);
                 }
-                load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, r12, eta_sign(mu & 3, x, y, z), lr, li);
+                load_pair<P, NT>(a.gauge, a.gscale, Vh, s, mu, r12, eta_sign(mu & 3, x, y, z), lr, li, ps);
             }
 #pragma unroll
             for (int r = 0; r < N; ++r) {
@@ -249,12 +250,12 @@ __global__ __launch_bounds__(kBlock) void k_hop(HopArgs a) {
                     load_raw<P>(a, in_r, r, nf, lazy_nb, wf);
                     load_raw<P>(a, in_r, r, nb, lazy_nb, wb);
                 }
-                T vr[3], vi[3], pr[3] = {T(0), T(0), T(0)}, pi[3] = {T(0), T(0), T(0)};
+                T vr[3], vi[3], pr[3], pi[3];
                 // stage 2 gathers t as stored
                 combine<P>(a, wf, r, nf, lazy_nb, be, EPI == EPI_PLAIN, vr, vi);
-                matvec_acc(lr, li, 0, vr, vi, pr, pi);
+                pair_start(lr, li, vr, vi, pr, pi);
                 combine<P>(a, wb, r, nb, lazy_nb, be, EPI == EPI_PLAIN, vr, vi);
-                matvec_acc(lr, li, 9, vr, vi, pr, pi);
+                pair_finish(lr, li, ps, vr, vi, pr, pi);
                 // binary-counter walk of the tree: the new pair sum is
                 // the right sibling of every pending sum at the levels
                 // where k has a 1 bit, and waits at the first 0 bit

@@ -225,14 +225,28 @@ __device__ __forceinline__ void load_pair_raw(const void* G, const float* gscale
     }
 }
 
-// The 18 complex entries of a pair from what load_pair_raw loaded: with r12
-// the third rows are rebuilt and the forward link is multiplied by eta, the
-// backward one by -eta (eta = eta_mu(x) = +-1); stored full links already
-// hold the phases. Both forms are formed and one is selected per entry.
+// Output factors of a hop pair (finish_pair): the pair sum is
+// p = S (F chi(x + h) + sigma B chi(x - h)) over the links F, B as
+// finish_pair leaves them, S = diag(s01, s01, s2) on the colour rows.
+// Stored full links hold the phases (sigma = +1, S = 1); with r12 the phase
+// eta goes to S and sigma = -1 (the backward link is -eta U^dagger). Scaling
+// by +-1 is exact, so p has the bits of multiplying the links themselves.
+// fp16 links are left divided by the site scale s and S carries it (s, and
+// s^2 on a row rebuilt from two divided rows): three multiplies per pair in
+// place of one per entry.
+template <typename T>
+struct PairScale {
+    T s01, s2, sigma;
+};
+
+// The 18 complex entries of a pair from what load_pair_raw loaded, with the
+// factors that complete them (PairScale): with r12 the third rows are
+// rebuilt. Both forms are formed and one is selected per entry.
 template <int P>
 __device__ __forceinline__ void finish_pair(int r12, int eta, const PairRaw<P>& w,
                                             typename Real<P>::T (&lr)[18],
-                                            typename Real<P>::T (&li)[18]) {
+                                            typename Real<P>::T (&li)[18],
+                                            PairScale<typename Real<P>::T>& ps) {
     using T = typename Real<P>::T;
     T fr[18], fi[18], cr[18], ci[18];  // full, compressed
     if constexpr (P == P64) {
@@ -249,8 +263,8 @@ __device__ __forceinline__ void finish_pair(int r12, int eta, const PairRaw<P>& 
             ci[9 + e] = w.v[6 + e].y;
         }
     } else {
-        // word e holds entries 2e and 2e + 1 (P32 as floats, P16S as
-        // fp16 pairs times the site scale)
+        // word e holds entries 2e and 2e + 1 (P32 as floats, P16S as fp16
+        // pairs, still divided by the site scale)
         T wr[18], wi[18];
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
@@ -260,10 +274,10 @@ __device__ __forceinline__ void finish_pair(int r12, int eta, const PairRaw<P>& 
                 wr[2 * e + 1] = w.v[e].z;
                 wi[2 * e + 1] = w.v[e].w;
             } else {
-                wr[2 * e] = h2f_lo(w.v[e].x) * w.sc;
-                wi[2 * e] = h2f_hi(w.v[e].x) * w.sc;
-                wr[2 * e + 1] = h2f_lo(w.v[e].y) * w.sc;
-                wi[2 * e + 1] = h2f_hi(w.v[e].y) * w.sc;
+                wr[2 * e] = h2f_lo(w.v[e].x);
+                wi[2 * e] = h2f_hi(w.v[e].x);
+                wr[2 * e + 1] = h2f_lo(w.v[e].y);
+                wi[2 * e + 1] = h2f_hi(w.v[e].y);
             }
         }
 #pragma unroll
@@ -281,19 +295,19 @@ __device__ __forceinline__ void finish_pair(int r12, int eta, const PairRaw<P>& 
     }
     third_row(cr, ci, 0);
     third_row(cr, ci, 9);
-    const T sf = (T)eta, sb = -(T)eta;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        cr[e] *= sf;
-        ci[e] *= sf;
-        cr[9 + e] *= sb;
-        ci[9 + e] *= sb;
-    }
 #pragma unroll
     for (int e = 0; e < 18; ++e) {
         lr[e] = r12 ? cr[e] : fr[e];
         li[e] = r12 ? ci[e] : fi[e];
     }
+    const T sg = r12 ? (T)eta : T(1);
+    if constexpr (P == P16S) {
+        ps.s01 = sg * w.sc;
+        ps.s2 = r12 ? sg * (w.sc * w.sc) : sg * w.sc;
+    } else {
+        ps.s01 = ps.s2 = sg;
+    }
+    ps.sigma = r12 ? T(-1) : T(1);
 }
 
 // Both steps at once: hop pair mu of output site s, ready to apply.
@@ -301,10 +315,11 @@ template <int P, bool NT>
 __device__ __forceinline__ void load_pair(const void* G, const float* gscale, uint32_t Vh,
                                           uint32_t s, int mu, int r12, int eta,
                                           typename Real<P>::T (&lr)[18],
-                                          typename Real<P>::T (&li)[18]) {
+                                          typename Real<P>::T (&li)[18],
+                                          PairScale<typename Real<P>::T>& ps) {
     PairRaw<P> w;
     load_pair_raw<P, NT>(G, gscale, Vh, s, mu, r12, w);
-    finish_pair<P>(r12, eta, w, lr, li);
+    finish_pair<P>(r12, eta, w, lr, li, ps);
 }
 
 // eta_mu(x) = (-1)^(x_0 + ... + x_{mu-1}) of the site with coordinates x, y, z.
@@ -328,6 +343,36 @@ __device__ __forceinline__ void matvec_acc(const T (&lr)[18], const T (&li)[18],
             ai[a] = fma(ur, vi[b], ai[a]);
             ai[a] = fma(ui, vr[b], ai[a]);
         }
+    }
+}
+
+// p = S (F vf + sigma B vb) for one pair (PairScale), in two steps so that
+// vb can be formed after vf has been used: pair_start(F vf), then
+// pair_finish(vb) adds sigma B vb and applies S.
+template <typename T>
+__device__ __forceinline__ void pair_start(const T (&lr)[18], const T (&li)[18], const T (&vfr)[3],
+                                           const T (&vfi)[3], T (&pr)[3], T (&pi)[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pr[c] = pi[c] = T(0);
+    matvec_acc(lr, li, 0, vfr, vfi, pr, pi);
+}
+
+template <typename T>
+__device__ __forceinline__ void pair_finish(const T (&lr)[18], const T (&li)[18],
+                                            const PairScale<T>& ps, const T (&vbr)[3],
+                                            const T (&vbi)[3], T (&pr)[3], T (&pi)[3]) {
+    T br[3], bi[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        br[c] = ps.sigma * vbr[c];
+        bi[c] = ps.sigma * vbi[c];
+    }
+    matvec_acc(lr, li, 9, br, bi, pr, pi);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const T f = c < 2 ? ps.s01 : ps.s2;
+        pr[c] *= f;
+        pi[c] *= f;
     }
 }
 

@@ -55,12 +55,13 @@ __device__ __forceinline__ void tiny_hop(const void* G, const float* gscale, con
         uint32_t nf, nb;
         neighbours(g, s, x, y, z, t, j, nf, nb);
         T lr[18], li[18];
-        load_pair<P, false>(G, gscale, g.Vh, s, j, r12, eta_sign(j, x, y, z), lr, li);
+        PairScale<T> ps;
+        load_pair<P, false>(G, gscale, g.Vh, s, j, r12, eta_sign(j, x, y, z), lr, li, ps);
         T vr[3], vi[3];
         load_site<P>(in, g.Vh, nf, vr, vi);
-        matvec_acc(lr, li, 0, vr, vi, ar, ai);
+        pair_start(lr, li, vr, vi, ar, ai);
         load_site<P>(in, g.Vh, nb, vr, vi);
-        matvec_acc(lr, li, 9, vr, vi, ar, ai);
+        pair_finish(lr, li, ps, vr, vi, ar, ai);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c)
