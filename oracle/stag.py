@@ -430,7 +430,7 @@ def refinement_cg(U, L, m, b, tol, prec="f32", eps_in=0.1, max_iter=None, Ulong=
 
 def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
              max_iter=None, max_stall=20, carry_direction=True, update="both", Ulong=None,
-             slow_ratio=None, r12=False):
+             slow_ratio=None, r12=False, cg_budget=None):
     """Corrected mixed-precision CG of Sec.3.2, emulated on the CPU.
 
     Inner iterations run on stored low-precision vectors (fp32 arithmetic,
@@ -470,6 +470,19 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
     system, so a cycle that does not even halve it means the low precision
     cannot refine it (the setting a solver that can hand over to a higher
     inner precision uses).
+    ``cg_budget``: also end with status "stall" at the first regular update
+    after more iterations than ``cg_budget`` times what the CG convergence
+    bound allows for the true-residual reduction reached so far: with
+    sqrt(kappa) estimated as sk = sqrt(lam / m^2) and R = |r_true| / |b|, the
+    allowance is sk/2 (ln(2/R) + ln(sk)) (the A-norm error bound
+    2 ((sk-1)/(sk+1))^k, with the residual up to sk times further off). m^2
+    bounds the smallest eigenvalue from below; lam is the largest Lanczos
+    diagonal 1/alpha_k + beta_{k-1}/alpha_{k-1} of the first cycle (a
+    Rayleigh quotient of the residual, so at most the largest eigenvalue; in
+    later cycles of a low-precision recurrence it loses that meaning and
+    grows far past the operator's norm, so it is taken from the first cycle
+    only). The inner precision then converges much slower than CG can on
+    this system, even if every cycle still contracts the true residual.
     Returns (x, stats).
     """
     if update not in ("both", "reliable", "fold_only"):
@@ -501,12 +514,18 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
     stall_count = 0
     best_true = rr
     true_rr = rr
+    true_rr0 = rr
+    lam = 0.0           # largest Lanczos diagonal seen (cg_budget)
+    alpha = 0.0
+    beta_d = 0.0        # the beta that formed the current direction (0: d = r)
     while stats["iters"] < max_iter:
         Ad = Alow(d)
         pAp = vdot(d, Ad).real
         if not (pAp > 0.0 and math.isfinite(pAp)):
             stats["status"] = "breakdown"
             break
+        if cg_budget and stats["updates"] == 0:
+            lam = max(lam, pAp / rr + (beta_d / alpha if beta_d > 0.0 and alpha > 0.0 else 0.0))
         alpha = rr / pAp
         a32 = np.float32(alpha)
         y = (y + a32 * d).astype(np.complex64)
@@ -538,6 +557,7 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
             if stall:
                 stats["restarts"] += 1
                 d = rs.copy()
+                beta_d = 0.0
                 continue
         elif upd or stall:
             if update == "both":
@@ -554,6 +574,12 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
             if slow_ratio and not stall and rr > slow_ratio * slow_ratio * prev_true:
                 stats["status"] = "stall"
                 break
+            if cg_budget and not stall and lam > 0.0 and rr < true_rr0:
+                sk = math.sqrt(lam / (m * m))
+                allow = 0.5 * sk * (math.log(2.0 / math.sqrt(rr / true_rr0)) + math.log(sk))
+                if stats["iters"] > cg_budget * allow:
+                    stats["status"] = "stall"
+                    break
             rs = q(r64)
             rmax = rmin = math.sqrt(rr)
             since = 0
@@ -568,12 +594,15 @@ def mixed_cg(U, L, m, b, tol, prec="f32", delta=0.1, stall_iters=None,
                         break
                 best_true = min(best_true, rr)
                 d = rs.copy()
+                beta_d = 0.0
                 continue
             best_true = min(best_true, rr)
             if not carry_direction:
                 d = rs.copy()
+                beta_d = 0.0
                 continue
         beta = rr / rr_old
+        beta_d = beta
         d = q((rs + np.float32(beta) * d).astype(np.complex64))
     if update == "reliable":
         # the solution is x + y; x is never updated by this variant

@@ -396,6 +396,28 @@ def test_slow_refinement_cycle_ends_the_fp16_pass():
     assert a == c and a["status"] == "ok" and np.array_equal(x1, x2)
 
 
+def test_cg_budget_ends_an_fp16_pass_that_lags_cg():
+    """The iteration budget of the CG convergence bound (6^4 Haar links,
+    1e-8). fp32 refinement keeps within the bound itself (the bound holds
+    for CG, and the budget's formula would exceed it with a factor or a term
+    dropped). fp16 storage at m = 0.05 keeps within twice it, so the budget
+    changes nothing. At m = 0.02 every fp16 cycle still contracts the true
+    residual tenfold, but at 3x the iterations CG needs (7 131 iterations in
+    all against fp32's 2 419), so the budget ends the pass."""
+    L = (6, 6, 6, 6)
+    U = synth.haar_links(L, 15)
+    b = synth.gaussian_rhs(L, 1, 1001)[0]
+    _, f32 = stag.mixed_cg(U, L, 0.02, b, 1e-8, prec="f32", r12=True, cg_budget=1.2)
+    assert f32["status"] == "ok"
+    _, lag = stag.mixed_cg(U, L, 0.02, b, 1e-8, prec="f16s", r12=True, cg_budget=2.0)
+    assert lag["status"] == "stall" and lag["restarts"] == 0
+    assert 2 <= lag["updates"] <= 6 and lag["iters"] < 0.6 * 7131
+    assert lag["true_rel_res"] < 1e-2
+    x1, a = stag.mixed_cg(U, L, 0.05, b, 1e-8, prec="f16s", r12=True, cg_budget=2.0)
+    x2, c = stag.mixed_cg(U, L, 0.05, b, 1e-8, prec="f16s", r12=True)
+    assert a == c and a["status"] == "ok" and np.array_equal(x1, x2)
+
+
 def test_paper_cost_model_golden():
     g = json.load(open(os.path.join(GOLDEN, "paper_cost_model.json")))
     reals = 8 * 18 + 8 * 6 + 6
