@@ -228,9 +228,12 @@ typedef struct stag_cg_params {
                           iteration cannot refine the system, continue from the current x
                           with F32 inner iterations (no stall restarts); default 1. The
                           fp16 pass ends (ESTALL) after 3 stall updates without progress,
-                          or at the first refinement cycle that reduces the true residual
+                          at the first refinement cycle that reduces the true residual
                           norm by less than half (a working inner solve reduces it by
-                          about delta) */
+                          about delta), or at the first update after more than twice the
+                          iterations the CG convergence bound allows for the reduction
+                          reached (sqrt(kappa) from the first cycle's largest Lanczos
+                          diagonal and mass^2) */
     int mixed_variant; /* mixed: what an update does with the search direction.
                           STAG_MIXED_CARRY (default): keep it, d = r + beta d with
                           beta = |r_true|^2 / |r_prev|^2 (Sec.3.2, Eq.6); the inner cycle

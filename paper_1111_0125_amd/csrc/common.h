@@ -210,6 +210,12 @@ struct RhsState {
                         // factor since the previous update ends the pass (F_ESTALL): the
                         // inner precision cannot refine this system (fp16 storage that
                         // can hand over to fp32); 0: off
+    double cg_budget;   // > 0: a non-stall update after more than this many times the
+                        // iterations the CG convergence bound allows for the true
+                        // residual reduction reached ends the pass (F_ESTALL); 0: off
+    double lam;         // largest Lanczos diagonal 1/alpha + beta/alpha_prev of the
+                        // pass's first cycle (a lower bound of the largest eigenvalue)
+    double rr_true0;    // true |r|^2 at the start of the pass
     int since;        // iterations since the last new residual minimum
     int stall_iters;
     int stall_count;

@@ -425,6 +425,11 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
             if (!(sum > 0.0) || !isfinite(sum)) {
                 s.flags = F_BREAKDOWN;
             } else {
+                // the Lanczos diagonal of this step, a Rayleigh quotient of the
+                // residual; taken from the first cycle only (later cycles of a
+                // low-precision recurrence lose that meaning)
+                if (s.cg_budget > 0.0 && s.updates == 0)
+                    s.lam = fmax(s.lam, sum / s.rr + (s.beta > 0.0 && s.alpha > 0.0 ? s.beta / s.alpha : 0.0));
                 s.alpha = s.rr / sum;
             }
             break;
@@ -473,7 +478,7 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
             const unsigned x0 = s.flags & F_X0;
             s.bb = sum;
             s.rr_stop = s.tol2 * sum;
-            s.rr = s.rr_old = s.rr_true = s.best_true = sum;
+            s.rr = s.rr_old = s.rr_true = s.best_true = s.rr_true0 = sum;
             s.rmax = s.rmin = s.rstart = sqrt(sum);
             s.since = 0;
             s.beta = 0.0;  // first direction d = r
@@ -488,7 +493,7 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
         }
         case FIN_X0:
             // r = b - A x0 replaces r = b
-            s.rr = s.rr_old = s.rr_true = s.best_true = sum;
+            s.rr = s.rr_old = s.rr_true = s.best_true = s.rr_true0 = sum;
             s.rmax = s.rmin = s.rstart = sqrt(sum);
             if (!isfinite(sum)) {
                 s.flags = F_BADINPUT;
@@ -554,6 +559,20 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
                 s.rr = rt;
                 s.flags = F_ESTALL;
                 break;
+            }
+            // a pass that needs more than cg_budget times the iterations the
+            // CG bound allows for the reduction reached so far (sqrt(kappa) from
+            // lam and m^2 <= lambda_min; error bound 2 ((sk-1)/(sk+1))^k, the
+            // residual up to sk further off) converges much slower than CG can
+            // on this system: end it too
+            if (!stall && s.cg_budget > 0.0 && s.lam > 0.0 && rt < s.rr_true0) {
+                const double sk = sqrt(s.lam / s.m2);
+                const double allow = 0.5 * sk * (log(2.0 / sqrt(rt / s.rr_true0)) + log(sk));
+                if ((double)s.iters > s.cg_budget * allow) {
+                    s.rr = rt;
+                    s.flags = F_ESTALL;
+                    break;
+                }
             }
             // Eq.6: the next direction is r + beta d with beta = |r_true|^2 / |r_prev|^2;
             // a stall, and every update of the Fig.2 variant, restarts it from r

@@ -613,8 +613,10 @@ static void start_state(const stag_engine* e, double mass, const stag_cg_params&
     s.flags = F_NEW | (x0 ? F_X0 : 0u);
     s.variant = p.mixed_variant;
     // an fp16-storage pass with somewhere to go hands over as soon as a
-    // refinement cycle fails to halve the true residual
+    // refinement cycle fails to halve the true residual, or the pass falls
+    // far behind the iterations CG needs on the system
     s.slow_ratio = escalating && e->prec == P16S ? kSlowCycleRatio : 0.0;
+    s.cg_budget = escalating && e->prec == P16S ? kCgBudget : 0.0;
 }
 
 int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots) {

@@ -359,6 +359,33 @@ def test_f16s_hands_over_at_first_slow_cycle(stag, ctx):
     assert st[0]["iters"] <= st32[0]["iters"] + 1.25 * est["iters"] + 50
 
 
+def test_f16s_hands_over_when_far_behind_cg(stag, ctx):
+    """6^4 Haar, m = 0.02, 1e-8: every fp16 refinement cycle still contracts
+    the true residual tenfold, but at about 3x the iterations CG needs (the
+    oracle's emulation: 7 131 iterations against fp32's 2 419; its budget ends
+    the fp16 pass after about 3 200). The solve hands over to fp32 once it is
+    twice behind the CG bound and reaches the tolerance (checked with the
+    oracle's fp64 A) in far fewer iterations than fp16 alone; at m = 0.05,
+    where fp16 keeps within the bound, the whole solve stays in fp16."""
+    L, tol = (6, 6, 6, 6), 1e-8
+    U = synth.haar_links(L, 15)
+    b = synth.gaussian_rhs(L, 1, 1001)
+    precs = ("f64", "f32", "f16s")
+    rc, st, x = solve(stag, ctx, L, U, b, [0.02], tol, inner="f16s", precisions=precs)
+    log("f16s with hand-over", rc, st[0])
+    assert rc == 0 and st[0]["inner_final"] == stag.PREC["f32"]
+    assert true_res(U, L, [0.02], b, x)[0] <= tol
+    rc16, st16, _ = solve(stag, ctx, L, U, b, [0.02], tol, inner="f16s", precisions=precs,
+                          escalate=False)
+    log("f16s alone", rc16, st16[0])
+    assert rc16 == 0 and st16[0]["inner_final"] == stag.PREC["f16s"]
+    assert st16[0]["iters"] > 1.3 * st[0]["iters"]
+    rc, st, x = solve(stag, ctx, L, U, b, [0.05], tol, inner="f16s", precisions=precs)
+    log("f16s at m = 0.05", rc, st[0])
+    assert rc == 0 and st[0]["inner_final"] == stag.PREC["f16s"]
+    assert true_res(U, L, [0.05], b, x)[0] <= tol
+
+
 def test_timing_mode_counts_launches_and_keeps_results(stag, ctx):
     """With kernel timing on, a solve runs eagerly with events at each
     kernel's start and end: the same iterations and bits as the graph solve,
