@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_vec(VecArgs a) {
         }
     }
     if constexpr (OP == OP_INIT_B || OP == OP_UPD_CG || OP == OP_UPD_MIXED) {
-        block_chunk_partials<N, 1>(dv, a.red, blk);
+        block_partials<N>(dv, a.red, blk);
     }
 }
 

@@ -624,9 +624,10 @@ __device__ __forceinline__ void finalize_one(int kind, RhsState* sp, double sum,
 
 // Reduction partials are taken over fixed chunks of 64 consecutive sites,
 // whatever the launch shape, and each chunk is summed by the same butterfly
-// over the site index; the consumer of a reduction then sums the chunk
-// partials of each right-hand side with one wavefront in a fixed order
-// (wave_sum_partials). The result is therefore independent of how many
+// over the site index (the vector kernels, which have one launch shape, add
+// a block's four chunk sums into one partial: block_partials); the consumer
+// of a reduction then sums the partials of each right-hand side with one
+// wavefront in a fixed order (wave_sum_partials). The result is therefore independent of how many
 // lanes serve a site, of how many right-hand sides share the kernel and of
 // which kernel forms the sum. No block waits for another and no atomics are
 // used: on this chip cross-block atomics serialise (tens of ns per block),
@@ -669,6 +670,30 @@ __device__ __forceinline__ void block_chunk_partials(double (&v)[N], const Reduc
                 if (lane == 0 && ch < (uint32_t)R.nparts) R.partials[(size_t)r * R.nparts + ch] = x;
             }
         }
+    }
+}
+
+// One thread per site, kBlock sites per block (the vector kernels): the
+// partial of each right-hand side is the block's, its four 64-site chunk
+// sums (the butterfly of block_chunk_partials) added as (c0 + c1) + (c2 + c3).
+// A quarter of the chunk count to sum for the reduction's consumers, and
+// still the same whatever the launch (the vector kernels have one shape).
+template <int N>
+__device__ __forceinline__ void block_partials(double (&v)[N], const Reduce& R, uint32_t blk) {
+    static_assert(kBlock == 4 * kChunk, "a block is four chunks");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ double sw[N][4];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        double x = v[r];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) sw[r][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < N && blk < (uint32_t)R.nparts) {
+        const int r = threadIdx.x;
+        R.partials[(size_t)r * R.nparts + blk] = (sw[r][0] + sw[r][1]) + (sw[r][2] + sw[r][3]);
     }
 }
 

@@ -226,6 +226,14 @@ Reduce make_red(stag_engine* e, int kind, double* partials = nullptr) {
     return r;
 }
 
+// A reduction produced by a vector kernel: one partial per block of kBlock
+// sites (block_partials) instead of one per 64-site chunk.
+Reduce make_red_vec(stag_engine* e, int kind, double* partials = nullptr) {
+    Reduce r = make_red(e, kind, partials);
+    r.nparts = (int)vec_blocks(e->Vh);
+    return r;
+}
+
 // Optional pieces of a kernel launch inside the solver.
 struct Opt {
     RhsState* st = nullptr;          // state read (null: e->st)
@@ -271,7 +279,7 @@ hipError_t vec(const Ctx& c, int prec, int op, std::initializer_list<std::pair<v
     a.st = o.st ? o.st : e->st;
     a.run_mask = run;
     a.swizzle = e->tune_lo.swizzle;
-    a.red = make_red(e, kind, o.partials);
+    a.red = make_red_vec(e, kind, o.partials);
     if (o.fin) a.fin = *o.fin;
     const int kk = op == OP_UPD_CG || op == OP_UPD_MIXED ? KK_UPDATE : KK_OTHER;
     hipError_t err = timed_launch(c, kk, [&]() { return launch_vec(prec, c.nk, op, a, c.is); });
@@ -305,7 +313,7 @@ hipError_t enqueue_iterations_xpay(const Ctx& c, int K) {
     void* r = mixed ? e->rs : e->r64;
     const size_t rs = mixed ? e->rsP : e->rs64;
     const bool fuse = fuse_finalize(e, c.nk);
-    Reduce pend_r = make_red(e, kind_r, e->partials1);
+    Reduce pend_r = make_red_vec(e, kind_r, e->partials1);
     pend_r.st = e->st1;
     pend_r.st_out = e->st;
     Reduce pend_a = make_red(e, FIN_ALPHA, e->partials);
@@ -384,7 +392,7 @@ hipError_t enqueue_iterations(const Ctx& c, int K) {
     void* r = mixed ? e->rs : e->r64;
     const bool fuse = fuse_finalize(e, c.nk);
     if (separate_xpay(e, c.nk)) return enqueue_iterations_xpay(c, K);
-    Reduce pend_r = make_red(e, kind_r, e->partials1);
+    Reduce pend_r = make_red_vec(e, kind_r, e->partials1);
     pend_r.st = e->st1;
     pend_r.st_out = e->st;
     Reduce pend_a = make_red(e, FIN_ALPHA, e->partials);
@@ -953,7 +961,7 @@ int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps,
     }
     const bool mixed = prec != P64;
     const bool fuse = fuse_finalize(e, N);
-    Reduce pend_r = make_red(e, FIN_STORE, e->partials1);
+    Reduce pend_r = make_red_vec(e, FIN_STORE, e->partials1);
     pend_r.st = e->st1;
     pend_r.st_out = e->st;
     pend_r.out = sink;
@@ -1001,7 +1009,7 @@ int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps,
         a.st = e->st;
         a.run_mask = F_ACTIVE;
         a.swizzle = t.swizzle;
-        a.red = make_red(e, FIN_STORE, e->partials1);
+        a.red = make_red_vec(e, FIN_STORE, e->partials1);
         if (fuse) a.fin = pend_a;
         return launch_vec(prec, N, mixed ? OP_UPD_MIXED : OP_UPD_CG, a, is);
     };
