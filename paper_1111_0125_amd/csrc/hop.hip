@@ -1,6 +1,8 @@
-// Hop kernel: the staggered Dirac operator of Eq.5 (with the phases of Sec.2
-// folded into the links) applied from one parity to the other, with optional
-// second-stage epilogues that complete A = m^2 - D_eo D_oe (Eq.3).
+// Hop kernel: the staggered Dirac operator of Eq.5 applied from one parity
+// to the other, with optional second-stage epilogues that complete
+// A = m^2 - D_eo D_oe (Eq.3). The phases of Sec.2 are folded into stored full
+// links; with 12-parameter links they multiply each hop pair's outputs (as
+// does the fp16 site scale: PairScale).
 //
 // The operator is a sum over NP hop pairs, each a forward and a backward hop
 // whose two 3x3 links are stored contiguously per site: NP = 4 for Eq.5
