@@ -22,16 +22,17 @@ def stag():
     return s
 
 
+@pytest.mark.parametrize("r12", [False, True])
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
-def test_noalloc_equals_apply_A_twice(stag, prec):
+def test_noalloc_equals_apply_A_twice(stag, prec, r12):
     # first call: 16^3 x 8 with 3 right-hand sides (kernels of 2 and 1),
     # second: a smaller 8^3 x 4 lattice with 1 right-hand side
     cases = [((16, 16, 16, 8), 3, [0.1, 0.05, 0.3], 7), ((8, 8, 8, 4), 1, [0.2], 9)]
     with stag.Context(0) as ctx:
         for L, n, masses, seed in cases:
-            log("noalloc", prec, L, n)
+            log("noalloc", prec, "r12" if r12 else "full", L, n)
             U = links(L, "haar", seed)
-            g = ctx.gauge(L, U, precisions=(prec,))
+            g = ctx.gauge(L, U, precisions=(prec,), r12=r12)
             v = synth.gaussian_rhs(L, n, seed + 1)
             fi = ctx.field(g, 0, prec, n).load(v)
             fa = ctx.field(g, 0, prec, n)
