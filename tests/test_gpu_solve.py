@@ -184,6 +184,29 @@ def test_batched_equals_single(stag, ctx):
             assert np.array_equal(x1[0], xb[r]), (inner, r, rel_norm(x1[0], xb[r]))
 
 
+def test_largest_block_and_one_more_refused(stag, ctx):
+    """The largest block, 16 right-hand sides (kernel groups of 8 and 8, the
+    direction as a pass of its own), ragged masses: every one meets the
+    oracle's true residual and the first and last equal their single solves
+    bit for bit; a 17th right-hand side is refused on the host."""
+    L, tol = (8, 8, 8, 8), 1e-8
+    U = links(L, "haar", 71)
+    n = 16
+    b = synth.gaussian_rhs(L, n, 72)
+    masses = [0.05 + 0.01 * (r % 5) for r in range(n)]
+    rc, st, xb = solve(stag, ctx, L, U, b, masses, tol, inner="f32")
+    log("16 RHS", rc, [s_["iters"] for s_ in st])
+    assert rc == 0 and max(true_res(U, L, masses, b, xb)) <= tol
+    for r in (0, n - 1):
+        rc1, st1, x1 = solve(stag, ctx, L, U, b[r:r + 1], [masses[r]], tol, inner="f32")
+        assert rc1 == 0 and st1[0]["iters"] == st[r]["iters"]
+        assert np.array_equal(x1[0], xb[r])
+    g = ctx.gauge(L, U, precisions=("f64",))
+    with pytest.raises(stag.StagError):
+        ctx.field(g, 0, "f64", n + 1)
+    g.destroy()
+
+
 def test_graph_and_eager_bitwise(stag, ctx):
     L, m, tol = (8, 8, 8, 8), 0.05, 1e-8
     U = links(L, "haar", 41)
