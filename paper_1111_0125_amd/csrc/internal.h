@@ -163,7 +163,7 @@ struct SlotInit {
 void run_init(EngineRun& R, stag_engine* e, hipStream_t s, const void* b, size_t b_rs, int K,
               bool use_graph);
 int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots);
-int run_enqueue_block(EngineRun& R);
+int run_enqueue_block(EngineRun& R, int K = 0);
 int run_process_poll(EngineRun& R, bool blocking, const RhsState** h);
 void fill_stats(const RhsState& s, double secs, int inner_prec, stag_cg_stats* out);
 bool flags_terminal(unsigned f);

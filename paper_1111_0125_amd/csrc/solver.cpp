@@ -668,9 +668,9 @@ int run_start_slots(EngineRun& R, const std::vector<SlotInit>& slots) {
 // The graph of one block of work (K iterations with their fix-ups) for
 // kernel block size nk, built node by node on first use and kept. Every
 // buffer it uses belongs to the engine, so it serves every later block.
-static int get_graph(EngineRun& R, int nk, hipGraphExec_t* out) {
+static int get_graph(EngineRun& R, int nk, int K, hipGraphExec_t* out) {
     stag_engine* e = R.e;
-    const long long key = ((long long)R.K << 16) | ((long long)R.variant << 8) | (long long)nk;
+    const long long key = ((long long)K << 16) | ((long long)R.variant << 8) | (long long)nk;
     auto it = e->graphs.find(key);
     if (it != e->graphs.end()) {
         *out = it->second;
@@ -682,7 +682,7 @@ static int get_graph(EngineRun& R, int nk, hipGraphExec_t* out) {
         Issue is;
         is.gb = &gb;
         Ctx c{e, is, nk, false, R.variant};
-        err = enqueue_block(c, R.K, R.F);
+        err = enqueue_block(c, K, R.F);
     }
     hipGraphExec_t exec = nullptr;
     if (err == hipSuccess) err = hipGraphInstantiate(&exec, gb.graph, nullptr, nullptr, 0);
@@ -697,21 +697,22 @@ static int get_graph(EngineRun& R, int nk, hipGraphExec_t* out) {
     return STAG_OK;
 }
 
-// Enqueue one block (K iterations with fix-ups) for the busy slots, then the
-// poll of the state.
-int run_enqueue_block(EngineRun& R) {
+// Enqueue one block (K iterations with fix-ups, R.K when K is 0) for the
+// busy slots, then the poll of the state.
+int run_enqueue_block(EngineRun& R, int K) {
     stag_engine* e = R.e;
     const int nk = pick_n(R.busy_hi > 0 ? R.busy_hi : 1);
+    const int k = K > 0 ? K : R.K;
     const long long j = R.launched;
     const int buf = (int)(j % 2);
     if (R.use_graph) {
         hipGraphExec_t exec = nullptr;
-        int rc = get_graph(R, nk, &exec);
+        int rc = get_graph(R, nk, k, &exec);
         if (rc) return rc;
         RCK(hipGraphLaunch(exec, R.s));
     } else {
         Ctx c{e, Issue{R.s}, nk, R.timed, R.variant};
-        RCK(enqueue_block(c, R.K, R.F));
+        RCK(enqueue_block(c, k, R.F));
     }
     RCK(hipMemcpyAsync(e->host[buf], e->st, state_bytes(e->N), hipMemcpyDeviceToHost, R.s));
     RCK(hipEventRecord(e->ev[buf], R.s));
@@ -856,6 +857,26 @@ static int engine_solve_finish(stag_engine* e, int n, void* x_out, size_t x_rs,
     return rc;
 }
 
+// Whether every slot, from its iterated residual at two polls, is predicted
+// to meet its tolerance within `budget` more iterations (at the rate between
+// the polls). No estimate (no progress, a reliable update in between, a
+// finished slot) counts as finished only for terminal slots.
+static bool finishes_within(const std::vector<RhsState>& a, const std::vector<RhsState>& b,
+                            int budget) {
+    if (budget <= 0 || a.size() != b.size()) return false;
+    for (size_t r = 0; r < b.size(); ++r) {
+        const RhsState& x = a[r];
+        const RhsState& y = b[r];
+        if (flags_terminal(y.flags)) continue;
+        const int kd = y.iters - x.iters;
+        if (kd <= 0 || !(y.rr > 0.0) || !(x.rr > y.rr) || !(y.rr_stop > 0.0)) return false;
+        if (y.rr <= y.rr_stop) continue;
+        if ((double)kd * std::log(y.rr / y.rr_stop) / std::log(x.rr / y.rr) > (double)budget)
+            return false;
+    }
+    return true;
+}
+
 int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, size_t b_rs,
                  void* x_out, size_t x_rs, const stag_cg_params& p, stag_cg_stats* stats,
                  hipStream_t stream, bool escalating) {
@@ -879,11 +900,18 @@ int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, siz
     }
     int rc = run_start_slots(R, slots);
     if (rc) return rc;
-    const long long max_blocks = (2ll * (p.max_iter > 0 ? p.max_iter : 1000000)) / K + 4096;
-    rc = run_enqueue_block(R);
+    const long long max_blocks = (2ll * (p.max_iter > 0 ? p.max_iter : 1000000)) / R.F + 4096;
+    // Blocks are enqueued one ahead of the poll being waited for, so the block
+    // after the one that converges runs idle. When the last two polls predict
+    // that the block in flight finishes every slot, the next one is short (one
+    // segment; results do not depend on how iterations are grouped in blocks).
+    std::vector<RhsState> older, newer;
+    int k_flight = K;
+    rc = run_enqueue_block(R, K);
     if (rc) return rc;
     for (;;) {
-        rc = run_enqueue_block(R);
+        const int k_next = !older.empty() && finishes_within(older, newer, k_flight - R.F) ? R.F : K;
+        rc = run_enqueue_block(R, k_next);
         if (rc) return rc;
         const RhsState* h = nullptr;
         rc = run_process_poll(R, true, &h);
@@ -896,6 +924,9 @@ int engine_solve(stag_engine* e, int n, const double* mass, const void* b64, siz
             std::copy(h, h + n, fin.begin());
             break;
         }
+        older.swap(newer);
+        newer.assign(h, h + n);
+        k_flight = k_next;
     }
     if (R.variant == MIXED_RELIABLE) {
         // the reliable-update-only ablation never folds y into x: the
