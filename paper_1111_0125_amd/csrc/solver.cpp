@@ -288,8 +288,6 @@ hipError_t vec(const Ctx& c, int prec, int op, std::initializer_list<std::pair<v
     return timed_launch(c, KK_OTHER, [&]() { return launch_finalize(c.nk, a.red, run, c.is); });
 }
 
-constexpr int kKernelsPerIteration = 3;
-
 // Large lattices, and blocks of 8 or more right-hand sides: the direction
 // update d = q(r + beta d) as a pass of its own before stage 1, which then
 // gathers one field per neighbour and right-hand side instead of two (the
