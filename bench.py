@@ -594,6 +594,10 @@ def main():
                     help="only tune and time the block iteration kernels of the 24^3x48 workload "
                          "for 4, 8 and 12 right-hand sides, then a 256 MiB copy kernel: the program "
                          "the block-kernel profiles run")
+    ap.add_argument("--c3-solves-only", action="store_true",
+                    help="only the 32^3x64 Haar solves at m = 0.1 to 1e-8 (fp32 and fp16+scale "
+                         "inner, 12-parameter links), a warm-up and a timed solve each: the program "
+                         "the in-solve kernel trace of the large lattice runs")
     ap.add_argument("--full-links", action="store_true",
                     help="store the gauge copies in full (18 reals per link) instead of 12 parameters")
     args = ap.parse_args()
@@ -627,6 +631,37 @@ def main():
                # then the 1 GiB copy kernel (3 + 20 launches)
                "launch_order": order, "copy_bytes_each_way": 1 << 30,
                "kernel_src_sha256": csrc_digest()}
+        print(json.dumps(out), flush=True)
+        return
+
+    if args.c3_solves_only:
+        torch.cuda.init()
+        name = "c3_32x32x32x64"
+        L = synth.CONFIGS[name]["L"]
+        U, b = c3_inputs(synth)
+        m, tol = 0.1, 1e-8
+        out = {"c3_solves_only": True, "workload": name, "lattice": list(L), "mass": m, "tol": tol,
+               "links": "r12", "solves": {}}
+        with stag.Context(0) as ctx:
+            g = ctx.gauge(L, U, precisions=("f64", "f32", "f16s"), r12=True)
+            out["vh"] = g.vh
+            fb = ctx.field(g, 0, "f64", 1).load(b)
+            fx = ctx.field(g, 0, "f64", 1)
+            tune64 = stag.stag_tune(ctx, g, "f64", 1)[0]
+            for inner in ("f32", "f16s"):
+                tune = stag.stag_tune(ctx, g, inner, 1)[0]
+                p = stag.cg_params(tol=tol, inner=inner)
+                stag.stag_cg_solve(ctx, g, [m], fb, fx, p)  # warm-up: graphs, workspace
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc, st = stag.stag_cg_solve(ctx, g, [m], fb, fx, p)
+                torch.cuda.synchronize()
+                out["solves"][inner] = {"tune": tune, "tune_f64": tune64, "status": rc,
+                                        "ms": round((time.perf_counter() - t0) * 1e3, 3),
+                                        "iters": st[0]["iters"],
+                                        "reliable_updates": st[0]["reliable_updates"],
+                                        "inner_final": st[0]["inner_final"]}
+        out["kernel_src_sha256"] = csrc_digest()
         print(json.dumps(out), flush=True)
         return
 

@@ -70,7 +70,7 @@ enum VecOp : int {
     OP_UPD_MIXED = 3,  // y += a d, rs = q(rs - a Ad), |rs|^2 -> FIN_MIXED
     OP_FOLD = 4,       // x64 += y, y = 0 (f0 = x64, f1 = y)
     OP_XPAY = 5,       // d = q(r + beta d) (f0 = r, f1 = d): the direction update as its
-                       // own pass, for blocks of several right-hand sides
+                       // own pass, on large lattices and for blocks of 8 or more
 };
 
 struct VecArgs {

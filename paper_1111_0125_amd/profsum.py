@@ -404,6 +404,84 @@ def cmd_headline(a):
     print(f"wrote {a.out}")
 
 
+def cmd_solves(a):
+    """Per-kernel durations of the 32^3x64 solves inside the solves themselves
+    (graph replays), against each kernel's compulsory bytes per launch."""
+    costs = _costs()
+    run = json.load(open(a.json))
+    vh = int(run["vh"])
+    r12 = run.get("links") == "r12"
+    names = {0: "f64", 1: "f32", 2: "f16s"}
+    trace = read_trace(a.trace)
+    per = {}
+    for _, name, dur in trace:
+        per.setdefault(name, []).append(dur)
+
+    def role_bytes(name):
+        h = hop_parts(name)
+        if h:
+            prec, n = names[h["prec"]], h["N"]
+            if h["prec"] == 0:
+                return ("fp64 fix-up stage %d (reliable update or check; idle launches exit early)"
+                        % (1 if h["epi"] == 0 else 2)), None
+            if h["epi"] == 0:
+                return f"hop stage 1, {prec} (t = D_oe d)", vh * costs.hop_bytes_per_site(
+                    prec, 1, n, lazy=False, r12=r12)
+            if h["epi"] == 2:
+                return f"hop stage 2, {prec} (Ad = m^2 d - D_eo t, <d, Ad>)", vh * costs.hop_bytes_per_site(
+                    prec, 2, n, lazy=False, r12=r12)
+            return f"hop {prec} epilogue {h['epi']}", None
+        m = VEC.search(name)
+        if m:
+            prec, n, op = names[int(m.group(1))], int(m.group(2)), int(m.group(3))
+            if op == 3:
+                return f"update, {prec} (y += a d, r -= a Ad, |r|^2)", vh * n * costs.update_bytes_per_site(prec, True)
+            if op == 5:
+                return f"direction pass, {prec} (d = r + beta d)", vh * n * 3 * costs.SPINOR_BYTES[prec]
+            return f"vector op {op}, {prec}", None
+        if "k_finalize" in name:
+            return "one-block finalisation of a reduction", None
+        return None, None
+
+    rows = []
+    for name, d in per.items():
+        role, byts = role_bytes(name)
+        if role is None:
+            continue
+        med = statistics.median(d)
+        rows.append((sum(d), name, role, len(d), statistics.mean(d), med, byts))
+    rows.sort(reverse=True)
+    lines = [f"# rocprofv3 kernel trace inside the solves: {run['workload']} Haar links, "
+             f"m = {run['mass']}, {run['tol']}, fp32 and fp16+scale inner iterations", "",
+             "Commands (from the repository root on one MI355X; `<repo>` is that root), the "
+             "unprofiled run first (it writes the launch-shape table the traced run loads, so the "
+             "trace has no autotuner sweep):", ""]
+    lines += ["    " + c for c in a.cmd]
+    sol = run["solves"]
+    lines += ["", "`bench.py --c3-solves-only` builds the lattice with 12-parameter links and runs, per "
+              "inner precision, a warm-up and a timed solve (HIP graph replays): "
+              + "; ".join(f"{k}: {v['iters']} iterations, {v['reliable_updates']} reliable updates, "
+                          f"{v['ms']} ms traced" for k, v in sol.items())
+              + ". On this lattice an iteration is the direction pass, the two hop stages, the "
+              "update and two one-block finalisations; every few iterations come the fp64 "
+              "fix-up launches, idle unless a slot is flagged. The bytes are each kernel's "
+              "compulsory bytes per launch (the links and every vector once); the median "
+              "duration stands for an active launch (a handful of launches per solve run idle "
+              "after a flag or after convergence).", "",
+              "| kernel | role | launches | mean us | median us | compulsory MB | GB/s at the median | frac of 8 TB/s |",
+              "|---|---|---:|---:|---:|---:|---:|---:|"]
+    for tot, name, role, n, mean, med, byts in rows:
+        if byts:
+            gbs = byts / (med * 1e-6) / 1e9
+            lines.append(f"| `{name}` | {role} | {n} | {mean:.2f} | {med:.2f} | {byts / 1e6:.1f} | "
+                         f"{gbs:.1f} | {gbs / 8000:.3f} |")
+        else:
+            lines.append(f"| `{name}` | {role} | {n} | {mean:.2f} | {med:.2f} | | | |")
+    lines.append("")
+    open(a.out, "w").write("\n".join(lines))
+    print(f"wrote {a.out}")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="rocprofv3 summaries for profiles/")
     sub = ap.add_subparsers(dest="what", required=True)
@@ -430,6 +508,11 @@ def main(argv=None):
     p.add_argument("--write", required=True)
     p.add_argument("--cmd", action="append", default=[])
     p.add_argument("--out", required=True)
+    p = sub.add_parser("solves")
+    p.add_argument("--json", required=True)
+    p.add_argument("--trace", required=True)
+    p.add_argument("--cmd", action="append", default=[])
+    p.add_argument("--out", required=True)
     p = sub.add_parser("headline")
     p.add_argument("--bench", required=True)
     p.add_argument("--trace", required=True)
@@ -438,7 +521,8 @@ def main(argv=None):
     p.add_argument("--cmd", action="append", default=[])
     p.add_argument("--out", required=True)
     a = ap.parse_args(argv)
-    {"aapply": cmd_aapply, "iteration": cmd_iteration, "headline": cmd_headline}[a.what](a)
+    {"aapply": cmd_aapply, "iteration": cmd_iteration, "solves": cmd_solves,
+     "headline": cmd_headline}[a.what](a)
 
 
 if __name__ == "__main__":
