@@ -949,7 +949,7 @@ namespace stag {
 
 // Average execution time (microseconds, from events recorded at the start
 // and the end of each kernel) of the three iteration kernels of engine e
-// with tuning t, over `reps` launches each: stage 1 (finalising the
+// with tuning t, over `reps` iterations run in order: stage 1 (finalising the
 // previous |r|^2 where the solver fuses finalisations), stage 2, update
 // (finalising alpha where fused). All of the first
 // nrhs slots are active with alpha = beta = 0, so d = r and every vector
@@ -983,7 +983,7 @@ int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps,
     if (err == hipSuccess && e->y32) err = hipMemsetAsync(e->y32, 0, bytes[2], s);
     if (err == hipSuccess) err = hipMemsetAsync(e->partials, 0, pbytes, s);
     if (err == hipSuccess) err = hipMemsetAsync(e->partials1, 0, pbytes, s);
-    std::vector<Issue> ev((size_t)reps, Issue{s});
+    std::vector<Issue> ev((size_t)(3 * reps), Issue{s});
     for (auto& v : ev) {
         if (err == hipSuccess) err = hipEventCreate(&v.ev_start);
         if (err == hipSuccess) err = hipEventCreate(&v.ev_stop);
@@ -1042,14 +1042,20 @@ int time_iteration_kernels(stag_engine* e, const HopTune& t, int nrhs, int reps,
         if (fuse) a.fin = pend_a;
         return launch_vec(prec, N, mixed ? OP_UPD_MIXED : OP_UPD_CG, a, is);
     };
+    // in iteration order, each kernel reading what the one before it wrote, as
+    // inside a solve (which XCD's L2 holds a vector depends on the block order)
+    for (int i = 0; i < 3 && err == hipSuccess; ++i)  // warm-up
+        for (int which = 0; which < 3 && err == hipSuccess; ++which) err = one(which, Issue{s});
+    for (int i = 0; i < reps && err == hipSuccess; ++i)
+        for (int which = 0; which < 3 && err == hipSuccess; ++which)
+            err = one(which, ev[(size_t)(3 * i + which)]);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
     for (int which = 0; which < 3 && err == hipSuccess; ++which) {
-        for (int i = 0; i < 3 && err == hipSuccess; ++i) err = one(which, Issue{s});  // warm-up
-        for (int i = 0; i < reps && err == hipSuccess; ++i) err = one(which, ev[(size_t)i]);
-        if (err == hipSuccess) err = hipStreamSynchronize(s);
         double tot = 0.0;
         for (int i = 0; i < reps && err == hipSuccess; ++i) {
             float ms = 0.f;
-            err = hipEventElapsedTime(&ms, ev[(size_t)i].ev_start, ev[(size_t)i].ev_stop);
+            const Issue& v = ev[(size_t)(3 * i + which)];
+            err = hipEventElapsedTime(&ms, v.ev_start, v.ev_stop);
             tot += ms;
         }
         us[which] = tot * 1e3 / reps;
