@@ -740,8 +740,8 @@ def main():
                 (("hop_stage1", stag.K_HOP1), ("hop_stage2", stag.K_HOP2), ("update", stag.K_UPDATE))}
     stag.stag_timing_enable(ctx, False)
 
-    # ---- the iteration's kernels, launched exactly as in the solve, timed
-    # back to back between HIP events on the library's stream
+    # ---- the iteration's kernels, launched exactly as in the solve and in its
+    # order, timed between HIP events on the library's stream
     us = stag.stag_time_kernels(ctx, g, inner, 1, reps=200)
     kinds = {}
     for k, name in enumerate(KERNEL_NAMES):

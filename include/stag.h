@@ -391,9 +391,9 @@ int stag_tune_counts(const stag_ctx* ctx, int* loaded, int* measured);
 #define STAG_K_HOP2_64 3  /* fp64 D_eo + residual + norm of a recompute */
 #define STAG_K_UPDATE 4   /* fused x/y and r update with |r|^2 */
 #define STAG_K_XPAY 5     /* the direction update d = r + beta d as its own pass (blocks
-                             of 8 or more right-hand sides, or of several on lattices of
-                             131072 sites per parity or more; otherwise fused into the
-                             hop stages) */
+                             of 8 or more right-hand sides, and every solve on lattices
+                             of 131072 sites per parity or more; otherwise fused into
+                             the hop stages) */
 #define STAG_K_OTHER 6
 int stag_timing_enable(stag_ctx* ctx, int on);
 /* stag_time_kernels: average execution time in microseconds of the three
@@ -403,11 +403,13 @@ int stag_timing_enable(stag_ctx* ctx, int on);
  * direction update and the finalisation of the previous |r|^2), us[1] = D_eo
  * stage with m^2 update and <d, A d>, us[2] = fused update with |r|^2 (and
  * the finalisation of alpha). Blocks of 8 or more right-hand sides, and
- * blocks of several on lattices of 131072 or more sites per parity, run
- * the direction update as a pass of its own (not included): their us[0]
- * and us[1] are the hop stages reading d as stored. Each is the mean over `reps` (1..100000)
- * launches of the time between events recorded at the start and the end of
- * the kernel (hipExtLaunchKernel) on the context's stream. Synchronous. */
+ * every solve on lattices of 131072 or more sites per parity, run the
+ * direction update as a pass of its own (not included): their us[0] and
+ * us[1] are the hop stages reading d as stored. The three run `reps`
+ * (1..100000) times in the solve's order (stage 1, stage 2, update), so each
+ * reads what the one before it wrote; each figure is the mean time between
+ * events recorded at the start and the end of the kernel
+ * (hipExtLaunchKernel) on the context's stream. Synchronous. */
 int stag_time_kernels(stag_ctx* ctx, const stag_gauge* gauge, int prec, int nrhs, int reps,
                       double* us);
 int stag_timing_read(stag_ctx* ctx, int kind, int64_t* count, double* total_ms);
