@@ -603,8 +603,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus}: this build runs one lattice per GPU on a single "
-              "GPU; multi-GPU runs are not supported", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus}: the library solves on one GPU; "
+              "multi-GPU runs are not supported", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np  # noqa: F401

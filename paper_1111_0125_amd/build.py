@@ -1,7 +1,7 @@
 """Build libstag.so in-tree with hipcc for gfx950.
 
 Usage: python paper_1111_0125_amd/build.py [-j JOBS] [-v]
-(run as a script: importing the package needs the library this builds)
+(run as a script: importing the package needs the library this script builds)
 """
 
 from __future__ import annotations

@@ -153,5 +153,5 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
-    assert "single GPU" in r.stderr
+    assert "one GPU" in r.stderr and "not supported" in r.stderr
     assert r.stdout == ""
