@@ -248,8 +248,10 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, stag_tune_
     auto time_cfg = [&](const HopTune& tu, double* us) -> int {
         return time_iteration_kernels(e, tu, nrhs, reps, us);
     };
-    // The default shape is measured first and kept unless another is at
-    // least 5 % faster, so repeated tunings settle on the same shape.
+    // The default shape is measured first and kept unless the fastest other
+    // shape is at least 5 % faster, so repeated tunings settle on the same
+    // shape (the margin is taken against the default, not against the shapes
+    // timed before, which would favour whichever came first).
     constexpr double kGain = 0.95;
     HopTune bestT = get_tune(ctx, prec, N, Vh, g->npairs);
     bestT.S1 = bestT.S2 = g->npairs == 8 ? 2 : 1;
@@ -258,6 +260,8 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, stag_tune_
     double us0[3];
     rc = time_cfg(bestT, us0);
     double best1 = us0[0], best2 = us0[1], best3 = us0[2];
+    HopTune fastT = bestT;
+    double fast[3] = {us0[0], us0[1], us0[2]};
     const int Ss[] = {1, 2, 4};
     // block orders: plain and XCD-aware; blocks of several right-hand sides
     // also the t-grouped orders (their neighbour gathers are what overflows L2)
@@ -275,28 +279,42 @@ int stag_tune(stag_ctx* ctx, const stag_gauge* g, int prec, int nrhs, stag_tune_
                 double us[3];
                 if ((rc = time_cfg(tu, us))) break;
                 // one (nt, swizzle) pair serves all kernels; S is per stage
-                if (us[0] + us[1] + us[2] < kGain * (best1 + best2 + best3)) {
-                    best1 = us[0];
-                    best2 = us[1];
-                    best3 = us[2];
-                    bestT = tu;
+                if (us[0] + us[1] + us[2] < fast[0] + fast[1] + fast[2]) {
+                    for (int k = 0; k < 3; ++k) fast[k] = us[k];
+                    fastT = tu;
                 }
             }
-    // refine S per stage with the chosen (nt, swizzle)
+    if (fast[0] + fast[1] + fast[2] < kGain * (best1 + best2 + best3)) {
+        best1 = fast[0];
+        best2 = fast[1];
+        bestT = fastT;
+    }
+    // refine S per stage with the chosen (nt, swizzle): the fastest S of each
+    // stage, if at least 5 % faster than the chosen shape's
+    int s1 = bestT.S1, s2 = bestT.S2;
+    double f1 = best1, f2 = best2;
     for (int S : Ss) {
         if (rc != STAG_OK) break;
         HopTune tu = bestT;
         tu.S1 = tu.S2 = S;
         double us[3];
         if ((rc = time_cfg(tu, us))) break;
-        if (us[0] < kGain * best1) {
-            best1 = us[0];
-            bestT.S1 = S;
+        if (us[0] < f1) {
+            f1 = us[0];
+            s1 = S;
         }
-        if (us[1] < kGain * best2) {
-            best2 = us[1];
-            bestT.S2 = S;
+        if (us[1] < f2) {
+            f2 = us[1];
+            s2 = S;
         }
+    }
+    if (f1 < kGain * best1) {
+        best1 = f1;
+        bestT.S1 = s1;
+    }
+    if (f2 < kGain * best2) {
+        best2 = f2;
+        bestT.S2 = s2;
     }
     engine_release(e);
     if (rc) return rc;
