@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 METRIC = "time-to-1e-8 solve & solves/s, mixed vs FP64 CG; A-apply HBM GB/s; p99 lat"
 WORKLOAD = "c2_16x16x16x32"
 HBM_PEAK_GBS = 8000.0
+INFINITY_CACHE_MB = 256          # MI355X last-level (MALL) cache
 
 
 def log(*a):
@@ -760,6 +761,14 @@ def main():
                            f"nt={tunes[inner]['nt']} swizzle={tunes[inner]['swizzle']})"),
                 "avg_us": d["avg_us"],
                 "bytes_per_launch": d["bytes_per_launch"]}
+    # what one iteration touches: both parities' links and the inner vectors
+    # (r, d, t, A d in the inner precision, y in fp32); on this lattice it fits
+    # in the 256 MB Infinity Cache, so 8 TB/s is a conservative ceiling here
+    link_b = (costs.LINK_BYTES_R12 if r12 else costs.LINK_BYTES)[inner]
+    ws = vh * (2 * (8 * link_b + costs.SITE_SCALE_BYTES[inner])
+               + 4 * costs.SPINOR_BYTES[inner] + costs.SPINOR_BYTES["f32"])
+    roofline["iteration_working_set_MB"] = round(ws / 1e6, 1)
+    roofline["infinity_cache_MB"] = INFINITY_CACHE_MB
     n_in, ms_in = in_solve[dom]
     in_us = ms_in * 1e3 / max(n_in, 1)
     roofline["in_solve"] = {"launches": n_in, "avg_us": round(in_us, 3),
