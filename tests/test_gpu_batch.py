@@ -80,13 +80,15 @@ def test_block_orders_bitwise_identical(stag, nrhs):
         assert float(np.abs(ref - Ax).max() / np.abs(Ax).max()) <= 1e-6
 
 
-def test_block_solve_bitwise_across_block_orders(stag):
-    """An 8-RHS mixed block solve (direction pass of its own, block hop
-    stages, fp64 fix-ups) gives the same iterations and bits in every block
+@pytest.mark.parametrize("n", [8, 16])
+def test_block_solve_bitwise_across_block_orders(stag, n):
+    """A mixed block solve gives the same iterations and bits in every block
     order, and the bits of a single-RHS solve on this small lattice (whose
     stage 1 forms the direction at every neighbour); each right-hand side
-    meets the oracle's true residual."""
-    L, m, tol, n = (8, 8, 8, 8), 0.05, 1e-9, 8
+    meets the oracle's true residual. 8 RHS run here as two overlapping
+    groups of 4 whose stage 1 forms the direction too, 16 as two groups of 8
+    with a direction pass of their own (block hop stages, fp64 fix-ups)."""
+    L, m, tol = (8, 8, 8, 8), 0.05, 1e-9
     U = synth.haar_links(L, 43)
     b = synth.gaussian_rhs(L, n, 44)
     res = []
@@ -96,7 +98,8 @@ def test_block_solve_bitwise_across_block_orders(stag):
         fx = ctx.field(g, 0, "f64", n)
         for sw in range(5):
             for p in ("f64", "f32"):
-                stag.stag_tune_set(ctx, p, n, g.vh, 1, 1, 1, sw)
+                for k in (4, 8, 16):  # the kernels of the block and of its groups
+                    stag.stag_tune_set(ctx, p, k, g.vh, 1, 1, 1, sw)
             rc, st = stag.stag_cg_solve(ctx, g, [m] * n, fb, fx,
                                         stag.cg_params(tol=tol, inner="f32", small_lattice=False))
             assert rc == 0, st
